@@ -1,0 +1,35 @@
+"""Seeded synthetic inputs for BOS ray tracing: scenes, temperature fields, wall patterns.
+
+This module produces *input data only*: scene geometry (box, camera, wall, projector,
+integrator settings), temperature fields T on voxel centres and wall / projector
+patterns. It holds none of the method's arithmetic (no refractive-index map, no ray
+tracing, no rendering); both the GPU path and the FP64 oracle consume what it makes.
+
+The paper's own inputs (an OpenFOAM RANS field and a wavelet-noise projector
+pattern, Sec. 3.A) are not available; seeded Gaussian hot plumes, a vertical
+stratification and random patterns stand in for them.
+"""
+
+from .scenes import (  # noqa: F401
+    Scene,
+    scene_c1,
+    scene_room,
+    scene_c2,
+    scene_c3,
+    scene_h,
+    scene_c5,
+    scenes_c4,
+    scene_paper_geometry,
+    ROOM_LO,
+    ROOM_HI,
+)
+from .fields import (  # noqa: F401
+    Plume,
+    plumes_c1,
+    plumes_room,
+    temperature_grid,
+    voxel_centres,
+    T_AMBIENT,
+)
+from .patterns import binary_dots, blurred_noise  # noqa: F401
+from .subsets import pixel_subset, strided_tiles  # noqa: F401
