@@ -1,0 +1,215 @@
+/*
+ * rbos.h -- C ABI of the MI355X (gfx950) BOS ray-tracing library librbos.so.
+ *
+ * What it computes (Teh, Ali, Rapp, Mansour, "Indoor Airflow Imaging Using
+ * Physics-Informed Background-Oriented Schlieren Tomography"):
+ *   - Sec. 2.A: the refractive index of air from temperature, eta = 1 + rho0 G T0 / T,
+ *     stored per voxel as eta - 1 (optionally scaled into FP16 / BF16 codes);
+ *   - Sec. 2.B, Eq. (1): camera rays traced through the voxelised field with
+ *     dx/dt = v, dv/dt = eta grad(eta) ("nonlinear ray tracing"), integrated with
+ *     Sharma's three-stage Runge-Kutta-Nystrom scheme on the trilinear interpolant of
+ *     the cell-centred grid (clamped to the edge values outside the voxel centres);
+ *     rays start at the box entry with |v| = eta, move straight outside the box;
+ *   - Sec. 2.C, Eq. (2) with one ray through each pixel centre and the luminance term
+ *     only: the back-wall hit is rendered as the printed texture or the pinhole
+ *     projector's image (bilinear, zero outside);
+ *   - Sec. 2.D: L_BOS = sum_j (I_flow^j - I^j(eta))^2, and its exact gradient with
+ *     respect to eta - 1 at every voxel, back-propagated through the integrator from
+ *     ray-state checkpoints (the gradient the paper obtains by automatic
+ *     differentiation / the adjoint state method, here for the discrete scheme).
+ *
+ * Conventions
+ *   - Units are metres in one world frame. Fields are indexed [nz][ny][nx] (x fastest);
+ *     voxel i on an axis of n voxels over [lo, hi] has its centre at
+ *     lo + (i + 1/2)(hi - lo)/n.
+ *   - Pixel j = row * width + col, row 0 at the top of the image; the camera has a
+ *     horizontal field of view and square pixels.
+ *   - Pointers marked [dev] are device memory owned by the caller. The library never
+ *     allocates, frees or synchronises; every launch goes on the `stream` argument
+ *     (a hipStream_t; NULL is the default stream), so all calls may be captured in a
+ *     hipGraph.
+ *   - Errors: argument validation happens on the host before anything is enqueued and
+ *     returns a negative rbos_status; rbos_last_error() then describes it. A failed
+ *     kernel launch returns RBOS_E_HIP. Faults inside kernels surface at the caller's
+ *     next synchronisation. Per-ray conditions are reported in the status array, never
+ *     through the return code.
+ *   - Thread safety: calls on distinct streams with distinct workspaces may run
+ *     concurrently. Outputs must not alias inputs.
+ */
+#ifndef RBOS_H
+#define RBOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBOS_ABI_VERSION 1
+
+typedef enum {
+  RBOS_OK = 0,
+  RBOS_E_NULL = -1,        /* a required pointer is NULL */
+  RBOS_E_SHAPE = -2,       /* sizes inconsistent or outside the supported range */
+  RBOS_E_RANGE = -3,       /* a value is out of range (non-finite, non-positive, ...) */
+  RBOS_E_DTYPE = -4,       /* unknown storage type */
+  RBOS_E_WORKSPACE = -5,   /* workspace NULL or smaller than rbos_workspace_bytes() */
+  RBOS_E_HIP = -6,         /* a HIP runtime call failed */
+  RBOS_E_UNSUPPORTED = -7  /* valid but unsupported option (e.g. checkpoint stride) */
+} rbos_status;
+
+/* storage type of the field codes q; eta - 1 = enc_offset + q / enc_scale */
+enum { RBOS_F32 = 0, RBOS_F16 = 1, RBOS_BF16 = 2 };
+
+/* back-wall luminance model (Sec. 2.C) */
+enum { RBOS_WALL_PRINTED = 0, RBOS_WALL_PROJECTOR = 1 };
+
+/* per-ray status bits */
+enum {
+  RBOS_RAY_MISSED_BOX = 1,  /* camera ray does not meet the field box: straight, 0 steps */
+  RBOS_RAY_TRUNCATED = 2,   /* max_steps reached inside the box; continues straight */
+  RBOS_RAY_NO_WALL_HIT = 4, /* final direction does not face the wall; rendered as 0 */
+  RBOS_RAY_NONFINITE = 8,   /* state became NaN/Inf (non-finite field values) */
+  RBOS_RAY_OFF_PATTERN = 16 /* wall point maps outside the pattern (set by rbos_render) */
+};
+
+/* Largest voxel count per axis. Positions are carried in grid units with an exact
+   straight-line base that needs |coordinate| < 512. */
+#define RBOS_MAX_DIM 448
+/* Supported checkpoint strides k (steps between stored ray states). */
+#define RBOS_CKPT_STRIDES_DOC "8, 16, 32"
+
+/* One acquisition (host struct). Geometry in metres, world frame. */
+typedef struct rbos_scene {
+  /* field: nx*ny*nz voxels (each in [2, RBOS_MAX_DIM]) on the box [box_lo, box_hi] */
+  int32_t nx, ny, nz;
+  double box_lo[3], box_hi[3];
+  int32_t dtype;                 /* RBOS_F32 / RBOS_F16 / RBOS_BF16 */
+  double enc_scale, enc_offset;  /* eta - 1 = enc_offset + q / enc_scale; enc_scale > 0 */
+  const void* field;             /* [dev] packed field from rbos_field_* (never modified) */
+  /* pinhole camera: position, orthonormal forward/right/up, horizontal FOV (degrees) */
+  double cam_pos[3], cam_fwd[3], cam_right[3], cam_up[3];
+  double cam_fov_x_deg;
+  int32_t width, height;
+  const int32_t* pixel_ids;      /* [dev] optional ray list (pixel ids); NULL: every pixel */
+  int32_t n_rays;                /* length of pixel_ids, or width*height when NULL */
+  /* back wall: a plane through wall_origin with unit normal wall_normal (facing the
+     camera); (wall_u, wall_v) orthonormal in-plane axes defining wall coordinates */
+  double wall_origin[3], wall_normal[3], wall_u[3], wall_v[3];
+  int32_t wall_mode;             /* RBOS_WALL_PRINTED / RBOS_WALL_PROJECTOR */
+  const float* pattern;          /* [dev] [pat_h][pat_w] luminance, row 0 at the top */
+  int32_t pat_w, pat_h;
+  double pat_extent_u, pat_extent_v;  /* printed: texture size on the wall, centred on
+                                          wall_origin */
+  double proj_pos[3], proj_fwd[3], proj_right[3], proj_up[3];  /* projector pinhole */
+  double proj_fov_x_deg;
+  /* integrator: Sharma RK4 step h in the ray parameter t, step cap, checkpoint stride
+     (0 = no checkpoints; needed by rbos_trace_adjoint) */
+  double step;
+  int32_t max_steps;
+  int32_t ckpt_stride;
+} rbos_scene;
+
+/* Per-scene forward outputs, indexed by ray r (pixel_ids[r], or pixel r). */
+typedef struct rbos_trace_out {
+  float* wall_uv;    /* [dev] [n_rays][2] wall coordinates (u, v) of the hit, FP32-rounded */
+  float* wall_duv;   /* [dev] [n_rays][2] (u, v) minus the undeflected camera ray's hit;
+                        nullable */
+  int32_t* n_steps;  /* [dev] [n_rays] Sharma steps taken inside the box */
+  uint8_t* status;   /* [dev] [n_rays] RBOS_RAY_* bits */
+  float* ckpt;       /* [dev] rbos_ckpt_bytes(scene) bytes of ray-state checkpoints,
+                        written when scene.ckpt_stride > 0; opaque layout; must stay
+                        unmodified until rbos_trace_adjoint has run */
+} rbos_trace_out;
+
+/* Per-scene render inputs/outputs. */
+typedef struct rbos_render_io {
+  const float* target;  /* [dev] [n_rays] measured image I_flow; nullable */
+  float* image;         /* [dev] [n_rays] rendered I(eta) */
+  float* dL_duv;        /* [dev] [n_rays][2] dL_BOS/d(u, v); needs target; nullable */
+  float* loss;          /* [dev] one float: L_BOS of this scene; needs target; nullable */
+} rbos_render_io;
+
+/* Per-scene adjoint inputs/outputs. */
+typedef struct rbos_adjoint_io {
+  const float* dL_duv;  /* [dev] [n_rays][2] */
+  double* grad;         /* [dev] [nz][ny][nx] FP64; the gradient w.r.t. eta - 1 is ADDED */
+} rbos_adjoint_io;
+
+/* Launch shape (nullable: library defaults). */
+typedef struct rbos_launch {
+  int32_t tile_w, tile_h;     /* rays per wavefront tile, tile_w * tile_h == 64 */
+  int32_t waves_per_block;    /* 1, 2 or 4 */
+  int32_t persistent;         /* 1: persistent blocks pulling tiles from per-XCD queues */
+  int32_t blocks_per_cu;      /* persistent mode: resident blocks per compute unit (1-16) */
+} rbos_launch;
+
+/* Library and ABI version (RBOS_ABI_VERSION). */
+int rbos_version(void);
+
+/* Description of the last error on the calling thread ("" if none). The pointer stays
+   valid until the thread's next rbos_* call. */
+const char* rbos_last_error(void);
+
+/* --- Sec. 2.A: field storage ------------------------------------------------------- */
+
+/* Bytes of the packed field for nx*ny*nz voxels and a storage type (0 if invalid).
+   Layout: one record per interpolation cell, (nx-1)(ny-1)(nz-1) records in x-fastest
+   order, each holding the cell's 8 corner codes (32 B for FP32, 16 B for FP16/BF16). */
+size_t rbos_field_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype);
+
+/* Encode eta - 1 from temperature: delta = rho0G * (T0 / T) in binary32 (two correctly
+   rounded operations), code q = RN_even((delta - c) * s) with c = (float)enc_offset and
+   s = (float)enc_scale a power of two. T: [dev] [nz][ny][nx] kelvin. field: [dev]
+   rbos_field_bytes() bytes. */
+int rbos_field_from_temperature(int32_t nx, int32_t ny, int32_t nz, const float* T,
+                                double rho0G, double T0, int32_t dtype, double enc_scale,
+                                double enc_offset, void* field, void* stream);
+
+/* Encode a given eta - 1 field: q = RN_even((delta - c) * s) as above.
+   delta: [dev] [nz][ny][nx] FP32. */
+int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, int32_t dtype,
+                      double enc_scale, double enc_offset, void* field, void* stream);
+
+/* --- Sec. 2.B / 2.C / 2.D: tracing, rendering, gradient ----------------------------- */
+
+/* Bytes of the checkpoint buffer of one scene (0 when ckpt_stride == 0). */
+size_t rbos_ckpt_bytes(const rbos_scene* scene);
+
+/* Bytes of device workspace needed by rbos_trace_forward / rbos_render /
+   rbos_trace_adjoint for this set of scenes (scene table, queue counters, loss
+   partials). One workspace may serve all three calls in stream order. */
+size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes);
+
+/* Trace every ray of every scene (Eq. 1 with Sharma steps) to the back wall; one launch
+   for all scenes. scenes, outs: host arrays of n_scenes entries. launch: nullable.
+   Writes outs[s] arrays; with ckpt_stride > 0 also the checkpoints. */
+int rbos_trace_forward(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                       const rbos_launch* launch, void* workspace, size_t ws_bytes, void* stream);
+
+/* Render the traced hits (wall luminance, bilinear) and, with a target, the residual,
+   L_BOS per scene (deterministic FP32 reduction) and dL_BOS/d(u, v). Also sets
+   RBOS_RAY_OFF_PATTERN in outs[s].status. */
+int rbos_render(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                const rbos_render_io* io, void* workspace, size_t ws_bytes, void* stream);
+
+/* Back-propagate dL/d(u, v) per ray through the wall step and every Sharma step
+   (replayed from the forward checkpoints) to dL/d(eta - 1) per voxel, accumulated in
+   FP64 into io[s].grad. Needs the same scenes (ckpt_stride > 0), the forward outputs and
+   the unmodified field. */
+int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                       const rbos_adjoint_io* io, const rbos_launch* launch, void* workspace,
+                       size_t ws_bytes, void* stream);
+
+/* --- binding support --------------------------------------------------------------- */
+
+/* Layout of the public structs for binding checks: which = 0 rbos_scene,
+   1 rbos_trace_out, 2 rbos_render_io, 3 rbos_adjoint_io, 4 rbos_launch. Writes up to
+   max_fields member offsets (declaration order) and returns sizeof, or 0 if unknown. */
+size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBOS_H */

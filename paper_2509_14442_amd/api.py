@@ -1,0 +1,279 @@
+"""Python binding of librbos: marshals torch device tensors into the C ABI.
+
+PyTorch provides device memory and the stream; every step of the path runs in the
+library's HIP kernels. There is no fallback: without librbos.so these functions raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+DTYPES = {"f32": L.RBOS_F32, "f16": L.RBOS_F16, "bf16": L.RBOS_BF16}
+RHO0G = 2.7e-4  # rho0 * G of air at the ambient state used by the synthetic workloads
+T_AMBIENT = 293.0
+
+
+def lib():
+    return L.load()
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+def code_scale(dtype: str, max_abs: float) -> float:
+    """Power-of-two scale s with s * max_abs <= 2^14 (16-bit codes: no overflow and, for
+    FP16, codes well inside the normal range); 1 for FP32."""
+    if dtype == "f32" or max_abs <= 0.0:
+        return 1.0
+    return 2.0 ** math.floor(math.log2(2.0 ** 14 / max_abs))
+
+
+class Field:
+    """A packed eta - 1 field on the GPU (cell records of the corner codes)."""
+
+    def __init__(self, dims: Sequence[int], dtype: str = "f32", scale: float = 1.0, offset: float = 0.0,
+                 device="cuda"):
+        nx, ny, nz = (int(d) for d in dims)
+        self.dims = (nx, ny, nz)
+        self.dtype = dtype
+        self.code = DTYPES[dtype]
+        self.scale = float(scale)
+        self.offset = float(offset)
+        nbytes = lib().rbos_field_bytes(nx, ny, nz, self.code)
+        if nbytes == 0:
+            raise ValueError(f"unsupported field shape {dims} / dtype {dtype}")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    @classmethod
+    def from_temperature(cls, T: torch.Tensor, dtype: str = "f32", scale: Optional[float] = None,
+                         offset: float = 0.0, rho0G: float = RHO0G, T0: float = T_AMBIENT, stream=None):
+        """eta - 1 = rho0G * T0 / T from a [nz][ny][nx] float32 temperature tensor (kelvin)."""
+        T = T.contiguous()
+        if T.dtype != torch.float32 or T.dim() != 3:
+            raise ValueError("T must be a float32 [nz][ny][nx] tensor")
+        nz, ny, nx = T.shape
+        if scale is None:
+            tmin, tmax = (float(x) for x in torch.aminmax(T))
+            bound = max(abs(rho0G * T0 / tmin - offset), abs(rho0G * T0 / tmax - offset))
+            scale = code_scale(dtype, bound)
+        f = cls((nx, ny, nz), dtype, scale, offset, T.device)
+        L.check(lib().rbos_field_from_temperature(nx, ny, nz, _ptr(T), rho0G, T0, f.code, f.scale, f.offset,
+                                                  _ptr(f.buf), _stream(stream)))
+        f._keep = T
+        return f
+
+    @classmethod
+    def from_delta(cls, delta: torch.Tensor, dtype: str = "f32", scale: Optional[float] = None,
+                   offset: float = 0.0, stream=None):
+        """Encode a given eta - 1 field ([nz][ny][nx] float32)."""
+        f = cls(tuple(reversed(delta.shape)), dtype, 1.0 if scale is None else scale, offset, delta.device)
+        if scale is None:
+            f.scale = code_scale(dtype, float((delta - offset).abs().max()))
+        f.encode(delta, stream)
+        return f
+
+    def encode(self, delta: torch.Tensor, stream=None):
+        delta = delta.contiguous()
+        if delta.dtype != torch.float32 or tuple(reversed(delta.shape)) != self.dims:
+            raise ValueError("delta must be float32 with shape [nz][ny][nx] of this field")
+        nx, ny, nz = self.dims
+        L.check(lib().rbos_field_encode(nx, ny, nz, _ptr(delta), self.code, self.scale, self.offset,
+                                        _ptr(self.buf), _stream(stream)))
+        self._keep = delta
+
+
+def _vec(x):
+    return L.D3(*(float(v) for v in x))
+
+
+class Scene:
+    """One acquisition bound to device data. `desc` is any object with the geometry
+    attributes of an rbos_scene (box_lo, cam_pos, wall_origin, step, ...)."""
+
+    def __init__(self, desc, field: Field, pattern: Optional[torch.Tensor] = None,
+                 pixel_ids: Optional[torch.Tensor] = None, ckpt_stride: Optional[int] = None):
+        if tuple(field.dims) != tuple(desc.dims):
+            raise ValueError(f"field dims {field.dims} != scene dims {desc.dims}")
+        s = L.rbos_scene()
+        s.nx, s.ny, s.nz = field.dims
+        s.box_lo, s.box_hi = _vec(desc.box_lo), _vec(desc.box_hi)
+        s.dtype, s.enc_scale, s.enc_offset = field.code, field.scale, field.offset
+        s.field = field.buf.data_ptr()
+        s.cam_pos, s.cam_fwd = _vec(desc.cam_pos), _vec(desc.cam_fwd)
+        s.cam_right, s.cam_up = _vec(desc.cam_right), _vec(desc.cam_up)
+        s.cam_fov_x_deg = desc.fov_x_deg
+        s.width, s.height = desc.width, desc.height
+        if pixel_ids is not None:
+            pixel_ids = pixel_ids.to(device=field.buf.device, dtype=torch.int32).contiguous()
+            s.pixel_ids = pixel_ids.data_ptr() if pixel_ids.numel() else field.buf.data_ptr()
+            s.n_rays = pixel_ids.numel()
+        else:
+            s.pixel_ids = None
+            s.n_rays = desc.width * desc.height
+        s.wall_origin, s.wall_normal = _vec(desc.wall_origin), _vec(desc.wall_normal)
+        s.wall_u, s.wall_v = _vec(desc.wall_u), _vec(desc.wall_v)
+        s.wall_mode = desc.wall_mode
+        if pattern is not None:
+            pattern = pattern.to(device=field.buf.device, dtype=torch.float32).contiguous()
+            if tuple(pattern.shape) != (desc.pat_h, desc.pat_w):
+                raise ValueError("pattern shape must be (pat_h, pat_w)")
+            s.pattern = pattern.data_ptr()
+        s.pat_w, s.pat_h = desc.pat_w, desc.pat_h
+        s.pat_extent_u, s.pat_extent_v = desc.pat_extent_u, desc.pat_extent_v
+        s.proj_pos, s.proj_fwd = _vec(desc.proj_pos), _vec(desc.proj_fwd)
+        s.proj_right, s.proj_up = _vec(desc.proj_right), _vec(desc.proj_up)
+        s.proj_fov_x_deg = desc.proj_fov_x_deg
+        s.step = desc.step
+        s.max_steps = desc.max_steps
+        s.ckpt_stride = desc.ckpt_stride if ckpt_stride is None else int(ckpt_stride)
+        self.struct = s
+        self.desc = desc
+        self.field = field
+        self.pattern = pattern
+        self.pixel_ids = pixel_ids
+        self.n_rays = int(s.n_rays)
+        self.dims = field.dims
+
+    def set_field(self, field: Field):
+        self.field = field
+        self.struct.field = field.buf.data_ptr()
+        self.struct.dtype, self.struct.enc_scale, self.struct.enc_offset = field.code, field.scale, field.offset
+
+
+def make_launch(tile=(8, 8), waves_per_block=4, persistent=False, blocks_per_cu=8) -> L.rbos_launch:
+    l = L.rbos_launch()
+    l.tile_w, l.tile_h = tile
+    l.waves_per_block = waves_per_block
+    l.persistent = 1 if persistent else 0
+    l.blocks_per_cu = blocks_per_cu
+    return l
+
+
+class Tracer:
+    """Output buffers, workspace and the three ABI calls for a batch of scenes."""
+
+    def __init__(self, scenes: List[Scene], launch: Optional[L.rbos_launch] = None, checkpoints: bool = True):
+        self.scenes = scenes
+        self.n = len(scenes)
+        self.launch = launch
+        self._arr = (L.rbos_scene * max(self.n, 1))(*[s.struct for s in scenes])
+        dev = scenes[0].field.buf.device if scenes else torch.device("cuda")
+        ws = lib().rbos_workspace_bytes(self._arr, self.n)
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+        self.uv, self.duv, self.n_steps, self.status, self.ckpt = [], [], [], [], []
+        self._outs = (L.rbos_trace_out * max(self.n, 1))()
+        for i, s in enumerate(scenes):
+            n = s.n_rays
+            self.uv.append(torch.empty((n, 2), dtype=torch.float32, device=dev))
+            self.duv.append(torch.empty((n, 2), dtype=torch.float32, device=dev))
+            self.n_steps.append(torch.empty(n, dtype=torch.int32, device=dev))
+            self.status.append(torch.empty(n, dtype=torch.uint8, device=dev))
+            cb = lib().rbos_ckpt_bytes(C.byref(self._arr[i])) if checkpoints else 0
+            self.ckpt.append(torch.empty(max(cb // 4, 1), dtype=torch.float32, device=dev) if cb else None)
+            o = self._outs[i]
+            o.wall_uv, o.wall_duv = self.uv[i].data_ptr(), self.duv[i].data_ptr()
+            o.n_steps, o.status = self.n_steps[i].data_ptr(), self.status[i].data_ptr()
+            o.ckpt = self.ckpt[i].data_ptr() if self.ckpt[i] is not None else None
+        if not checkpoints:
+            for i in range(self.n):
+                self._arr[i].ckpt_stride = 0
+
+    def refresh(self):
+        """Re-read the scene structs (e.g. after Scene.set_field)."""
+        for i, s in enumerate(self.scenes):
+            stride = self._arr[i].ckpt_stride
+            self._arr[i] = s.struct
+            self._arr[i].ckpt_stride = stride
+
+    def _launch_ptr(self):
+        return C.byref(self.launch) if self.launch is not None else None
+
+    def forward(self, stream=None):
+        L.check(lib().rbos_trace_forward(self._arr, self.n, self._outs, self._launch_ptr(),
+                                         _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
+        return self
+
+    def render(self, targets: Optional[List[Optional[torch.Tensor]]] = None, want_grad: bool = True, stream=None):
+        dev = self.workspace.device
+        io = (L.rbos_render_io * max(self.n, 1))()
+        self.image, self.dL_duv, self.loss = [], [], []
+        self._targets = []
+        for i, s in enumerate(self.scenes):
+            img = torch.empty(s.n_rays, dtype=torch.float32, device=dev)
+            tgt = targets[i] if targets is not None else None
+            if tgt is not None:
+                tgt = tgt.to(device=dev, dtype=torch.float32).contiguous().reshape(-1)
+            g = torch.empty((s.n_rays, 2), dtype=torch.float32, device=dev) if (tgt is not None and want_grad) else None
+            lo = torch.zeros(1, dtype=torch.float32, device=dev) if tgt is not None else None
+            io[i].target, io[i].image = _ptr(tgt), _ptr(img)
+            io[i].dL_duv, io[i].loss = _ptr(g), _ptr(lo)
+            self.image.append(img)
+            self.dL_duv.append(g)
+            self.loss.append(lo)
+            self._targets.append(tgt)
+        L.check(lib().rbos_render(self._arr, self.n, self._outs, io, _ptr(self.workspace),
+                                  self.workspace.numel(), _stream(stream)))
+        return self
+
+    def adjoint(self, grads: Optional[List[torch.Tensor]] = None, dL_duv: Optional[List[torch.Tensor]] = None,
+                zero: bool = True, stream=None) -> List[torch.Tensor]:
+        """dL/d(eta - 1) per scene (float64 [nz][ny][nx]); accumulates into `grads` if given."""
+        dev = self.workspace.device
+        dL = dL_duv if dL_duv is not None else self.dL_duv
+        if grads is None:
+            grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device=dev) for s in self.scenes]
+        elif zero:
+            for g in grads:
+                g.zero_()
+        io = (L.rbos_adjoint_io * max(self.n, 1))()
+        keep = []
+        for i in range(self.n):
+            d = dL[i].to(device=dev, dtype=torch.float32).contiguous()
+            keep.append(d)
+            io[i].dL_duv, io[i].grad = _ptr(d), _ptr(grads[i])
+        L.check(lib().rbos_trace_adjoint(self._arr, self.n, self._outs, io, self._launch_ptr(),
+                                         _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
+        self._keep_adj = keep
+        return grads
+
+
+class BOSLoss(torch.autograd.Function):
+    """L_BOS(eta - 1) for one scene, with the hand-written adjoint as its backward.
+
+    forward(delta [nz][ny][nx] float32, tracer, target [n_rays]) -> scalar loss.
+    The tracer's scene must use an FP32 field whose buffer this function re-encodes."""
+
+    @staticmethod
+    def forward(ctx, delta, tracer: Tracer, target):
+        sc = tracer.scenes[0]
+        sc.field.encode(delta.detach())
+        tracer.forward().render([target])
+        ctx.tracer = tracer
+        ctx.shape = delta.shape
+        return tracer.loss[0].reshape(()).clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        tr = ctx.tracer
+        grads = tr.adjoint()
+        return (grads[0] * g.to(torch.float64)).to(torch.float32), None, None
+
+
+def bos_loss(delta: torch.Tensor, tracer: Tracer, target: torch.Tensor) -> torch.Tensor:
+    return BOSLoss.apply(delta, tracer, target)

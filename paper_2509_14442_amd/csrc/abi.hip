@@ -1,0 +1,530 @@
+// abi.hip -- the C ABI of librbos: host-side validation, device scene tables and the
+// launches of the field, forward, render and adjoint kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rbos.h"
+#include "rbos_device.hpp"
+#include "rbos_launch.hpp"
+
+namespace {
+
+using rbos::df;
+using rbos::SceneDev;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+df to_df(double x) {
+  float hi = (float)x;
+  float lo = (float)(x - (double)hi);
+  return {hi, lo};
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+bool unit3(const double* v) { return finite3(v) && std::fabs(dot3(v, v) - 1.0) < 1e-9; }
+bool orthonormal(const double* a, const double* b, const double* c) {
+  return unit3(a) && unit3(b) && unit3(c) && std::fabs(dot3(a, b)) < 1e-9 && std::fabs(dot3(a, c)) < 1e-9 &&
+         std::fabs(dot3(b, c)) < 1e-9;
+}
+bool pow2(double s) {
+  if (!(s > 0.0) || !std::isfinite(s)) return false;
+  int e;
+  return std::frexp(s, &e) == 0.5;
+}
+
+struct Launch {
+  int tile_w = 8, tile_h = 8, wpb = 4, persistent = 0, blocks_per_cu = 8;
+};
+
+int check_launch(const rbos_launch* L, Launch& out) {
+  if (!L) return RBOS_OK;
+  if (L->tile_w < 1 || L->tile_h < 1 || L->tile_w * L->tile_h != 64 || (L->tile_w & (L->tile_w - 1)))
+    return fail(RBOS_E_RANGE, "launch: tile_w * tile_h must be 64 with tile_w a power of two (got %d x %d)",
+                L->tile_w, L->tile_h);
+  if (L->waves_per_block != 1 && L->waves_per_block != 2 && L->waves_per_block != 4)
+    return fail(RBOS_E_RANGE, "launch: waves_per_block must be 1, 2 or 4 (got %d)", L->waves_per_block);
+  if (L->persistent != 0 && L->persistent != 1) return fail(RBOS_E_RANGE, "launch: persistent must be 0 or 1");
+  if (L->persistent && (L->blocks_per_cu < 1 || L->blocks_per_cu > 16))
+    return fail(RBOS_E_RANGE, "launch: blocks_per_cu must be in [1, 16] (got %d)", L->blocks_per_cu);
+  out.tile_w = L->tile_w;
+  out.tile_h = L->tile_h;
+  out.wpb = L->waves_per_block;
+  out.persistent = L->persistent;
+  out.blocks_per_cu = L->blocks_per_cu;
+  return RBOS_OK;
+}
+
+int check_scene(const rbos_scene* S, int idx, bool need_render) {
+  if (S->nx < 2 || S->ny < 2 || S->nz < 2 || S->nx > RBOS_MAX_DIM || S->ny > RBOS_MAX_DIM || S->nz > RBOS_MAX_DIM)
+    return fail(RBOS_E_SHAPE, "scene %d: voxel counts must be in [2, %d] (got %d x %d x %d)", idx, RBOS_MAX_DIM, S->nx,
+                S->ny, S->nz);
+  if (!finite3(S->box_lo) || !finite3(S->box_hi) || !(S->box_lo[0] < S->box_hi[0]) ||
+      !(S->box_lo[1] < S->box_hi[1]) || !(S->box_lo[2] < S->box_hi[2]))
+    return fail(RBOS_E_RANGE, "scene %d: box must be finite with lo < hi on every axis", idx);
+  if (S->dtype != RBOS_F32 && S->dtype != RBOS_F16 && S->dtype != RBOS_BF16)
+    return fail(RBOS_E_DTYPE, "scene %d: unknown dtype %d", idx, S->dtype);
+  if (!pow2(S->enc_scale)) return fail(RBOS_E_RANGE, "scene %d: enc_scale must be a positive power of two", idx);
+  if (!std::isfinite(S->enc_offset)) return fail(RBOS_E_RANGE, "scene %d: enc_offset must be finite", idx);
+  if (!S->field) return fail(RBOS_E_NULL, "scene %d: field is NULL", idx);
+  if (!finite3(S->cam_pos) || !orthonormal(S->cam_fwd, S->cam_right, S->cam_up))
+    return fail(RBOS_E_RANGE, "scene %d: camera position must be finite and fwd/right/up orthonormal", idx);
+  if (!(S->cam_fov_x_deg > 0.0 && S->cam_fov_x_deg < 179.0))
+    return fail(RBOS_E_RANGE, "scene %d: cam_fov_x_deg must be in (0, 179)", idx);
+  if (S->width < 1 || S->height < 1 || (long long)S->width * S->height > (1LL << 30))
+    return fail(RBOS_E_SHAPE, "scene %d: width and height must be >= 1 with width*height <= 2^30", idx);
+  if (!S->pixel_ids && (long long)S->n_rays != (long long)S->width * S->height)
+    return fail(RBOS_E_SHAPE, "scene %d: n_rays must equal width*height when pixel_ids is NULL", idx);
+  if (S->n_rays < 0) return fail(RBOS_E_SHAPE, "scene %d: n_rays < 0", idx);
+  if (!finite3(S->wall_origin) || !orthonormal(S->wall_normal, S->wall_u, S->wall_v))
+    return fail(RBOS_E_RANGE, "scene %d: wall origin must be finite and normal/u/v orthonormal", idx);
+  if (S->wall_mode != RBOS_WALL_PRINTED && S->wall_mode != RBOS_WALL_PROJECTOR)
+    return fail(RBOS_E_RANGE, "scene %d: unknown wall_mode %d", idx, S->wall_mode);
+  double vmin = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    int n = a == 0 ? S->nx : (a == 1 ? S->ny : S->nz);
+    vmin = std::fmin(vmin, (S->box_hi[a] - S->box_lo[a]) / n);
+  }
+  if (!(S->step > 0.0) || !std::isfinite(S->step) || S->step > 4.0 * vmin)
+    return fail(RBOS_E_RANGE, "scene %d: step must be in (0, 4 * smallest voxel]", idx);
+  if (S->max_steps < 1 || S->max_steps > (1 << 16))
+    return fail(RBOS_E_RANGE, "scene %d: max_steps must be in [1, 65536]", idx);
+  if (S->ckpt_stride != 0 && S->ckpt_stride != 8 && !(S->ckpt_stride % 16 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
+    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 8 or a multiple of 16 up to 256 (got %d)", idx,
+                S->ckpt_stride);
+  if (need_render) {
+    if (!S->pattern) return fail(RBOS_E_NULL, "scene %d: pattern is NULL", idx);
+    if (S->pat_w < 1 || S->pat_h < 1 || S->pat_w > (1 << 15) || S->pat_h > (1 << 15))
+      return fail(RBOS_E_SHAPE, "scene %d: pattern size must be in [1, 32768]", idx);
+    if (S->wall_mode == RBOS_WALL_PRINTED && !(S->pat_extent_u > 0.0 && S->pat_extent_v > 0.0 &&
+                                               std::isfinite(S->pat_extent_u) && std::isfinite(S->pat_extent_v)))
+      return fail(RBOS_E_RANGE, "scene %d: printed pattern extents must be positive", idx);
+    if (S->wall_mode == RBOS_WALL_PROJECTOR &&
+        (!finite3(S->proj_pos) || !orthonormal(S->proj_fwd, S->proj_right, S->proj_up) ||
+         !(S->proj_fov_x_deg > 0.0 && S->proj_fov_x_deg < 179.0)))
+      return fail(RBOS_E_RANGE, "scene %d: projector pose must be orthonormal with fov in (0, 179)", idx);
+  }
+  return RBOS_OK;
+}
+
+long long tiles_of(const rbos_scene* S, const Launch& L, int* tiles_x) {
+  if (S->pixel_ids) {
+    *tiles_x = 0;
+    return ((long long)S->n_rays + 63) / 64;
+  }
+  int tx = (S->width + L.tile_w - 1) / L.tile_w;
+  int ty = (S->height + L.tile_h - 1) / L.tile_h;
+  *tiles_x = tx;
+  return (long long)tx * ty;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t table, queues, partials, total;
+  long long total_tiles;
+  int total_render_blocks;
+};
+
+Layout layout(const rbos_scene* scenes, int n, const Launch& L) {
+  Layout y{};
+  y.table = 0;
+  y.queues = align256(sizeof(SceneDev) * (size_t)n);
+  y.partials = y.queues + 256;
+  long long tiles = 0;
+  long long rblocks = 0;
+  for (int i = 0; i < n; ++i) {
+    int tx;
+    tiles += tiles_of(&scenes[i], L, &tx);
+    rblocks += ((long long)scenes[i].n_rays + 255) / 256;
+  }
+  y.total_tiles = tiles;
+  y.total_render_blocks = (int)rblocks;
+  y.total = align256(y.partials + sizeof(float) * (size_t)(rblocks > 0 ? rblocks : 1));
+  return y;
+}
+
+SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int render_block_begin) {
+  SceneDev d;
+  std::memset(&d, 0, sizeof d);
+  const int n[3] = {S->nx, S->ny, S->nz};
+  const double scale = S->enc_scale;
+  const double dec = 1.0 / scale;
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = n[a];
+    double vox = (S->box_hi[a] - S->box_lo[a]) / n[a];
+    d.km[a] = (float)(dec / (vox * vox));
+    d.vox[a] = (float)vox;
+    d.lo_f[a] = (float)S->box_lo[a];
+    d.hi_bound[a] = (float)n[a] - 0.5f;
+    d.lo[a] = to_df(S->box_lo[a]);
+    d.hi[a] = to_df(S->box_hi[a]);
+    d.inv_vox[a] = to_df(1.0 / vox);
+    d.cam_pos[a] = to_df(S->cam_pos[a]);
+    d.cam_fwd[a] = to_df(S->cam_fwd[a]);
+    d.cam_right[a] = to_df(S->cam_right[a]);
+    d.cam_up[a] = to_df(S->cam_up[a]);
+    d.wall_org[a] = to_df(S->wall_origin[a]);
+    d.wall_n[a] = to_df(S->wall_normal[a]);
+    d.wall_u[a] = to_df(S->wall_u[a]);
+    d.wall_v[a] = to_df(S->wall_v[a]);
+    d.wall_org_f[a] = (float)S->wall_origin[a];
+    d.wall_n_f[a] = (float)S->wall_normal[a];
+    d.wall_u_f[a] = (float)S->wall_u[a];
+    d.wall_v_f[a] = (float)S->wall_v[a];
+    d.proj_pos[a] = to_df(S->proj_pos[a]);
+    d.proj_fwd[a] = to_df(S->proj_fwd[a]);
+    d.proj_right[a] = to_df(S->proj_right[a]);
+    d.proj_up[a] = to_df(S->proj_up[a]);
+  }
+  d.cnx = S->nx - 1;
+  d.cny = S->ny - 1;
+  d.dtype = S->dtype;
+  d.field = S->field;
+  d.dec = (float)dec;
+  d.off = (float)S->enc_offset;
+  d.one_plus_off = (float)(1.0 + (double)(float)S->enc_offset);
+  const double h = S->step;
+  d.h = to_df(h);
+  d.hf = (float)h;
+  d.h_2 = (float)(h / 2.0);
+  d.h_6 = (float)(h / 6.0);
+  d.h2_8 = (float)(h * h / 8.0);
+  d.h2_2 = (float)(h * h / 2.0);
+  d.h2_6 = (float)(h * h / 6.0);
+  d.max_steps = S->max_steps;
+  d.ckpt_k = S->ckpt_stride > 0 ? S->ckpt_stride : 1;
+  d.ckpt_slots = S->ckpt_stride > 0 ? (S->max_steps - 1) / S->ckpt_stride : 0;
+  const double t = std::tan(0.5 * S->cam_fov_x_deg * M_PI / 180.0);
+  d.cam_ax = to_df(t / S->width);
+  d.cam_cx = to_df(t);
+  d.cam_cy = to_df(t * S->height / S->width);
+  d.width = S->width;
+  d.height = S->height;
+  d.pixel_ids = S->pixel_ids;
+  d.n_rays = S->n_rays;
+  int tx;
+  long long nt = tiles_of(S, L, &tx);
+  d.tile_w = L.tile_w;
+  d.tile_h = L.tile_h;
+  d.tiles_x = tx;
+  d.n_tiles = (int)nt;
+  d.tile_begin = tile_begin;
+  d.ckpt_pad = S->n_rays;
+  d.wall_mode = S->wall_mode;
+  d.pattern = S->pattern;
+  d.pat_w = S->pat_w;
+  d.pat_h = S->pat_h;
+  if (S->wall_mode == RBOS_WALL_PRINTED && S->pat_extent_u > 0 && S->pat_extent_v > 0) {
+    d.pat_half_u = to_df(0.5 * S->pat_extent_u);
+    d.pat_half_v = to_df(0.5 * S->pat_extent_v);
+    d.pat_inv_tu = to_df(S->pat_w / S->pat_extent_u);
+    d.pat_inv_tv = to_df(S->pat_h / S->pat_extent_v);
+  }
+  if (S->proj_fov_x_deg > 0 && S->pat_w > 0) {
+    const double tp = std::tan(0.5 * S->proj_fov_x_deg * M_PI / 180.0);
+    d.proj_inv_tx = to_df(1.0 / tp);
+    d.proj_inv_ty = to_df(1.0 / (tp * S->pat_h / S->pat_w));
+  }
+  d.render_block_begin = render_block_begin;
+  d.render_blocks = (int)(((long long)S->n_rays + 255) / 256);
+  return d;
+}
+
+// Common front half of the three tracing entry points.
+struct Prepared {
+  Launch L;
+  Layout Y;
+  std::vector<SceneDev> table;
+};
+
+int prepare(const rbos_scene* scenes, int32_t n_scenes, const rbos_launch* launch, void* workspace, size_t ws_bytes,
+            bool need_render, Prepared& P) {
+  if (!scenes) return fail(RBOS_E_NULL, "scenes is NULL");
+  if (n_scenes < 0) return fail(RBOS_E_SHAPE, "n_scenes < 0");
+  int rc = check_launch(launch, P.L);
+  if (rc) return rc;
+  for (int i = 0; i < n_scenes; ++i) {
+    rc = check_scene(&scenes[i], i, need_render);
+    if (rc) return rc;
+    if (scenes[i].dtype != scenes[0].dtype)
+      return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one call must share the storage dtype", i);
+  }
+  P.Y = layout(scenes, n_scenes, P.L);
+  if (P.Y.total_tiles > (1LL << 30)) return fail(RBOS_E_SHAPE, "too many rays in one call");
+  if (n_scenes > 0) {
+    if (!workspace) return fail(RBOS_E_WORKSPACE, "workspace is NULL");
+    if (ws_bytes < P.Y.total) return fail(RBOS_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, P.Y.total);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+      return fail(RBOS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  }
+  P.table.resize((size_t)n_scenes);
+  int tile = 0, rblk = 0;
+  for (int i = 0; i < n_scenes; ++i) {
+    P.table[i] = make_dev(&scenes[i], P.L, tile, rblk);
+    tile += P.table[i].n_tiles;
+    rblk += P.table[i].render_blocks;
+  }
+  return RBOS_OK;
+}
+
+int persistent_blocks(const Launch& L) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cus = v;
+    if (cus <= 0) cus = 256;
+  }
+  return cus * L.blocks_per_cu;
+}
+
+int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::LaunchPlan& plan) {
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  hipError_t e = rbos::launch_upload(ws + P.Y.table, P.table.data(), sizeof(SceneDev) * P.table.size(), stream);
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "scene table upload failed: %s", hipGetErrorString(e));
+  plan.scenes = reinterpret_cast<const SceneDev*>(ws + P.Y.table);
+  plan.n_scenes = (int)P.table.size();
+  plan.total_tiles = (int)P.Y.total_tiles;
+  plan.wpb = P.L.wpb;
+  plan.dtype = P.table.empty() ? 0 : P.table[0].dtype;
+  plan.persistent = P.L.persistent;
+  plan.persistent_blocks = P.L.persistent ? persistent_blocks(P.L) : 0;
+  plan.queues = reinterpret_cast<unsigned int*>(ws + P.Y.queues);
+  plan.total_render_blocks = P.Y.total_render_blocks;
+  plan.partials = reinterpret_cast<float*>(ws + P.Y.partials);
+  plan.ckpt_k = P.table.empty() ? 0 : P.table[0].ckpt_k;
+  if (P.L.persistent) {
+    e = rbos::launch_fill_u32(plan.queues, 0u, 16, stream);
+    if (e != hipSuccess) return fail(RBOS_E_HIP, "queue reset failed: %s", hipGetErrorString(e));
+  }
+  return RBOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rbos_version(void) { return RBOS_ABI_VERSION; }
+
+const char* rbos_last_error(void) { return g_err.c_str(); }
+
+size_t rbos_field_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype) {
+  if (nx < 2 || ny < 2 || nz < 2 || nx > RBOS_MAX_DIM || ny > RBOS_MAX_DIM || nz > RBOS_MAX_DIM) return 0;
+  size_t rec = dtype == RBOS_F32 ? 32 : (dtype == RBOS_F16 || dtype == RBOS_BF16 ? 16 : 0);
+  return rec * (size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1);
+}
+
+static int field_common(int32_t nx, int32_t ny, int32_t nz, const float* src, int from_t, double rho0G, double T0,
+                        int32_t dtype, double scale, double offset, void* field, void* stream) {
+  g_err.clear();
+  if (nx < 2 || ny < 2 || nz < 2 || nx > RBOS_MAX_DIM || ny > RBOS_MAX_DIM || nz > RBOS_MAX_DIM)
+    return fail(RBOS_E_SHAPE, "voxel counts must be in [2, %d]", RBOS_MAX_DIM);
+  if (dtype != RBOS_F32 && dtype != RBOS_F16 && dtype != RBOS_BF16) return fail(RBOS_E_DTYPE, "unknown dtype %d", dtype);
+  if (!src || !field) return fail(RBOS_E_NULL, "input or field pointer is NULL");
+  if (!pow2(scale)) return fail(RBOS_E_RANGE, "enc_scale must be a positive power of two");
+  if (!std::isfinite(offset)) return fail(RBOS_E_RANGE, "enc_offset must be finite");
+  if (from_t && (!(rho0G > 0.0) || !std::isfinite(rho0G) || !(T0 > 0.0) || !std::isfinite(T0)))
+    return fail(RBOS_E_RANGE, "rho0G and T0 must be positive and finite");
+  hipError_t e = rbos::launch_field_pack(nx, ny, nz, src, from_t, (float)rho0G, (float)T0, dtype, (float)scale,
+                                         (float)offset, field, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "field pack launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+int rbos_field_from_temperature(int32_t nx, int32_t ny, int32_t nz, const float* T, double rho0G, double T0,
+                                int32_t dtype, double enc_scale, double enc_offset, void* field, void* stream) {
+  return field_common(nx, ny, nz, T, 1, rho0G, T0, dtype, enc_scale, enc_offset, field, stream);
+}
+
+int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, int32_t dtype, double enc_scale,
+                      double enc_offset, void* field, void* stream) {
+  return field_common(nx, ny, nz, delta, 0, 0.0, 0.0, dtype, enc_scale, enc_offset, field, stream);
+}
+
+size_t rbos_ckpt_bytes(const rbos_scene* S) {
+  if (!S || S->ckpt_stride <= 0 || S->max_steps < 1 || S->n_rays < 0) return 0;
+  // checkpoint slots for steps k, 2k, ... below max_steps; 6 floats per ray and slot
+  size_t slots = (size_t)((S->max_steps - 1) / S->ckpt_stride);
+  return slots * 6 * (size_t)S->n_rays * sizeof(float);
+}
+
+size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes) {
+  if (!scenes || n_scenes < 0) return 0;
+  Launch L;
+  // tile counts differ with the tile shape only for full images; take the largest
+  size_t best = 0;
+  const int shapes[7][2] = {{1, 64}, {2, 32}, {4, 16}, {8, 8}, {16, 4}, {32, 2}, {64, 1}};
+  for (auto& sh : shapes) {
+    L.tile_w = sh[0];
+    L.tile_h = sh[1];
+    Layout y = layout(scenes, n_scenes, L);
+    if (y.total > best) best = y.total;
+  }
+  return best;
+}
+
+int rbos_trace_forward(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                       const rbos_launch* launch, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Prepared P;
+  int rc = prepare(scenes, n_scenes, launch, workspace, ws_bytes, false, P);
+  if (rc) return rc;
+  if (n_scenes > 0 && !outs) return fail(RBOS_E_NULL, "outs is NULL");
+  for (int i = 0; i < n_scenes; ++i) {
+    const rbos_trace_out& o = outs[i];
+    const bool rays = scenes[i].n_rays > 0;
+    if (rays && (!o.wall_uv || !o.wall_duv || !o.n_steps || !o.status))
+      return fail(RBOS_E_NULL, "scene %d: wall_uv, wall_duv, n_steps and status are required", i);
+    if (rays && scenes[i].ckpt_stride > 0 && !o.ckpt && scenes[i].max_steps > scenes[i].ckpt_stride)
+      return fail(RBOS_E_NULL, "scene %d: ckpt_stride > 0 needs ckpt", i);
+    if (scenes[i].n_rays > 0 && scenes[i].pixel_ids == nullptr && scenes[i].n_rays != scenes[i].width * scenes[i].height)
+      return fail(RBOS_E_SHAPE, "scene %d: n_rays mismatch", i);
+    SceneDev& d = P.table[i];
+    d.uv = o.wall_uv;
+    d.duv = o.wall_duv;
+    d.n_steps = o.n_steps;
+    d.status = o.status;
+    d.ckpt = scenes[i].ckpt_stride > 0 ? o.ckpt : nullptr;
+  }
+  if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
+  rbos::LaunchPlan plan{};
+  hipStream_t stream_h = static_cast<hipStream_t>(stream);
+  rc = finish_launch(P, workspace, stream_h, plan);
+  if (rc) return rc;
+  hipError_t e = rbos::launch_trace_fwd(plan, stream_h);
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "forward launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+int rbos_render(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs, const rbos_render_io* io,
+                void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  Prepared P;
+  int rc = prepare(scenes, n_scenes, nullptr, workspace, ws_bytes, true, P);
+  if (rc) return rc;
+  if (n_scenes > 0 && (!outs || !io)) return fail(RBOS_E_NULL, "outs or io is NULL");
+  for (int i = 0; i < n_scenes; ++i) {
+    const bool rays = scenes[i].n_rays > 0;
+    if (rays && (!outs[i].wall_duv || !outs[i].status))
+      return fail(RBOS_E_NULL, "scene %d: wall_duv and status are required", i);
+    if (rays && !io[i].image) return fail(RBOS_E_NULL, "scene %d: image is required", i);
+    if ((io[i].dL_duv || io[i].loss) && !io[i].target)
+      return fail(RBOS_E_NULL, "scene %d: dL_duv and loss need a target", i);
+    SceneDev& d = P.table[i];
+    d.duv = outs[i].wall_duv;
+    d.status = outs[i].status;
+    d.target = io[i].target;
+    d.image = io[i].image;
+    d.dL_duv = io[i].dL_duv;
+    d.loss = io[i].loss;
+  }
+  if (n_scenes == 0) return RBOS_OK;
+  rbos::LaunchPlan plan{};
+  hipStream_t stream_h = static_cast<hipStream_t>(stream);
+  rc = finish_launch(P, workspace, stream_h, plan);
+  if (rc) return rc;
+  hipError_t e = rbos::launch_render(plan, stream_h);
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "render launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                       const rbos_adjoint_io* io, const rbos_launch* launch, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  g_err.clear();
+  Prepared P;
+  int rc = prepare(scenes, n_scenes, launch, workspace, ws_bytes, false, P);
+  if (rc) return rc;
+  if (n_scenes > 0 && (!outs || !io)) return fail(RBOS_E_NULL, "outs or io is NULL");
+  for (int i = 0; i < n_scenes; ++i) {
+    if (scenes[i].ckpt_stride <= 0) return fail(RBOS_E_UNSUPPORTED, "scene %d: the adjoint needs ckpt_stride > 0", i);
+    if (scenes[i].ckpt_stride != scenes[0].ckpt_stride)
+      return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one adjoint call must share ckpt_stride", i);
+    const bool rays = scenes[i].n_rays > 0;
+    if (rays && ((!outs[i].ckpt && scenes[i].max_steps > scenes[i].ckpt_stride) || !outs[i].n_steps || !outs[i].status))
+      return fail(RBOS_E_NULL, "scene %d: ckpt, n_steps and status are required", i);
+    if (rays && !io[i].dL_duv) return fail(RBOS_E_NULL, "scene %d: dL_duv is required", i);
+    if (!io[i].grad) return fail(RBOS_E_NULL, "scene %d: grad is required", i);
+    SceneDev& d = P.table[i];
+    d.n_steps = outs[i].n_steps;
+    d.status = outs[i].status;
+    d.ckpt = outs[i].ckpt;
+    d.adj_dL_duv = io[i].dL_duv;
+    d.grad = io[i].grad;
+  }
+  if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
+  rbos::LaunchPlan plan{};
+  hipStream_t stream_h = static_cast<hipStream_t>(stream);
+  rc = finish_launch(P, workspace, stream_h, plan);
+  if (rc) return rc;
+  hipError_t e = rbos::launch_trace_adj(plan, stream_h);
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "adjoint launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields) {
+#define OFF(T, f) offsetof(T, f)
+  std::vector<size_t> o;
+  size_t sz = 0;
+  switch (which) {
+    case 0:
+      o = {OFF(rbos_scene, nx), OFF(rbos_scene, ny), OFF(rbos_scene, nz), OFF(rbos_scene, box_lo),
+           OFF(rbos_scene, box_hi), OFF(rbos_scene, dtype), OFF(rbos_scene, enc_scale), OFF(rbos_scene, enc_offset),
+           OFF(rbos_scene, field), OFF(rbos_scene, cam_pos), OFF(rbos_scene, cam_fwd), OFF(rbos_scene, cam_right),
+           OFF(rbos_scene, cam_up), OFF(rbos_scene, cam_fov_x_deg), OFF(rbos_scene, width), OFF(rbos_scene, height),
+           OFF(rbos_scene, pixel_ids), OFF(rbos_scene, n_rays), OFF(rbos_scene, wall_origin),
+           OFF(rbos_scene, wall_normal), OFF(rbos_scene, wall_u), OFF(rbos_scene, wall_v), OFF(rbos_scene, wall_mode),
+           OFF(rbos_scene, pattern), OFF(rbos_scene, pat_w), OFF(rbos_scene, pat_h), OFF(rbos_scene, pat_extent_u),
+           OFF(rbos_scene, pat_extent_v), OFF(rbos_scene, proj_pos), OFF(rbos_scene, proj_fwd),
+           OFF(rbos_scene, proj_right), OFF(rbos_scene, proj_up), OFF(rbos_scene, proj_fov_x_deg),
+           OFF(rbos_scene, step), OFF(rbos_scene, max_steps), OFF(rbos_scene, ckpt_stride)};
+      sz = sizeof(rbos_scene);
+      break;
+    case 1:
+      o = {OFF(rbos_trace_out, wall_uv), OFF(rbos_trace_out, wall_duv), OFF(rbos_trace_out, n_steps),
+           OFF(rbos_trace_out, status), OFF(rbos_trace_out, ckpt)};
+      sz = sizeof(rbos_trace_out);
+      break;
+    case 2:
+      o = {OFF(rbos_render_io, target), OFF(rbos_render_io, image), OFF(rbos_render_io, dL_duv),
+           OFF(rbos_render_io, loss)};
+      sz = sizeof(rbos_render_io);
+      break;
+    case 3:
+      o = {OFF(rbos_adjoint_io, dL_duv), OFF(rbos_adjoint_io, grad)};
+      sz = sizeof(rbos_adjoint_io);
+      break;
+    case 4:
+      o = {OFF(rbos_launch, tile_w), OFF(rbos_launch, tile_h), OFF(rbos_launch, waves_per_block),
+           OFF(rbos_launch, persistent), OFF(rbos_launch, blocks_per_cu)};
+      sz = sizeof(rbos_launch);
+      break;
+    default:
+      return 0;
+  }
+#undef OFF
+  if (offsets)
+    for (int i = 0; i < (int)o.size() && i < max_fields; ++i) offsets[i] = o[i];
+  return sz;
+}
+
+}  // extern "C"

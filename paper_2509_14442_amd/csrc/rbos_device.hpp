@@ -1,0 +1,570 @@
+// rbos_device.hpp -- device-side building blocks shared by the librbos kernels.
+//
+//  * double-float arithmetic (pairs of binary32 values; Knuth two-sum, Dekker fast
+//    two-sum, FMA two-product) for the per-ray geometry that needs ~1e-9 m accuracy:
+//    camera ray, box entry, straight-line base of the ray, wall and projector maps;
+//  * the device scene record built by the host from an rbos_scene;
+//  * the cell-record field layout and the trilinear sampler (value, gradient,
+//    mixed second derivatives) of the cell-centred grid, clamped to the edge values;
+//  * one step of Sharma's Runge-Kutta-Nystrom scheme for Eq. (1) in grid units.
+//
+// Everything here is compiled with -ffp-contract=off: fused multiply-adds appear only
+// where written (fmaf), so the forward kernel and the adjoint's replay of it perform
+// bit-identical arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rbos {
+
+// ------------------------------------------------------------------------------------
+// double-float
+// ------------------------------------------------------------------------------------
+struct df {
+  float hi, lo;
+};
+
+__device__ __forceinline__ df dd_two_sum(float a, float b) {
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+// requires |a| >= |b| (or a == 0)
+__device__ __forceinline__ df dd_fast(float a, float b) {
+  float s = a + b;
+  float e = b - (s - a);
+  return {s, e};
+}
+__device__ __forceinline__ df dd_add(df a, df b) {
+  df s = dd_two_sum(a.hi, b.hi);
+  df t = dd_two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = dd_fast(s.hi, s.lo);
+  s.lo += t.lo;
+  return dd_fast(s.hi, s.lo);
+}
+__device__ __forceinline__ df dd_neg(df a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ df dd_sub(df a, df b) { return dd_add(a, dd_neg(b)); }
+__device__ __forceinline__ df dd_add_f(df a, float b) {
+  df s = dd_two_sum(a.hi, b);
+  s.lo += a.lo;
+  return dd_fast(s.hi, s.lo);
+}
+__device__ __forceinline__ df dd_mul(df a, df b) {
+  float p = a.hi * b.hi;
+  float e = fmaf(a.hi, b.hi, -p);
+  e = fmaf(a.hi, b.lo, e);
+  e = fmaf(a.lo, b.hi, e);
+  return dd_fast(p, e);
+}
+__device__ __forceinline__ df dd_mul_f(df a, float b) {
+  float p = a.hi * b;
+  float e = fmaf(a.hi, b, -p);
+  e = fmaf(a.lo, b, e);
+  return dd_fast(p, e);
+}
+__device__ __forceinline__ df dd_div(df a, df b) {
+  float q1 = a.hi / b.hi;
+  df r = dd_sub(a, dd_mul_f(b, q1));
+  float q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul_f(b, q2));
+  float q3 = r.hi / b.hi;
+  return dd_add_f(dd_fast(q1, q2), q3);
+}
+__device__ __forceinline__ df dd_sqrt(df a) {
+  if (!(a.hi > 0.0f)) return {0.0f, 0.0f};
+  float s = sqrtf(a.hi);
+  float p = s * s;
+  float pe = fmaf(s, s, -p);
+  float e = (((a.hi - p) - pe) + a.lo) / (2.0f * s);
+  return dd_fast(s, e);
+}
+__device__ __forceinline__ bool dd_lt(df a, df b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+__device__ __forceinline__ df dd_dot3(const df* a, const df* b) {
+  return dd_add(dd_add(dd_mul(a[0], b[0]), dd_mul(a[1], b[1])), dd_mul(a[2], b[2]));
+}
+__device__ __forceinline__ float dd_to_f(df a) { return a.hi + a.lo; }
+
+// ------------------------------------------------------------------------------------
+// device scene record (host-built; see abi.hip)
+// ------------------------------------------------------------------------------------
+struct SceneDev {
+  // field
+  int n[3];            // voxels per axis
+  int cnx, cny;        // cells per axis (x, y)
+  int dtype;
+  const void* field;   // cell records
+  float dec;           // 1 / enc_scale
+  float one_plus_off;  // 1 + enc_offset (binary32)
+  float off;           // enc_offset (binary32)
+  float km[3];         // dec / voxel^2: force factor in grid units
+  float vox[3];        // voxel size (m)
+  float lo_f[3];       // box lo (m)
+  float hi_bound[3];   // n - 1/2: box faces in grid units are -1/2 and n - 1/2
+  df lo[3];            // box lo (m)
+  df hi[3];            // box hi (m)
+  df inv_vox[3];       // 1 / voxel size
+  // integrator
+  df h;                // step in t
+  float hf, h_2, h_6, h2_8, h2_2, h2_6;
+  int max_steps, ckpt_k, ckpt_slots;
+  long long ckpt_pad;  // rays per checkpoint component (tiles * 64)
+  // camera
+  df cam_pos[3], cam_fwd[3], cam_right[3], cam_up[3];
+  df cam_ax;           // tan(fov_x / 2) / width
+  df cam_cx;           // tan(fov_x / 2)
+  df cam_cy;           // tan(fov_x / 2) * height / width
+  int width, height;
+  const int* pixel_ids;
+  int n_rays;
+  int tile_w, tile_h, tiles_x, n_tiles, tile_begin;
+  // wall
+  df wall_org[3], wall_n[3], wall_u[3], wall_v[3];
+  float wall_n_f[3], wall_u_f[3], wall_v_f[3], wall_org_f[3];
+  int wall_mode;
+  const float* pattern;
+  int pat_w, pat_h;
+  df pat_half_u, pat_half_v;  // printed: extent / 2
+  df pat_inv_tu, pat_inv_tv;  // printed: texels per metre
+  df proj_pos[3], proj_fwd[3], proj_right[3], proj_up[3];
+  df proj_inv_tx, proj_inv_ty;  // 1 / tan(fov_x/2), 1 / (tan(fov_x/2) * pat_h / pat_w)
+  // forward outputs
+  float* uv;
+  float* duv;
+  int* n_steps;
+  unsigned char* status;
+  float* ckpt;
+  // render io
+  const float* target;
+  float* image;
+  float* dL_duv;
+  float* loss;
+  int render_block_begin, render_blocks;
+  // adjoint io
+  const float* adj_dL_duv;
+  double* grad;
+};
+
+enum : int {
+  RAY_MISSED_BOX = 1,
+  RAY_TRUNCATED = 2,
+  RAY_NO_WALL_HIT = 4,
+  RAY_NONFINITE = 8,
+  RAY_OFF_PATTERN = 16
+};
+
+enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+// ------------------------------------------------------------------------------------
+// work decomposition: XCD-aware block order, tiles of 64 rays
+// ------------------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that each
+// XCD works on a contiguous range of tiles (neighbouring rays share field cells, and
+// each XCD has its own L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  int q = nblocks >> 3, r = nblocks & 7;
+  int x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// scene owning global tile index t (scenes are sorted by tile_begin)
+__device__ __forceinline__ int find_scene(const SceneDev* scenes, int n_scenes, int t) {
+  int lo = 0, hi = n_scenes - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (scenes[mid].tile_begin <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ray index r and pixel of lane `lane` in scene tile `tile`; false if none
+__device__ __forceinline__ bool tile_ray(const SceneDev& S, int tile, int lane, int& r, int& pix) {
+  if (S.pixel_ids) {
+    r = tile * 64 + lane;
+    if (r >= S.n_rays) return false;
+    pix = S.pixel_ids[r];
+    return true;
+  }
+  int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
+  int col = tx * S.tile_w + lane % S.tile_w;
+  int row = ty * S.tile_h + lane / S.tile_w;
+  if (col >= S.width || row >= S.height) return false;
+  r = row * S.width + col;
+  pix = r;
+  return true;
+}
+
+// ------------------------------------------------------------------------------------
+// per-ray geometry (double-float)
+// ------------------------------------------------------------------------------------
+struct Ray {
+  df dir[3];     // unit camera ray direction
+  bool entered;  // meets the field box
+  df U0[3];      // box entry point in grid units, u = (x - lo)/voxel - 1/2
+  bool wall0;    // the undeflected camera ray hits the wall
+  df uv0[2];     // its wall coordinates
+};
+
+__device__ __forceinline__ void camera_ray(const SceneDev& S, int pix, df dir[3]) {
+  int col = pix % S.width, row = pix / S.width;
+  df px = dd_sub(dd_mul_f(S.cam_ax, (float)(2 * col + 1)), S.cam_cx);
+  df py = dd_sub(S.cam_cy, dd_mul_f(S.cam_ax, (float)(2 * row + 1)));
+  for (int a = 0; a < 3; ++a)
+    dir[a] = dd_add(S.cam_fwd[a], dd_add(dd_mul(px, S.cam_right[a]), dd_mul(py, S.cam_up[a])));
+  df len = dd_sqrt(dd_dot3(dir, dir));
+  for (int a = 0; a < 3; ++a) dir[a] = dd_div(dir[a], len);
+}
+
+// slab test against the field box; t_in >= 0
+__device__ __forceinline__ bool box_entry(const SceneDev& S, const df dir[3], df& t_in) {
+  bool have_n = false;
+  df tn = {0.0f, 0.0f}, tf = {0.0f, 0.0f};
+  bool have_f = false;
+  for (int a = 0; a < 3; ++a) {
+    if (dir[a].hi != 0.0f) {
+      df t1 = dd_div(dd_sub(S.lo[a], S.cam_pos[a]), dir[a]);
+      df t2 = dd_div(dd_sub(S.hi[a], S.cam_pos[a]), dir[a]);
+      df tmin = dd_lt(t1, t2) ? t1 : t2, tmax = dd_lt(t1, t2) ? t2 : t1;
+      if (!have_n || dd_lt(tn, tmin)) tn = tmin;
+      if (!have_f || dd_lt(tmax, tf)) tf = tmax;
+      have_n = have_f = true;
+    } else if (dd_lt(S.cam_pos[a], S.lo[a]) || dd_lt(S.hi[a], S.cam_pos[a])) {
+      return false;
+    }
+  }
+  df start = (have_n && tn.hi > 0.0f) ? tn : df{0.0f, 0.0f};
+  if (!have_f) return false;  // degenerate direction
+  if (!dd_lt(start, tf)) return false;
+  t_in = start;
+  return true;
+}
+
+// undeflected wall hit of the camera ray: (u0, v0)
+__device__ __forceinline__ bool wall_hit_straight(const SceneDev& S, const df dir[3], df uv[2]) {
+  df dn = dd_dot3(dir, S.wall_n);
+  if (!(dn.hi < 0.0f)) return false;
+  df w[3];
+  for (int a = 0; a < 3; ++a) w[a] = dd_sub(S.wall_org[a], S.cam_pos[a]);
+  df t = dd_div(dd_dot3(w, S.wall_n), dn);
+  df r[3];
+  for (int a = 0; a < 3; ++a) r[a] = dd_sub(dd_add(S.cam_pos[a], dd_mul(t, dir[a])), S.wall_org[a]);
+  uv[0] = dd_dot3(r, S.wall_u);
+  uv[1] = dd_dot3(r, S.wall_v);
+  return true;
+}
+
+__device__ __forceinline__ void setup_ray(const SceneDev& S, int pix, Ray& R) {
+  camera_ray(S, pix, R.dir);
+  R.wall0 = wall_hit_straight(S, R.dir, R.uv0);
+  df t_in;
+  R.entered = box_entry(S, R.dir, t_in);
+  if (R.entered) {
+    for (int a = 0; a < 3; ++a) {
+      df x = dd_add(S.cam_pos[a], dd_mul(t_in, R.dir[a]));
+      R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), -0.5f);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// field: cell records and the trilinear sampler
+// ------------------------------------------------------------------------------------
+// Record of cell (i, j, k): the 8 corner codes q[a + 2b + 4c] = code(i+a, j+b, k+c).
+// FP32: 8 floats (32 B). FP16/BF16: 8 x 16-bit (16 B), two per 32-bit word.
+template <int DT>
+__device__ __forceinline__ void fetch_cell(const void* __restrict__ field, int cell, float c[8]) {
+  if constexpr (DT == DT_F32) {
+    const float4* p = reinterpret_cast<const float4*>(field) + 2 * (size_t)cell;
+    float4 a = p[0], b = p[1];
+    c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+    c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+  } else {
+    uint4 w = reinterpret_cast<const uint4*>(field)[cell];
+    unsigned int v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (DT == DT_F16) {
+        c[2 * k] = (float)__builtin_bit_cast(_Float16, (unsigned short)(v[k] & 0xffffu));
+        c[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(v[k] >> 16));
+      } else {
+        c[2 * k] = __uint_as_float(v[k] << 16);
+        c[2 * k + 1] = __uint_as_float(v[k] & 0xffff0000u);
+      }
+    }
+  }
+}
+
+// Locate one axis: the point is (bhi + small) grid units, bhi exact. Returns the cell's
+// lower index (clamped to [0, n-2]), the fraction (0 / 1 on a clamped axis) and the
+// gradient mask (0 on a clamped axis).
+__device__ __forceinline__ void locate(float bhi, float small, int n, int& i0, float& f, float& m) {
+  float fl = floorf(bhi);
+  float ff = (bhi - fl) + small;
+  int i = (int)fl;
+  if (ff < 0.0f) {
+    ff += 1.0f;
+    i -= 1;
+  } else if (ff >= 1.0f) {
+    ff -= 1.0f;
+    i += 1;
+  }
+  m = 1.0f;
+  if (i < 0) {
+    i0 = 0; f = 0.0f; m = 0.0f;
+  } else if (i > n - 2) {
+    bool at_last_centre = (i == n - 1) && (ff == 0.0f);
+    i0 = n - 2; f = 1.0f;
+    if (!at_last_centre) m = 0.0f;
+  } else {
+    i0 = i; f = ff;
+  }
+}
+
+struct Cell {
+  int i[3];
+  float f[3], m[3];
+};
+
+__device__ __forceinline__ void locate3(const SceneDev& S, const float bhi[3], const float small[3], Cell& C) {
+  locate(bhi[0], small[0], S.n[0], C.i[0], C.f[0], C.m[0]);
+  locate(bhi[1], small[1], S.n[1], C.i[1], C.f[1], C.m[1]);
+  locate(bhi[2], small[2], S.n[2], C.i[2], C.f[2], C.m[2]);
+}
+
+__device__ __forceinline__ int cell_index(const SceneDev& S, const Cell& C) {
+  return C.i[0] + S.cnx * (C.i[1] + S.cny * C.i[2]);
+}
+
+// Trilinear value q and its grid-unit gradient (unmasked) from the 8 corners.
+__device__ __forceinline__ void trilinear(const float c[8], const float f[3], float& q, float g[3]) {
+  float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
+  float a00 = fmaf(f[0], d00, c[0]), a10 = fmaf(f[0], d10, c[2]);
+  float a01 = fmaf(f[0], d01, c[4]), a11 = fmaf(f[0], d11, c[6]);
+  float e0 = a10 - a00, e1 = a11 - a01;
+  float b0 = fmaf(f[1], e0, a00), b1 = fmaf(f[1], e1, a01);
+  float gx0 = fmaf(f[1], d10 - d00, d00), gx1 = fmaf(f[1], d11 - d01, d01);
+  float dz = b1 - b0;
+  q = fmaf(f[2], dz, b0);
+  g[0] = fmaf(f[2], gx1 - gx0, gx0);
+  g[1] = fmaf(f[2], e1 - e0, e0);
+  g[2] = dz;
+}
+
+// Same, plus the mixed second derivatives H = (q_xy, q_xz, q_yz) (unmasked).
+__device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], float& q, float g[3], float H[3]) {
+  float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
+  float a00 = fmaf(f[0], d00, c[0]), a10 = fmaf(f[0], d10, c[2]);
+  float a01 = fmaf(f[0], d01, c[4]), a11 = fmaf(f[0], d11, c[6]);
+  float e0 = a10 - a00, e1 = a11 - a01;
+  float b0 = fmaf(f[1], e0, a00), b1 = fmaf(f[1], e1, a01);
+  float x0 = d10 - d00, x1 = d11 - d01;
+  float gx0 = fmaf(f[1], x0, d00), gx1 = fmaf(f[1], x1, d01);
+  float dz = b1 - b0;
+  q = fmaf(f[2], dz, b0);
+  g[0] = fmaf(f[2], gx1 - gx0, gx0);
+  g[1] = fmaf(f[2], e1 - e0, e0);
+  g[2] = dz;
+  H[0] = fmaf(f[2], x1 - x0, x0);  // d2q / dx dy
+  H[1] = gx1 - gx0;                // d2q / dx dz
+  H[2] = e1 - e0;                  // d2q / dy dz
+}
+
+// Grid-unit force of Eq. (1) at a located point: K_a = (1 + delta) d(delta)/du_a / voxel_a^2.
+template <int DT>
+__device__ __forceinline__ void force_at(const SceneDev& S, const Cell& C, float K[3]) {
+  float c[8];
+  fetch_cell<DT>(S.field, cell_index(S, C), c);
+  float q, g[3];
+  trilinear(c, C.f, q, g);
+  float eta = fmaf(q, S.dec, S.one_plus_off);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) K[a] = eta * (g[a] * (C.m[a] * S.km[a]));
+}
+
+// ------------------------------------------------------------------------------------
+// ray state in grid units: position = base(t) + d, velocity = V + e, where the base is
+// the straight line through the entry point with the entry velocity V. The base is
+// carried exactly: at half step j it is bh(j) + lo(j) with bh(j) = U0hi + j*g2hi a sum
+// of multiples of 2^-14 (exact in binary32 while |u| < 512) and lo(j) = U0lo + j*g2lo.
+// ------------------------------------------------------------------------------------
+struct RayBase {
+  float U0hi[3], U0lo[3], g2hi[3], g2lo[3];
+  float V[3];  // entry velocity (m per unit t), binary32
+};
+
+__device__ __forceinline__ void split14(df x, float& hi, float& lo) {
+  hi = rintf(x.hi * 16384.0f) * (1.0f / 16384.0f);
+  lo = (x.hi - hi) + x.lo;
+}
+
+// entry velocity v0 = (1 + delta(x0)) dir (Sharma's |v| = eta) and the base increments
+template <int DT>
+__device__ __forceinline__ void make_base(const SceneDev& S, const Ray& R, RayBase& B, Cell& C0) {
+  float bh[3], small[3];
+  for (int a = 0; a < 3; ++a) {
+    split14(R.U0[a], B.U0hi[a], B.U0lo[a]);
+    bh[a] = B.U0hi[a];
+    small[a] = B.U0lo[a];
+  }
+  locate3(S, bh, small, C0);
+  float c[8];
+  fetch_cell<DT>(S.field, cell_index(S, C0), c);
+  float q, g[3];
+  trilinear(c, C0.f, q, g);
+  float delta = fmaf(q, S.dec, S.off);
+  df eta0 = dd_fast(1.0f, delta);
+  for (int a = 0; a < 3; ++a) {
+    df v = dd_mul(eta0, R.dir[a]);
+    B.V[a] = dd_to_f(v);
+    df G2 = dd_mul_f(dd_mul(dd_mul(S.h, v), S.inv_vox[a]), 0.5f);
+    split14(G2, B.g2hi[a], B.g2lo[a]);
+  }
+}
+
+struct State {
+  float bh[3];  // base hi at the start of the step (half step j = 2n)
+  float jf;     // 2n as a float
+  float d[3];   // position deviation (grid units)
+  float e[3];   // velocity deviation (grid units per unit t)
+};
+
+__device__ __forceinline__ void state_at_step(const RayBase& B, int n, State& st) {
+  st.jf = (float)(2 * n);
+  for (int a = 0; a < 3; ++a) st.bh[a] = fmaf(st.jf, B.g2hi[a], B.U0hi[a]);
+}
+
+// small part of the position at half step (jf + dj) with deviation dev
+__device__ __forceinline__ float small_part(const RayBase& B, int a, float jf, float dev) {
+  return fmaf(jf, B.g2lo[a], B.U0lo[a]) + dev;
+}
+
+// One Sharma step of Eq. (1) (grid units):
+//   K1 = D(P1), P1 = x
+//   K2 = D(P2), P2 = x + h/2 v + h^2/8 K1
+//   K3 = D(P3), P3 = x + h v + h^2/2 K2
+//   x <- x + h v + h^2/6 (K1 + 2 K2),  v <- v + h/6 (K1 + 4 K2 + K3)
+// The base absorbs the h V part of every position. On return st holds the new state
+// and `C` the located cell of the new position (the next step's first sample).
+template <int DT>
+__device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B, State& st, Cell& C) {
+  float K1[3], K2[3], K3[3], bh2[3], bh3[3], sm[3];
+  force_at<DT>(S, C, K1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bh2[a] = st.bh[a] + B.g2hi[a];
+    float dev = st.d[a] + fmaf(S.h_2, st.e[a], S.h2_8 * K1[a]);
+    sm[a] = small_part(B, a, st.jf + 1.0f, dev);
+  }
+  locate3(S, bh2, sm, C);
+  force_at<DT>(S, C, K2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bh3[a] = bh2[a] + B.g2hi[a];
+    float dev = st.d[a] + fmaf(S.hf, st.e[a], S.h2_2 * K2[a]);
+    sm[a] = small_part(B, a, st.jf + 2.0f, dev);
+  }
+  locate3(S, bh3, sm, C);
+  force_at<DT>(S, C, K3);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float dn = st.d[a] + fmaf(S.hf, st.e[a], S.h2_6 * fmaf(2.0f, K2[a], K1[a]));
+    float en = st.e[a] + S.h_6 * (fmaf(4.0f, K2[a], K1[a]) + K3[a]);
+    st.d[a] = dn;
+    st.e[a] = en;
+    st.bh[a] = bh3[a];
+  }
+  st.jf += 2.0f;
+  for (int a = 0; a < 3; ++a) sm[a] = small_part(B, a, st.jf, st.d[a]);
+  locate3(S, st.bh, sm, C);
+}
+
+// Position strictly outside the box on some axis (or not a number).
+__device__ __forceinline__ bool outside_box(const SceneDev& S, const RayBase& B, const State& st) {
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float sm = small_part(B, a, st.jf, st.d[a]);
+    float lo_gap = (st.bh[a] + 0.5f) + sm;            // u + 1/2, first term exact
+    float hi_gap = (st.bh[a] - S.hi_bound[a]) + sm;   // u - (n - 1/2), first term exact
+    inside = inside && (lo_gap >= 0.0f) && (hi_gap <= 0.0f);
+  }
+  return !inside;
+}
+
+__device__ __forceinline__ bool state_finite(const State& st) {
+  float s = st.d[0] + st.d[1] + st.d[2] + st.e[0] + st.e[1] + st.e[2];
+  return isfinite(s) && isfinite(st.d[0]) && isfinite(st.d[1]) && isfinite(st.d[2]) && isfinite(st.e[0]) &&
+         isfinite(st.e[1]) && isfinite(st.e[2]);
+}
+
+// Deviation of the wall hit from the undeflected hit, from the last state:
+// x = base + d, v = V + e (metres). With b = V.n, s_b the base point's distance to the
+// wall along V, the hit is x + s v with s = s_b - (d.n + s_b e.n) / (b + e.n), and
+// X - X0 = d + (s - s_b) V + s e. Returns false when v does not face the wall.
+__device__ __forceinline__ bool wall_deflection(const SceneDev& S, const RayBase& B, const State& st, float dX[3],
+                                                float* s_out) {
+  float dm[3], em[3], Rb[3];
+  float b = 0.0f, dn = 0.0f, en = 0.0f, wb = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dm[a] = st.d[a] * S.vox[a];
+    em[a] = st.e[a] * S.vox[a];
+    float u = st.bh[a] + fmaf(st.jf, B.g2lo[a], B.U0lo[a]);
+    Rb[a] = S.lo_f[a] + (u + 0.5f) * S.vox[a];
+    b += B.V[a] * S.wall_n_f[a];
+    dn += dm[a] * S.wall_n_f[a];
+    en += em[a] * S.wall_n_f[a];
+    wb += (S.wall_org_f[a] - Rb[a]) * S.wall_n_f[a];
+  }
+  if (!(b + en < 0.0f)) return false;
+  float sb = wb / b;
+  float ds = -(dn + sb * en) / (b + en);
+  float s = sb + ds;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dX[a] = dm[a] + ds * B.V[a] + s * em[a];
+  if (s_out) *s_out = s;
+  return true;
+}
+
+}  // namespace rbos
+
+namespace rbos {
+
+// ------------------------------------------------------------------------------------
+// wavefront reductions (DPP within rows, row broadcasts across them; all 64 lanes must
+// be active). The result is returned to every lane.
+// ------------------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL, ROW_MASK>(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<0xb1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f<0x4e>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);       // row_half_mirror
+  v += dpp_f<0x140>(v);       // row_mirror
+  v += dpp_f<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// max over lanes of a non-negative int
+__device__ __forceinline__ int wave_max_nonneg(int v) {
+  v = max(v, dpp_i<0xb1>(v));
+  v = max(v, dpp_i<0x4e>(v));
+  v = max(v, dpp_i<0x141>(v));
+  v = max(v, dpp_i<0x140>(v));
+  v = max(v, dpp_i<0x142, 0xa>(v));
+  v = max(v, dpp_i<0x143, 0xc>(v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+}  // namespace rbos

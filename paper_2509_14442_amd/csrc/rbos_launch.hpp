@@ -1,0 +1,33 @@
+// rbos_launch.hpp -- host-side launch descriptors passed from the C ABI to the kernel
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rbos {
+
+struct SceneDev;
+
+struct LaunchPlan {
+  const SceneDev* scenes;   // device scene table
+  int n_scenes;
+  int total_tiles;          // sum of per-scene 64-ray tiles
+  int wpb;                  // wavefronts per block
+  int dtype;                // storage type shared by all scenes of the call
+  int persistent;           // 1: persistent blocks + per-XCD tile queues
+  int persistent_blocks;
+  unsigned int* queues;     // 8 counters (zeroed before the launch)
+  int ckpt_k;               // checkpoint stride shared by all scenes (adjoint)
+  int total_render_blocks;  // render: sum of per-scene blocks
+  float* partials;          // render: per-block partial loss sums
+};
+
+hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream);
+hipError_t launch_render(const LaunchPlan& P, hipStream_t stream);
+hipError_t launch_trace_adj(const LaunchPlan& P, hipStream_t stream);
+hipError_t launch_field_pack(int nx, int ny, int nz, const float* src, int from_temperature, float rho0G, float T0,
+                             int dtype, float scale, float offset, void* field, hipStream_t stream);
+hipError_t launch_fill_u32(unsigned int* p, unsigned int value, int n, hipStream_t stream);
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+}  // namespace rbos

@@ -1,0 +1,148 @@
+// trace_fwd.hip -- forward ray tracing (Sec. 2.B, Eq. 1): one ray per lane, 64-ray
+// tiles per wavefront, every scene of a batch in one launch.
+#include "rbos_device.hpp"
+#include "rbos_launch.hpp"
+
+namespace rbos {
+
+// Trace one ray; writes its outputs. Checkpoints (d, e) before steps k, 2k, ... are
+// stored component-major: ckpt[(slot * 6 + c) * n_rays + r].
+template <int DT>
+__device__ __forceinline__ void trace_one(const SceneDev& S, int tile, int lane, int r, int pix) {
+  Ray R;
+  setup_ray(S, pix, R);
+  int n = 0;
+  unsigned char status = 0;
+  float uvd[2] = {0.0f, 0.0f};
+  bool ok = true;
+  if (!R.entered) {
+    status |= RAY_MISSED_BOX;
+  } else {
+    RayBase B;
+    Cell C;
+    make_base<DT>(S, R, B, C);
+    State st;
+    state_at_step(B, 0, st);
+    for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
+    const int K = S.ckpt_k;
+    float* ck = S.ckpt ? S.ckpt + (size_t)r : nullptr;
+    bool exited = false;
+    while (n < S.max_steps) {
+      if (ck && n > 0 && (n % K) == 0) {
+        size_t base = (size_t)(n / K - 1) * 6 * (size_t)S.ckpt_pad;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          ck[base + (size_t)a * S.ckpt_pad] = st.d[a];
+          ck[base + (size_t)(3 + a) * S.ckpt_pad] = st.e[a];
+        }
+      }
+      sharma_step<DT>(S, B, st, C);
+      ++n;
+      if (!state_finite(st)) {
+        status |= RAY_NONFINITE;
+        exited = true;
+        break;
+      }
+      if (outside_box(S, B, st)) {
+        exited = true;
+        break;
+      }
+    }
+    if (!exited) status |= RAY_TRUNCATED;
+    if (!(status & RAY_NONFINITE)) {
+      float dX[3];
+      if (wall_deflection(S, B, st, dX, nullptr)) {
+        uvd[0] = dX[0] * S.wall_u_f[0] + dX[1] * S.wall_u_f[1] + dX[2] * S.wall_u_f[2];
+        uvd[1] = dX[0] * S.wall_v_f[0] + dX[1] * S.wall_v_f[1] + dX[2] * S.wall_v_f[2];
+      } else {
+        status |= RAY_NO_WALL_HIT;
+        ok = false;
+      }
+    } else {
+      ok = false;
+    }
+  }
+  if (!R.wall0 && !(status & RAY_NONFINITE)) {
+    // the camera ray itself never reaches the wall: treat the hit as missing
+    if (!R.entered) status |= RAY_NO_WALL_HIT;
+    ok = false;
+  }
+  float u, v;
+  if (ok) {
+    u = dd_to_f(dd_add_f(R.uv0[0], uvd[0]));
+    v = dd_to_f(dd_add_f(R.uv0[1], uvd[1]));
+  } else {
+    u = v = __builtin_nanf("");
+    uvd[0] = uvd[1] = __builtin_nanf("");
+  }
+  S.uv[2 * (size_t)r] = u;
+  S.uv[2 * (size_t)r + 1] = v;
+  if (S.duv) {
+    S.duv[2 * (size_t)r] = uvd[0];
+    S.duv[2 * (size_t)r + 1] = uvd[1];
+  }
+  S.n_steps[r] = n;
+  S.status[r] = status;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ scenes, int n_scenes,
+                                                   int total_tiles, int wpb, int nblocks) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
+  if (gtile >= total_tiles) return;
+  const int si = find_scene(scenes, n_scenes, gtile);
+  const SceneDev& S = scenes[si];
+  const int tile = gtile - S.tile_begin;
+  int r, pix;
+  if (!tile_ray(S, tile, lane, r, pix)) return;
+  trace_one<DT>(S, tile, lane, r, pix);
+}
+
+// Persistent form: blocks pull tiles from per-XCD queues (contiguous tile ranges), and
+// steal from the other XCDs' ranges once their own is drained.
+template <int DT>
+__global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
+                                                              int total_tiles, unsigned int* __restrict__ queues) {
+  const int lane = threadIdx.x & 63;
+  const int xcd = blockIdx.x & 7;
+  for (int q = 0; q < 8; ++q) {
+    const int qx = (xcd + q) & 7;
+    const int q_begin = (int)(((long long)total_tiles * qx) >> 3);
+    const int q_end = (int)(((long long)total_tiles * (qx + 1)) >> 3);
+    while (true) {
+      int t = 0;
+      if (lane == 0) t = (int)atomicAdd(&queues[qx], 1u);
+      t = __shfl(t, 0) + q_begin;
+      if (t >= q_end) break;
+      const int si = find_scene(scenes, n_scenes, t);
+      const SceneDev& S = scenes[si];
+      const int tile = t - S.tile_begin;
+      int r, pix;
+      if (tile_ray(S, tile, lane, r, pix)) trace_one<DT>(S, tile, lane, r, pix);
+    }
+  }
+}
+
+hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream) {
+  if (P.total_tiles == 0) return hipSuccess;
+  if (P.persistent) {
+    dim3 grid(P.persistent_blocks), block(64 * P.wpb);
+    switch (P.dtype) {
+      case DT_F32: hipLaunchKernelGGL(k_trace_fwd_persistent<DT_F32>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.queues); break;
+      case DT_F16: hipLaunchKernelGGL(k_trace_fwd_persistent<DT_F16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.queues); break;
+      default: hipLaunchKernelGGL(k_trace_fwd_persistent<DT_BF16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.queues); break;
+    }
+  } else {
+    int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
+    dim3 grid(nblocks), block(64 * P.wpb);
+    switch (P.dtype) {
+      case DT_F32: hipLaunchKernelGGL(k_trace_fwd<DT_F32>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb, nblocks); break;
+      case DT_F16: hipLaunchKernelGGL(k_trace_fwd<DT_F16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb, nblocks); break;
+      default: hipLaunchKernelGGL(k_trace_fwd<DT_BF16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb, nblocks); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rbos

@@ -1,0 +1,160 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every entry
+point that include/rbos.h declares, the binding's struct layouts match the compiled ones,
+and invalid arguments are rejected before anything is enqueued."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2509_14442_amd._lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        import paper_2509_14442_amd.build as b
+
+        b.build()
+    return L.load()
+
+
+def test_exports_match_header(lib):
+    with open(os.path.join(ROOT, "include", "rbos.h")) as f:
+        hdr = f.read()
+    declared = set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(rbos_\w+)\s*\(", hdr, re.M))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.rbos_version() == 1
+
+
+def test_struct_layouts_match(lib):
+    for which, st in enumerate(L.STRUCTS):
+        offs = (C.c_size_t * 64)()
+        size = lib.rbos_struct_layout(which, offs, 64)
+        assert size == C.sizeof(st), st.__name__
+        for i, (name, _) in enumerate(st._fields_):
+            assert offs[i] == getattr(st, name).offset, (st.__name__, name)
+    assert lib.rbos_struct_layout(99, None, 0) == 0
+
+
+def test_field_bytes(lib):
+    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F32) == 32 * 127 ** 3
+    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F16) == 16 * 127 ** 3
+    assert lib.rbos_field_bytes(1, 4, 4, 0) == 0 and lib.rbos_field_bytes(449, 4, 4, 0) == 0
+    assert lib.rbos_field_bytes(4, 4, 4, 7) == 0
+
+
+def _valid_scene():
+    s = L.rbos_scene()
+    s.nx = s.ny = s.nz = 8
+    s.box_lo, s.box_hi = L.D3(0, 0, 0), L.D3(1, 1, 1)
+    s.dtype, s.enc_scale, s.enc_offset = 0, 1.0, 0.0
+    s.field = 0x1000
+    s.cam_pos, s.cam_fwd = L.D3(0.5, -1.5, 0.5), L.D3(0, 1, 0)
+    s.cam_right, s.cam_up = L.D3(1, 0, 0), L.D3(0, 0, 1)
+    s.cam_fov_x_deg = 40.0
+    s.width = s.height = 4
+    s.n_rays = 16
+    s.wall_origin, s.wall_normal = L.D3(0.5, 1.5, 0.5), L.D3(0, -1, 0)
+    s.wall_u, s.wall_v = L.D3(1, 0, 0), L.D3(0, 0, 1)
+    s.wall_mode = 0
+    s.pattern, s.pat_w, s.pat_h = 0x2000, 4, 4
+    s.pat_extent_u = s.pat_extent_v = 1.0
+    s.step, s.max_steps, s.ckpt_stride = 1 / 16, 64, 16
+    return s
+
+
+def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
+    if outs is None:
+        outs = L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0x7000)
+    rc = lib.rbos_trace_forward(C.byref(s), 1, C.byref(outs), C.byref(launch) if launch else None,
+                                C.c_void_p(ws), ws_bytes, None)
+    return rc, lib.rbos_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda s: setattr(s, "nx", 1), -2),
+    (lambda s: setattr(s, "nz", 500), -2),
+    (lambda s: setattr(s, "box_hi", L.D3(0, 1, 1)), -3),
+    (lambda s: setattr(s, "dtype", 5), -4),
+    (lambda s: setattr(s, "enc_scale", 3.0), -3),
+    (lambda s: setattr(s, "field", None), -1),
+    (lambda s: setattr(s, "cam_fwd", L.D3(0, 1, 0.1)), -3),
+    (lambda s: setattr(s, "cam_fov_x_deg", 0.0), -3),
+    (lambda s: setattr(s, "n_rays", 15), -2),
+    (lambda s: setattr(s, "wall_normal", L.D3(0, -2, 0)), -3),
+    (lambda s: setattr(s, "step", -1.0), -3),
+    (lambda s: setattr(s, "step", 1.0), -3),
+    (lambda s: setattr(s, "max_steps", 0), -3),
+    (lambda s: setattr(s, "ckpt_stride", 12), -7),
+])
+def test_forward_validation(lib, mutate, code):
+    s = _valid_scene()
+    mutate(s)
+    rc, msg = _fwd(lib, s)
+    assert rc == code, msg
+    assert msg
+
+
+def test_forward_output_and_workspace_checks(lib):
+    s = _valid_scene()
+    rc, msg = _fwd(lib, s, outs=L.rbos_trace_out(0, 0x4000, 0x5000, 0x6000, 0x7000))
+    assert rc == -1 and "wall_uv" in msg
+    rc, msg = _fwd(lib, s, outs=L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0))
+    assert rc == -1 and "ckpt" in msg
+    rc, msg = _fwd(lib, s, ws=0)
+    assert rc == -5
+    rc, msg = _fwd(lib, s, ws_bytes=16)
+    assert rc == -5
+    rc, msg = _fwd(lib, s, ws=0x100010)
+    assert rc == -5 and "aligned" in msg
+    bad = L.rbos_launch(8, 4, 4, 0, 1)
+    rc, msg = _fwd(lib, s, launch=bad)
+    assert rc == -3
+    bad = L.rbos_launch(8, 8, 3, 0, 1)
+    rc, msg = _fwd(lib, s, launch=bad)
+    assert rc == -3
+
+
+def test_render_and_adjoint_validation(lib):
+    s = _valid_scene()
+    outs = L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0x7000)
+    io = L.rbos_render_io(None, 0x8000, 0x9000, None)
+    rc = lib.rbos_render(C.byref(s), 1, C.byref(outs), C.byref(io), C.c_void_p(0x100000), 1 << 20, None)
+    assert rc == -1 and b"target" in lib.rbos_last_error()
+    s.pattern = None
+    io = L.rbos_render_io(None, 0x8000, None, None)
+    rc = lib.rbos_render(C.byref(s), 1, C.byref(outs), C.byref(io), C.c_void_p(0x100000), 1 << 20, None)
+    assert rc == -1 and b"pattern" in lib.rbos_last_error()
+    s = _valid_scene()
+    s.ckpt_stride = 0
+    aio = L.rbos_adjoint_io(0xa000, 0xb000)
+    rc = lib.rbos_trace_adjoint(C.byref(s), 1, C.byref(outs), C.byref(aio), None, C.c_void_p(0x100000),
+                                1 << 20, None)
+    assert rc == -7
+    s.ckpt_stride = 16
+    aio = L.rbos_adjoint_io(0xa000, None)
+    rc = lib.rbos_trace_adjoint(C.byref(s), 1, C.byref(outs), C.byref(aio), None, C.c_void_p(0x100000),
+                                1 << 20, None)
+    assert rc == -1
+
+
+def test_field_validation_and_sizes(lib):
+    assert lib.rbos_field_from_temperature(1, 4, 4, C.c_void_p(0x10), 2.7e-4, 293.0, 0, 1.0, 0.0,
+                                           C.c_void_p(0x20), None) == -2
+    assert lib.rbos_field_from_temperature(4, 4, 4, None, 2.7e-4, 293.0, 0, 1.0, 0.0, C.c_void_p(0x20), None) == -1
+    assert lib.rbos_field_from_temperature(4, 4, 4, C.c_void_p(0x10), -1.0, 293.0, 0, 1.0, 0.0,
+                                           C.c_void_p(0x20), None) == -3
+    assert lib.rbos_field_encode(4, 4, 4, C.c_void_p(0x10), 3, 1.0, 0.0, C.c_void_p(0x20), None) == -4
+    s = _valid_scene()
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == ((64 - 1) // 16) * 6 * 16 * 4
+    s.ckpt_stride = 0
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == 0
+    assert lib.rbos_workspace_bytes(C.byref(s), 1) >= 256
+    # empty batch is a no-op
+    assert lib.rbos_trace_forward(C.byref(s), 0, None, None, None, 0, None) == 0
