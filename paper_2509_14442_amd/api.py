@@ -73,10 +73,20 @@ class Field:
             bound = max(abs(rho0G * T0 / tmin - offset), abs(rho0G * T0 / tmax - offset))
             scale = code_scale(dtype, bound)
         f = cls((nx, ny, nz), dtype, scale, offset, T.device)
-        L.check(lib().rbos_field_from_temperature(nx, ny, nz, _ptr(T), rho0G, T0, f.code, f.scale, f.offset,
-                                                  _ptr(f.buf), _stream(stream)))
-        f._keep = T
+        f.rho0G, f.T0 = rho0G, T0
+        f.encode_temperature(T, stream)
         return f
+
+    def encode_temperature(self, T: torch.Tensor, stream=None):
+        """Re-encode this field in place from a temperature tensor of the same shape."""
+        T = T.contiguous()
+        nx, ny, nz = self.dims
+        if T.dtype != torch.float32 or tuple(T.shape) != (nz, ny, nx):
+            raise ValueError("T must be a float32 [nz][ny][nx] tensor of this field's shape")
+        L.check(lib().rbos_field_from_temperature(nx, ny, nz, _ptr(T), getattr(self, "rho0G", RHO0G),
+                                                  getattr(self, "T0", T_AMBIENT), self.code, self.scale,
+                                                  self.offset, _ptr(self.buf), _stream(stream)))
+        self._keep = T
 
     @classmethod
     def from_delta(cls, delta: torch.Tensor, dtype: str = "f32", scale: Optional[float] = None,
@@ -210,24 +220,32 @@ class Tracer:
         return self
 
     def render(self, targets: Optional[List[Optional[torch.Tensor]]] = None, want_grad: bool = True, stream=None):
+        """Images (and with targets: L_BOS and dL/d(u, v)). Output buffers are reused
+        across calls with the same targets, so repeated calls allocate nothing."""
         dev = self.workspace.device
-        io = (L.rbos_render_io * max(self.n, 1))()
-        self.image, self.dL_duv, self.loss = [], [], []
-        self._targets = []
-        for i, s in enumerate(self.scenes):
-            img = torch.empty(s.n_rays, dtype=torch.float32, device=dev)
-            tgt = targets[i] if targets is not None else None
-            if tgt is not None:
-                tgt = tgt.to(device=dev, dtype=torch.float32).contiguous().reshape(-1)
-            g = torch.empty((s.n_rays, 2), dtype=torch.float32, device=dev) if (tgt is not None and want_grad) else None
-            lo = torch.zeros(1, dtype=torch.float32, device=dev) if tgt is not None else None
-            io[i].target, io[i].image = _ptr(tgt), _ptr(img)
-            io[i].dL_duv, io[i].loss = _ptr(g), _ptr(lo)
-            self.image.append(img)
-            self.dL_duv.append(g)
-            self.loss.append(lo)
-            self._targets.append(tgt)
-        L.check(lib().rbos_render(self._arr, self.n, self._outs, io, _ptr(self.workspace),
+        key = (tuple(None if t is None else t.data_ptr() for t in targets) if targets is not None else None,
+               want_grad)
+        if getattr(self, "_render_key", None) != key:
+            io = (L.rbos_render_io * max(self.n, 1))()
+            self.image, self.dL_duv, self.loss = [], [], []
+            self._targets = []
+            for i, s in enumerate(self.scenes):
+                img = torch.empty(s.n_rays, dtype=torch.float32, device=dev)
+                tgt = targets[i] if targets is not None else None
+                if tgt is not None:
+                    tgt = tgt.to(device=dev, dtype=torch.float32).contiguous().reshape(-1)
+                g = (torch.empty((s.n_rays, 2), dtype=torch.float32, device=dev)
+                     if (tgt is not None and want_grad) else None)
+                lo = torch.zeros(1, dtype=torch.float32, device=dev) if tgt is not None else None
+                io[i].target, io[i].image = _ptr(tgt), _ptr(img)
+                io[i].dL_duv, io[i].loss = _ptr(g), _ptr(lo)
+                self.image.append(img)
+                self.dL_duv.append(g)
+                self.loss.append(lo)
+                self._targets.append(tgt)
+            self._render_io = io
+            self._render_key = key
+        L.check(lib().rbos_render(self._arr, self.n, self._outs, self._render_io, _ptr(self.workspace),
                                   self.workspace.numel(), _stream(stream)))
         return self
 
