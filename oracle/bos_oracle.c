@@ -150,7 +150,9 @@ static double field_voxel(const or_field* F, int i, int j, int k) {
 }
 
 /* Trilinear interpolation over cell-centred voxels, clamp-to-edge; the gradient and
-   Hessian are those of the interpolant. lock != NULL reuses a recorded cell (and the
+   Hessian are those of the interpolant. Along each axis the interpolation cell of u is
+   [i, i+1) with i = floor(u); u < 0 and u >= n - 1 are outside the centres, where the
+   field is held at the edge values (zero derivative along that axis). lock != NULL reuses a recorded cell (and the
    clamp decisions) instead of locating P. */
 static void sample_grid(const or_field* F, const double* P, const cell_t* lock, sample_t* s) {
   for (int a = 0; a < 3; ++a) {
@@ -165,11 +167,10 @@ static void sample_grid(const or_field* F, const double* P, const cell_t* lock, 
       f = cl ? lock->fcl[a] : u - i0;
     } else if (!(u >= 0.0)) { /* below the first centre, or not a number */
       i0 = 0; f = 0.0; cl = 1;
-    } else if (u > n - 1) {
+    } else if (u >= n - 1) { /* at or beyond the last centre: cells are half-open [i, i+1) */
       i0 = n - 2; f = 1.0; cl = 1;
     } else {
       i0 = (int)floor(u);
-      if (i0 > n - 2) i0 = n - 2;
       f = u - i0; cl = 0;
     }
     s->cell.i0[a] = i0;
