@@ -77,8 +77,6 @@ enum {
 /* Largest voxel count per axis. Positions are carried in grid units with an exact
    straight-line base that needs |coordinate| < 512. */
 #define RBOS_MAX_DIM 448
-/* Supported checkpoint strides k (steps between stored ray states). */
-#define RBOS_CKPT_STRIDES_DOC "8, 16, 32"
 
 /* One acquisition (host struct). Geometry in metres, world frame. */
 typedef struct rbos_scene {
@@ -104,8 +102,9 @@ typedef struct rbos_scene {
                                           wall_origin */
   double proj_pos[3], proj_fwd[3], proj_right[3], proj_up[3];  /* projector pinhole */
   double proj_fov_x_deg;
-  /* integrator: Sharma RK4 step h in the ray parameter t, step cap, checkpoint stride
-     (0 = no checkpoints; needed by rbos_trace_adjoint) */
+  /* integrator: Sharma RK4 step h in the ray parameter t (at most 4 voxels), step cap
+     (1 .. 65536), checkpoint stride k (0 = no checkpoints; else a multiple of 8 up to
+     256; rbos_trace_adjoint needs k > 0) */
   double step;
   int32_t max_steps;
   int32_t ckpt_stride;
@@ -155,8 +154,10 @@ const char* rbos_last_error(void);
 /* --- Sec. 2.A: field storage ------------------------------------------------------- */
 
 /* Bytes of the packed field for nx*ny*nz voxels and a storage type (0 if invalid).
-   Layout: one record per interpolation cell, (nx-1)(ny-1)(nz-1) records in x-fastest
-   order, each holding the cell's 8 corner codes (32 B for FP32, 16 B for FP16/BF16). */
+   Layout: one record per interpolation cell (i, j, k), i in [-1, nx-1] etc., i.e.
+   (nx+1)(ny+1)(nz+1) records in x-fastest order starting at cell (-1, -1, -1); each
+   holds the cell's 8 corner codes (32 B for FP32, 16 B for FP16/BF16), corner indices
+   clamped to the grid (the apron cells repeat the edge voxels). */
 size_t rbos_field_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype);
 
 /* Encode eta - 1 from temperature: delta = rho0G * (T0 / T) in binary32 (two correctly

@@ -107,8 +107,8 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
     return fail(RBOS_E_RANGE, "scene %d: step must be in (0, 4 * smallest voxel]", idx);
   if (S->max_steps < 1 || S->max_steps > (1 << 16))
     return fail(RBOS_E_RANGE, "scene %d: max_steps must be in [1, 65536]", idx);
-  if (S->ckpt_stride != 0 && S->ckpt_stride != 8 && !(S->ckpt_stride % 16 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
-    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 8 or a multiple of 16 up to 256 (got %d)", idx,
+  if (S->ckpt_stride != 0 && !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
+    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0 or a multiple of 8 up to 256 (got %d)", idx,
                 S->ckpt_stride);
   if (need_render) {
     if (!S->pattern) return fail(RBOS_E_NULL, "scene %d: pattern is NULL", idx);
@@ -195,11 +195,16 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
     d.proj_right[a] = to_df(S->proj_right[a]);
     d.proj_up[a] = to_df(S->proj_up[a]);
   }
-  d.cnx = S->nx - 1;
-  d.cny = S->ny - 1;
+  d.P0 = S->nx + 1;
+  d.P01 = (S->nx + 1) * (S->ny + 1);
   d.dtype = S->dtype;
   d.field = S->field;
+  {
+    const size_t rec = S->dtype == RBOS_F32 ? 32 : 16;
+    d.cell0 = static_cast<const unsigned char*>(S->field) + rec * (size_t)(1 + d.P0 + d.P01);
+  }
   d.dec = (float)dec;
+  d.inv_dec = (float)scale;
   d.off = (float)S->enc_offset;
   d.one_plus_off = (float)(1.0 + (double)(float)S->enc_offset);
   const double h = S->step;
@@ -330,7 +335,7 @@ const char* rbos_last_error(void) { return g_err.c_str(); }
 size_t rbos_field_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype) {
   if (nx < 2 || ny < 2 || nz < 2 || nx > RBOS_MAX_DIM || ny > RBOS_MAX_DIM || nz > RBOS_MAX_DIM) return 0;
   size_t rec = dtype == RBOS_F32 ? 32 : (dtype == RBOS_F16 || dtype == RBOS_BF16 ? 16 : 0);
-  return rec * (size_t)(nx - 1) * (size_t)(ny - 1) * (size_t)(nz - 1);
+  return rec * (size_t)(nx + 1) * (size_t)(ny + 1) * (size_t)(nz + 1);
 }
 
 static int field_common(int32_t nx, int32_t ny, int32_t nz, const float* src, int from_t, double rho0G, double T0,
@@ -362,9 +367,10 @@ int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, in
 
 size_t rbos_ckpt_bytes(const rbos_scene* S) {
   if (!S || S->ckpt_stride <= 0 || S->max_steps < 1 || S->n_rays < 0) return 0;
-  // checkpoint slots for steps k, 2k, ... below max_steps; 6 floats per ray and slot
+  // a per-ray header, then checkpoint slots for steps k, 2k, ... below max_steps
+  // (6 floats per ray and slot)
   size_t slots = (size_t)((S->max_steps - 1) / S->ckpt_stride);
-  return slots * 6 * (size_t)S->n_rays * sizeof(float);
+  return (rbos::RAY_HEADER + slots * 6) * (size_t)S->n_rays * sizeof(float);
 }
 
 size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes) {
@@ -394,7 +400,7 @@ int rbos_trace_forward(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
     const bool rays = scenes[i].n_rays > 0;
     if (rays && (!o.wall_uv || !o.wall_duv || !o.n_steps || !o.status))
       return fail(RBOS_E_NULL, "scene %d: wall_uv, wall_duv, n_steps and status are required", i);
-    if (rays && scenes[i].ckpt_stride > 0 && !o.ckpt && scenes[i].max_steps > scenes[i].ckpt_stride)
+    if (rays && scenes[i].ckpt_stride > 0 && !o.ckpt)
       return fail(RBOS_E_NULL, "scene %d: ckpt_stride > 0 needs ckpt", i);
     if (scenes[i].n_rays > 0 && scenes[i].pixel_ids == nullptr && scenes[i].n_rays != scenes[i].width * scenes[i].height)
       return fail(RBOS_E_SHAPE, "scene %d: n_rays mismatch", i);
@@ -460,7 +466,7 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
     if (scenes[i].ckpt_stride != scenes[0].ckpt_stride)
       return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one adjoint call must share ckpt_stride", i);
     const bool rays = scenes[i].n_rays > 0;
-    if (rays && ((!outs[i].ckpt && scenes[i].max_steps > scenes[i].ckpt_stride) || !outs[i].n_steps || !outs[i].status))
+    if (rays && (!outs[i].ckpt || !outs[i].n_steps || !outs[i].status))
       return fail(RBOS_E_NULL, "scene %d: ckpt, n_steps and status are required", i);
     if (rays && !io[i].dL_duv) return fail(RBOS_E_NULL, "scene %d: dL_duv is required", i);
     if (!io[i].grad) return fail(RBOS_E_NULL, "scene %d: grad is required", i);

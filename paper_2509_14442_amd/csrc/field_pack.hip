@@ -14,23 +14,27 @@ __device__ __forceinline__ unsigned int code16(float q, int dtype) {
   return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;  // round to nearest, ties to even
 }
 
-// One thread per cell. delta = rho0G * (T0 / T) (two binary32 roundings) when
-// from_temperature, else the input is delta; code q = RN((delta - c) * s).
+// One thread per record of the padded cell grid: cells (i, j, k) with i in [-1, nx-1]
+// etc.; corner indices are clamped to the grid, so apron records repeat edge voxels.
+// delta = rho0G * (T0 / T) (two binary32 roundings) when from_temperature, else the
+// input is delta; code q = RN((delta - c) * s).
 __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, const float* __restrict__ src,
                                                     int from_temperature, float rho0G, float T0, int dtype,
                                                     float scale, float offset, void* __restrict__ field) {
-  const int cnx = nx - 1, cny = ny - 1, cnz = nz - 1;
-  const long long ncell = (long long)cnx * cny * cnz;
-  for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
-       cell += (long long)gridDim.x * blockDim.x) {
-    int i = (int)(cell % cnx);
-    int j = (int)((cell / cnx) % cny);
-    int k = (int)(cell / ((long long)cnx * cny));
+  const int px = nx + 1, py = ny + 1, pz = nz + 1;
+  const long long nrec = (long long)px * py * pz;
+  for (long long rec = (long long)blockIdx.x * blockDim.x + threadIdx.x; rec < nrec;
+       rec += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(rec % px) - 1;
+    int j = (int)((rec / px) % py) - 1;
+    int k = (int)(rec / ((long long)px * py)) - 1;
     float q[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      int a = c & 1, b = (c >> 1) & 1, z = c >> 2;
-      float v = src[((size_t)(k + z) * ny + (j + b)) * nx + (i + a)];
+      int x = min(max(i + (c & 1), 0), nx - 1);
+      int y = min(max(j + ((c >> 1) & 1), 0), ny - 1);
+      int z = min(max(k + (c >> 2), 0), nz - 1);
+      float v = src[((size_t)z * ny + y) * nx + x];
       if (from_temperature) {
         float ratio = T0 / v;
         v = rho0G * ratio;
@@ -39,7 +43,7 @@ __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, cons
       q[c] = t * scale;
     }
     if (dtype == DT_F32) {
-      float4* p = reinterpret_cast<float4*>(field) + 2 * cell;
+      float4* p = reinterpret_cast<float4*>(field) + 2 * rec;
       p[0] = make_float4(q[0], q[1], q[2], q[3]);
       p[1] = make_float4(q[4], q[5], q[6], q[7]);
     } else {
@@ -48,15 +52,15 @@ __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, cons
       w.y = code16(q[2], dtype) | (code16(q[3], dtype) << 16);
       w.z = code16(q[4], dtype) | (code16(q[5], dtype) << 16);
       w.w = code16(q[6], dtype) | (code16(q[7], dtype) << 16);
-      reinterpret_cast<uint4*>(field)[cell] = w;
+      reinterpret_cast<uint4*>(field)[rec] = w;
     }
   }
 }
 
 hipError_t launch_field_pack(int nx, int ny, int nz, const float* src, int from_temperature, float rho0G, float T0,
                              int dtype, float scale, float offset, void* field, hipStream_t stream) {
-  long long ncell = (long long)(nx - 1) * (ny - 1) * (nz - 1);
-  long long blocks = (ncell + 255) / 256;
+  long long nrec = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  long long blocks = (nrec + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_field_pack, dim3((unsigned)blocks), dim3(256), 0, stream, nx, ny, nz, src, from_temperature,
                      rho0G, T0, dtype, scale, offset, field);

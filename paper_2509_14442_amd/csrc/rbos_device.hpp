@@ -4,8 +4,9 @@
 //    two-sum, FMA two-product) for the per-ray geometry that needs ~1e-9 m accuracy:
 //    camera ray, box entry, straight-line base of the ray, wall and projector maps;
 //  * the device scene record built by the host from an rbos_scene;
-//  * the cell-record field layout and the trilinear sampler (value, gradient,
-//    mixed second derivatives) of the cell-centred grid, clamped to the edge values;
+//  * the cell-record field layout (with a one-voxel apron that repeats the edge voxels,
+//    so clamp-to-edge needs no per-axis branching) and the trilinear sampler (value,
+//    gradient, mixed second derivatives) of the cell-centred grid;
 //  * one step of Sharma's Runge-Kutta-Nystrom scheme for Eq. (1) in grid units.
 //
 // Everything here is compiled with -ffp-contract=off: fused multiply-adds appear only
@@ -93,10 +94,12 @@ __device__ __forceinline__ float dd_to_f(df a) { return a.hi + a.lo; }
 struct SceneDev {
   // field
   int n[3];            // voxels per axis
-  int cnx, cny;        // cells per axis (x, y)
+  int P0, P01;         // record strides of the padded cell grid: (nx+1), (nx+1)(ny+1)
   int dtype;
   const void* field;   // cell records
+  const void* cell0;   // record of cell (0, 0, 0); cells -1 .. n-1 exist on every axis
   float dec;           // 1 / enc_scale
+  float inv_dec;       // enc_scale
   float one_plus_off;  // 1 + enc_offset (binary32)
   float off;           // enc_offset (binary32)
   float km[3];         // dec / voxel^2: force factor in grid units
@@ -272,17 +275,19 @@ __device__ __forceinline__ void setup_ray(const SceneDev& S, int pix, Ray& R) {
 // ------------------------------------------------------------------------------------
 // field: cell records and the trilinear sampler
 // ------------------------------------------------------------------------------------
-// Record of cell (i, j, k): the 8 corner codes q[a + 2b + 4c] = code(i+a, j+b, k+c).
+// Record of cell (i, j, k), i in [-1, n-1] per axis: the 8 corner codes
+// q[a + 2b + 4c] = code(clamp(i+a), clamp(j+b), clamp(k+c)), indices clamped to the grid.
 // FP32: 8 floats (32 B). FP16/BF16: 8 x 16-bit (16 B), two per 32-bit word.
+// `cell` is relative to the record of cell (0, 0, 0) and may be negative.
 template <int DT>
-__device__ __forceinline__ void fetch_cell(const void* __restrict__ field, int cell, float c[8]) {
+__device__ __forceinline__ void fetch_cell(const void* __restrict__ cell0, int cell, float c[8]) {
   if constexpr (DT == DT_F32) {
-    const float4* p = reinterpret_cast<const float4*>(field) + 2 * (size_t)cell;
+    const float4* p = reinterpret_cast<const float4*>(cell0) + 2 * (ptrdiff_t)cell;
     float4 a = p[0], b = p[1];
     c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
     c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
   } else {
-    uint4 w = reinterpret_cast<const uint4*>(field)[cell];
+    uint4 w = reinterpret_cast<const uint4*>(cell0)[(ptrdiff_t)cell];
     unsigned int v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -297,48 +302,36 @@ __device__ __forceinline__ void fetch_cell(const void* __restrict__ field, int c
   }
 }
 
-// Locate one axis: the point is (bhi + small) grid units, bhi exact. Returns the cell's
-// lower index (clamped to [0, n-2]), the fraction (0 / 1 on a clamped axis) and the
-// gradient mask (0 on a clamped axis).
-__device__ __forceinline__ void locate(float bhi, float small, int n, int& i0, float& f, float& m) {
+// Locate one axis: the point is (bhi + small) grid units with bhi exact. The cell is
+// i = floor(u) and f = u - i, computed without rounding u itself: bhi - floor(bhi) is
+// exact, so f carries one rounding (~3e-8 voxel). The index is clamped to [-1, n-1]:
+// apron cells repeat the edge voxels, so there the field is constant along the axis
+// (edge value, zero derivative) for any f -- clamp-to-edge with half-open cells.
+__device__ __forceinline__ void locate(float bhi, float small, int n, int& i, float& f) {
   float fl = floorf(bhi);
   float ff = (bhi - fl) + small;
-  int i = (int)fl;
-  if (ff < 0.0f) {
-    ff += 1.0f;
-    i -= 1;
-  } else if (ff >= 1.0f) {
-    ff -= 1.0f;
-    i += 1;
-  }
-  m = 1.0f;
-  if (i < 0) {
-    i0 = 0; f = 0.0f; m = 0.0f;
-  } else if (i > n - 2) {
-    bool at_last_centre = (i == n - 1) && (ff == 0.0f);
-    i0 = n - 2; f = 1.0f;
-    if (!at_last_centre) m = 0.0f;
-  } else {
-    i0 = i; f = ff;
-  }
+  float t = floorf(ff);
+  f = ff - t;
+  int ii = (int)(fl + t);
+  i = min(max(ii, -1), n - 1);
 }
 
 struct Cell {
   int i[3];
-  float f[3], m[3];
+  float f[3];
 };
 
 __device__ __forceinline__ void locate3(const SceneDev& S, const float bhi[3], const float small[3], Cell& C) {
-  locate(bhi[0], small[0], S.n[0], C.i[0], C.f[0], C.m[0]);
-  locate(bhi[1], small[1], S.n[1], C.i[1], C.f[1], C.m[1]);
-  locate(bhi[2], small[2], S.n[2], C.i[2], C.f[2], C.m[2]);
+  locate(bhi[0], small[0], S.n[0], C.i[0], C.f[0]);
+  locate(bhi[1], small[1], S.n[1], C.i[1], C.f[1]);
+  locate(bhi[2], small[2], S.n[2], C.i[2], C.f[2]);
 }
 
 __device__ __forceinline__ int cell_index(const SceneDev& S, const Cell& C) {
-  return C.i[0] + S.cnx * (C.i[1] + S.cny * C.i[2]);
+  return C.i[0] + S.P0 * C.i[1] + S.P01 * C.i[2];
 }
 
-// Trilinear value q and its grid-unit gradient (unmasked) from the 8 corners.
+// Trilinear value q and its grid-unit gradient from the 8 corners.
 __device__ __forceinline__ void trilinear(const float c[8], const float f[3], float& q, float g[3]) {
   float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
   float a00 = fmaf(f[0], d00, c[0]), a10 = fmaf(f[0], d10, c[2]);
@@ -353,7 +346,7 @@ __device__ __forceinline__ void trilinear(const float c[8], const float f[3], fl
   g[2] = dz;
 }
 
-// Same, plus the mixed second derivatives H = (q_xy, q_xz, q_yz) (unmasked).
+// Same, plus the mixed second derivatives H = (q_xy, q_xz, q_yz).
 __device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], float& q, float g[3], float H[3]) {
   float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
   float a00 = fmaf(f[0], d00, c[0]), a10 = fmaf(f[0], d10, c[2]);
@@ -376,12 +369,12 @@ __device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], 
 template <int DT>
 __device__ __forceinline__ void force_at(const SceneDev& S, const Cell& C, float K[3]) {
   float c[8];
-  fetch_cell<DT>(S.field, cell_index(S, C), c);
+  fetch_cell<DT>(S.cell0, cell_index(S, C), c);
   float q, g[3];
   trilinear(c, C.f, q, g);
   float eta = fmaf(q, S.dec, S.one_plus_off);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) K[a] = eta * (g[a] * (C.m[a] * S.km[a]));
+  for (int a = 0; a < 3; ++a) K[a] = eta * (g[a] * S.km[a]);
 }
 
 // ------------------------------------------------------------------------------------
@@ -411,7 +404,7 @@ __device__ __forceinline__ void make_base(const SceneDev& S, const Ray& R, RayBa
   }
   locate3(S, bh, small, C0);
   float c[8];
-  fetch_cell<DT>(S.field, cell_index(S, C0), c);
+  fetch_cell<DT>(S.cell0, cell_index(S, C0), c);
   float q, g[3];
   trilinear(c, C0.f, q, g);
   float delta = fmaf(q, S.dec, S.off);
@@ -565,6 +558,49 @@ __device__ __forceinline__ int wave_max_nonneg(int v) {
   v = max(v, dpp_i<0x142, 0xa>(v));
   v = max(v, dpp_i<0x143, 0xc>(v));
   return __builtin_amdgcn_readlane(v, 63);
+}
+
+}  // namespace rbos
+
+namespace rbos {
+
+// ------------------------------------------------------------------------------------
+// per-ray header stored with the checkpoints (component-major, n_rays per component):
+// the straight-line base (U0hi, U0lo, g2hi, g2lo), the entry velocity V, the final
+// velocity deviation e and the wall distance parameter s of the last state. The adjoint
+// reads it instead of redoing the double-float ray setup.
+// ------------------------------------------------------------------------------------
+constexpr int RAY_HEADER = 19;
+
+__device__ __forceinline__ void store_ray_header(const SceneDev& S, int r, const RayBase& B, const State& st,
+                                                 float s) {
+  float* p = S.ckpt + (size_t)r;
+  const size_t P = (size_t)S.ckpt_pad;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    p[(0 + a) * P] = B.U0hi[a];
+    p[(3 + a) * P] = B.U0lo[a];
+    p[(6 + a) * P] = B.g2hi[a];
+    p[(9 + a) * P] = B.g2lo[a];
+    p[(12 + a) * P] = B.V[a];
+    p[(15 + a) * P] = st.e[a];
+  }
+  p[18 * P] = s;
+}
+
+__device__ __forceinline__ void load_ray_header(const SceneDev& S, int r, RayBase& B, float e_end[3], float& s) {
+  const float* p = S.ckpt + (size_t)r;
+  const size_t P = (size_t)S.ckpt_pad;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    B.U0hi[a] = p[(0 + a) * P];
+    B.U0lo[a] = p[(3 + a) * P];
+    B.g2hi[a] = p[(6 + a) * P];
+    B.g2lo[a] = p[(9 + a) * P];
+    B.V[a] = p[(12 + a) * P];
+    e_end[a] = p[(15 + a) * P];
+  }
+  s = p[18 * P];
 }
 
 }  // namespace rbos

@@ -5,27 +5,41 @@
 
 namespace rbos {
 
-// Trace one ray; writes its outputs. Checkpoints (d, e) before steps k, 2k, ... are
-// stored component-major: ckpt[(slot * 6 + c) * n_rays + r].
+// Trace one ray; writes its outputs. With checkpoints the buffer holds, component-major
+// (component c of ray r at [c * n_rays + r]): the ray header (see store_ray_header), then
+// the states (d, e) before steps k, 2k, ... (6 components per slot).
 template <int DT>
-__device__ __forceinline__ void trace_one(const SceneDev& S, int tile, int lane, int r, int pix) {
-  Ray R;
-  setup_ray(S, pix, R);
+__device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   int n = 0;
   unsigned char status = 0;
   float uvd[2] = {0.0f, 0.0f};
   bool ok = true;
-  if (!R.entered) {
+  bool entered;
+  RayBase B;
+  Cell C;
+  {
+    Ray R;
+    camera_ray(S, pix, R.dir);
+    df t_in;
+    entered = box_entry(S, R.dir, t_in);
+    if (entered) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        df x = dd_add(S.cam_pos[a], dd_mul(t_in, R.dir[a]));
+        R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), -0.5f);
+      }
+      make_base<DT>(S, R, B, C);
+    }
+  }
+  if (!entered) {
     status |= RAY_MISSED_BOX;
   } else {
-    RayBase B;
-    Cell C;
-    make_base<DT>(S, R, B, C);
     State st;
     state_at_step(B, 0, st);
+#pragma unroll
     for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
     const int K = S.ckpt_k;
-    float* ck = S.ckpt ? S.ckpt + (size_t)r : nullptr;
+    float* ck = S.ckpt ? S.ckpt + (size_t)RAY_HEADER * S.ckpt_pad + (size_t)r : nullptr;
     bool exited = false;
     while (n < S.max_steps) {
       if (ck && n > 0 && (n % K) == 0) {
@@ -50,8 +64,10 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int tile, int lane,
     }
     if (!exited) status |= RAY_TRUNCATED;
     if (!(status & RAY_NONFINITE)) {
-      float dX[3];
-      if (wall_deflection(S, B, st, dX, nullptr)) {
+      float dX[3], s = 0.0f;
+      const bool hit = wall_deflection(S, B, st, dX, &s);
+      if (ck) store_ray_header(S, r, B, st, s);
+      if (hit) {
         uvd[0] = dX[0] * S.wall_u_f[0] + dX[1] * S.wall_u_f[1] + dX[2] * S.wall_u_f[2];
         uvd[1] = dX[0] * S.wall_v_f[0] + dX[1] * S.wall_v_f[1] + dX[2] * S.wall_v_f[2];
       } else {
@@ -62,15 +78,19 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int tile, int lane,
       ok = false;
     }
   }
-  if (!R.wall0 && !(status & RAY_NONFINITE)) {
+  // the undeflected camera ray's wall hit, recomputed here rather than kept live
+  df dir[3], uv0[2];
+  camera_ray(S, pix, dir);
+  const bool wall0 = wall_hit_straight(S, dir, uv0);
+  if (!wall0 && !(status & RAY_NONFINITE)) {
     // the camera ray itself never reaches the wall: treat the hit as missing
-    if (!R.entered) status |= RAY_NO_WALL_HIT;
+    status |= RAY_NO_WALL_HIT;
     ok = false;
   }
   float u, v;
   if (ok) {
-    u = dd_to_f(dd_add_f(R.uv0[0], uvd[0]));
-    v = dd_to_f(dd_add_f(R.uv0[1], uvd[1]));
+    u = dd_to_f(dd_add_f(uv0[0], uvd[0]));
+    v = dd_to_f(dd_add_f(uv0[1], uvd[1]));
   } else {
     u = v = __builtin_nanf("");
     uvd[0] = uvd[1] = __builtin_nanf("");
@@ -96,7 +116,7 @@ __global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ 
   const int tile = gtile - S.tile_begin;
   int r, pix;
   if (!tile_ray(S, tile, lane, r, pix)) return;
-  trace_one<DT>(S, tile, lane, r, pix);
+  trace_one<DT>(S, r, pix);
 }
 
 // Persistent form: blocks pull tiles from per-XCD queues (contiguous tile ranges), and
@@ -119,7 +139,7 @@ __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __
       const SceneDev& S = scenes[si];
       const int tile = t - S.tile_begin;
       int r, pix;
-      if (tile_ray(S, tile, lane, r, pix)) trace_one<DT>(S, tile, lane, r, pix);
+      if (tile_ray(S, tile, lane, r, pix)) trace_one<DT>(S, r, pix);
     }
   }
 }

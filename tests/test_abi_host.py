@@ -43,8 +43,9 @@ def test_struct_layouts_match(lib):
 
 
 def test_field_bytes(lib):
-    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F32) == 32 * 127 ** 3
-    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F16) == 16 * 127 ** 3
+    # one record per cell of the padded grid (one apron cell on each side)
+    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F32) == 32 * 129 ** 3
+    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F16) == 16 * 129 ** 3
     assert lib.rbos_field_bytes(1, 4, 4, 0) == 0 and lib.rbos_field_bytes(449, 4, 4, 0) == 0
     assert lib.rbos_field_bytes(4, 4, 4, 7) == 0
 
@@ -92,6 +93,7 @@ def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
     (lambda s: setattr(s, "step", 1.0), -3),
     (lambda s: setattr(s, "max_steps", 0), -3),
     (lambda s: setattr(s, "ckpt_stride", 12), -7),
+    (lambda s: setattr(s, "ckpt_stride", 264), -7),
 ])
 def test_forward_validation(lib, mutate, code):
     s = _valid_scene()
@@ -152,7 +154,8 @@ def test_field_validation_and_sizes(lib):
                                            C.c_void_p(0x20), None) == -3
     assert lib.rbos_field_encode(4, 4, 4, C.c_void_p(0x10), 3, 1.0, 0.0, C.c_void_p(0x20), None) == -4
     s = _valid_scene()
-    assert lib.rbos_ckpt_bytes(C.byref(s)) == ((64 - 1) // 16) * 6 * 16 * 4
+    # a 19-float ray header plus 6 floats per checkpoint slot, per ray
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + ((64 - 1) // 16) * 6) * 16 * 4
     s.ckpt_stride = 0
     assert lib.rbos_ckpt_bytes(C.byref(s)) == 0
     assert lib.rbos_workspace_bytes(C.byref(s), 1) >= 256

@@ -40,19 +40,18 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def _unrecord(buf: np.ndarray, dims, dtype):
-    """Cell records -> per-voxel codes (each voxel read from every record holding it)."""
-    nx, ny, nz = dims
-    k = 8
-    rec = buf.view(np.uint32 if dtype == "f32" else np.uint16).reshape(nz - 1, ny - 1, nx - 1, k)
-    out = np.zeros((nz, ny, nx), rec.dtype)
+def _expected_records(codes: np.ndarray) -> np.ndarray:
+    """Cell records of the padded grid from per-voxel codes [nz][ny][nx]: record (k, j, i)
+    for cells -1 .. n-1 holds corner c = a + 2b + 4z at voxel clamp(i + a) etc."""
+    nz, ny, nx = codes.shape
+    out = np.empty((nz + 1, ny + 1, nx + 1, 8), codes.dtype)
+    ix, iy, iz = np.arange(-1, nx), np.arange(-1, ny), np.arange(-1, nz)
     for c in range(8):
         a, b, z = c & 1, (c >> 1) & 1, c >> 2
-        out[z:z + nz - 1, b:b + ny - 1, a:a + nx - 1] = rec[..., c]
-    # consistency: every record agrees on shared voxels
-    for c in range(8):
-        a, b, z = c & 1, (c >> 1) & 1, c >> 2
-        assert np.array_equal(out[z:z + nz - 1, b:b + ny - 1, a:a + nx - 1], rec[..., c])
+        X = np.clip(ix + a, 0, nx - 1)
+        Y = np.clip(iy + b, 0, ny - 1)
+        Z = np.clip(iz + z, 0, nz - 1)
+        out[..., c] = codes[Z][:, Y][:, :, X]
     return out
 
 
@@ -63,11 +62,12 @@ def test_field_codes_bit_exact(dtype, offset):
     T = torch.from_numpy(w.T32).to(DEV)
     field = api.Field.from_temperature(T, dtype, None, offset)
     torch.cuda.synchronize()
-    got = _unrecord(_np(field.buf), field.dims, dtype)
+    nx, ny, nz = field.dims
+    got = _np(field.buf).view(np.uint32 if dtype == "f32" else np.uint16).reshape(nz + 1, ny + 1, nx + 1, 8)
     d32 = oracle.delta_from_temperature_f32(w.T32, RHO0G, T0)
     ref = oracle.encode(d32, CODES[dtype], field.scale, offset)
     ref = ref.view(np.uint32) if dtype == "f32" else ref
-    assert np.array_equal(got, ref)
+    assert np.array_equal(got, _expected_records(ref))
     if dtype != "f32":
         q = oracle.decode(ref, CODES[dtype], field.scale, 0.0) * field.scale
         assert np.abs(q).max() <= 2 ** 14  # scale keeps the codes in range
