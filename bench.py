@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: BOS ray tracing forward and forward+adjoint on one MI355X.
 
-Workload H: the 4 x 4 x 3 m room with a 128^3 voxel field (seeded hot plumes plus
-0.5 K/m stratification), a 1024 x 1024 pinhole camera (1,048,576 rays), Sharma RK4 with
-h = 0.5 voxel and at most 512 steps, checkpoints every 16 steps, projector pattern
+Default workload H: the 4 x 4 x 3 m room with a 128^3 voxel field (seeded hot plumes
+plus 0.5 K/m stratification), a 1024 x 1024 pinhole camera (1,048,576 rays), Sharma RK4
+with h = 0.5 voxel and at most 512 steps, checkpoints every 16 steps, projector pattern
 1024 x 1024 (blurred uniform noise). Inputs are synthetic and seeded.
 
-One timed step = the whole hot path on resident inputs: encode the field from
-temperature, trace every ray with checkpoints, render + L_BOS + dL/d(u, v), zero the
-FP64 gradient, adjoint. value = ray-steps / step time (ray-steps = sum of per-ray Sharma
-steps inside the box, read back from the kernel output).
+One timed step = the whole hot path on resident inputs, replayed as one captured HIP
+graph: encode the field(s) from temperature, trace every ray with checkpoints, render +
+L_BOS + dL/d(u, v), zero the FP64 gradient(s), adjoint. value = ray-steps / step time
+(ray-steps = sum of per-ray Sharma steps inside the box, read back from the kernels).
 
-Prints one JSON line (rank 0). See the design doc for the roofline and algorithmic counts.
+Other workloads (--workload): c4 = 64 scenes of uneven grids (48-192 per axis) and
+cameras (128-1024 per side) in one persistent launch with autotuned launch shape and
+checkpoint stride; c5 = 256 x 256 x 192 field, 2048 x 1536 rays, <= 1024 steps, with
+16-bit storage (--dtype f16/bf16) and errors on a 4096-ray subsample.
+
+Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -39,6 +44,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="h", choices=["h", "c4", "c5"])
     p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     p.add_argument("--offset", type=float, default=0.0, help="16-bit code offset c (eta - 1 = c + q/s)")
     p.add_argument("--ckpt", type=int, default=16)
@@ -47,10 +53,87 @@ def parse():
     p.add_argument("--persistent", type=int, default=0)
     p.add_argument("--blocks-per-cu", type=int, default=8)
     p.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
+    p.add_argument("--tune", type=int, default=1, help="c4: autotune launch shape and checkpoint stride")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per adjoint launch")
     return p.parse_args()
+
+
+class Workload:
+    """Fields, scenes, tracer, targets and gradients of one benchmark configuration."""
+
+    def __init__(self, args, dev):
+        import numpy as np
+        import torch
+
+        import bos_inputs as bi
+        from paper_2509_14442_amd import api
+
+        self.args = args
+        tw, th = (int(x) for x in args.tile.split("x"))
+        launch = api.make_launch((tw, th), args.wpb, bool(args.persistent), args.blocks_per_cu)
+        self.temps, self.fields, self.scenes, self.descs = [], [], [], []
+        if args.workload in ("h", "c5"):
+            desc = (bi.scene_h() if args.workload == "h" else bi.scene_c5()).replace(ckpt_stride=args.ckpt)
+            seed_a, seed_b = (3, 4) if args.workload == "h" else (5, 6)
+            lo, hi, dims = desc.box_lo, desc.box_hi, desc.dims
+            TA = bi.temperature_grid(bi.plumes_room(seed_a, lo, hi), lo, hi, dims).astype(np.float32)
+            TB = bi.temperature_grid(bi.plumes_room(seed_b, lo, hi), lo, hi, dims).astype(np.float32)
+            pat_np = bi.blurred_noise(12, (desc.pat_h, desc.pat_w)).astype(np.float32)
+            self.pat_np, self.TA_np, self.TB_np = pat_np, TA, TB
+            pat = torch.from_numpy(pat_np).to(dev)
+            tA = torch.from_numpy(TA).to(dev)
+            fA = api.Field.from_temperature(tA, args.dtype, None, args.offset)
+            fB = api.Field.from_temperature(torch.from_numpy(TB).to(dev), args.dtype, fA.scale, args.offset)
+            trB = api.Tracer([api.Scene(desc, fB, pat)], launch, checkpoints=False)
+            trB.forward().render()
+            self.targets = [trB.image[0].clone()]
+            del trB, fB
+            self.temps, self.fields, self.descs = [tA], [fA], [desc]
+            self.scenes = [api.Scene(desc, fA, pat)]
+            self.pat = pat
+            self.data_note = "synthetic: seeded plume fields; target = render of a second seeded field"
+        else:  # c4
+            pat = torch.from_numpy(bi.blurred_noise(12, (1024, 1024)).astype(np.float32)).to(dev)
+            self.pat = pat
+            for sc, spec in bi.scenes_c4(64):
+                sc = sc.replace(ckpt_stride=args.ckpt)
+                T = torch.from_numpy(bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32))
+                T = T.to(dev)
+                f = api.Field.from_temperature(T, args.dtype, None, args.offset)
+                self.temps.append(T)
+                self.fields.append(f)
+                self.descs.append(sc)
+                self.scenes.append(api.Scene(sc, f, pat))
+            self.targets = [torch.zeros(s.n_rays, device=dev) for s in self.scenes]
+            self.data_note = "synthetic: 64 seeded plume fields; target image = 0"
+            if args.tune:
+                from paper_2509_14442_amd import autotune
+
+                # tune on a subset (every 8th scene), then apply to the batch
+                sub = self.scenes[::8]
+                entry = autotune.tune(sub, "fwd+adj", [self.targets[i] for i in range(0, 64, 8)], reps=1)
+                launch = autotune.launch_of(entry)
+                for s in self.scenes:
+                    s.struct.ckpt_stride = entry["ckpt_stride"]
+                self.tuned = entry
+        self.launch = launch
+        self.tracer = api.Tracer(self.scenes, launch, checkpoints=True)
+        self.fwd_only = api.Tracer(self.scenes, launch, checkpoints=False)
+        self.grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device=dev) for s in self.scenes]
+
+    def encode(self):
+        for f, T in zip(self.fields, self.temps):
+            f.encode_temperature(T)
+
+    def step(self):
+        self.encode()
+        self.tracer.forward()
+        self.tracer.render(self.targets)
+        for g in self.grads:
+            g.zero_()
+        self.tracer.adjoint(self.grads, zero=False)
 
 
 def main():
@@ -63,48 +146,16 @@ def main():
     import numpy as np
     import torch
 
-    import bos_inputs as bi
-    from paper_2509_14442_amd import api
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    desc = bi.scene_h().replace(ckpt_stride=args.ckpt)
-    lo, hi, dims = desc.box_lo, desc.box_hi, desc.dims
-    TA = bi.temperature_grid(bi.plumes_room(3, lo, hi), lo, hi, dims).astype(np.float32)
-    TB = bi.temperature_grid(bi.plumes_room(4, lo, hi), lo, hi, dims).astype(np.float32)
-    pat_np = bi.blurred_noise(12, (desc.pat_h, desc.pat_w)).astype(np.float32)
+    W = Workload(args, dev)
+    tr = W.tracer
 
-    tA = torch.from_numpy(TA).to(dev)
-    tB = torch.from_numpy(TB).to(dev)
-    pat = torch.from_numpy(pat_np).to(dev)
-    tw, th = (int(x) for x in args.tile.split("x"))
-    launch = api.make_launch((tw, th), args.wpb, bool(args.persistent), args.blocks_per_cu)
-
-    fieldA = api.Field.from_temperature(tA, args.dtype, None, args.offset)
-    fieldB = api.Field.from_temperature(tB, args.dtype, fieldA.scale, args.offset)
-    # measured image: the render of field B (outside the timed region)
-    trB = api.Tracer([api.Scene(desc, fieldB, pat)], launch, checkpoints=False)
-    trB.forward().render()
-    target = trB.image[0].clone()
-
-    scene = api.Scene(desc, fieldA, pat)
-    tr = api.Tracer([scene], launch, checkpoints=True)
-    grad = torch.zeros((dims[2], dims[1], dims[0]), dtype=torch.float64, device=dev)
-    fwd_only = api.Tracer([scene], launch, checkpoints=False)
-
-    def step():
-        fieldA.encode_temperature(tA)
-        tr.forward()
-        tr.render([target])
-        grad.zero_()
-        tr.adjoint([grad], zero=False)
-
-    # warm up (also allocates every buffer the step uses)
     for _ in range(max(args.warmup, 1)):
-        step()
+        W.step()
     torch.cuda.synchronize()
-    ray_steps = int(tr.n_steps[0].sum(dtype=torch.int64))
-    loss = float(tr.loss[0])
+    ray_steps = int(sum(int(n.sum(dtype=torch.int64)) for n in tr.n_steps))
+    loss = float(sum(float(l) for l in tr.loss))
 
     graph = None
     if args.graph:
@@ -112,20 +163,19 @@ def main():
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            step()
+            W.step()
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         with torch.cuda.graph(graph):
-            step()
+            W.step()
         torch.cuda.synchronize()
+        W.step()
+        torch.cuda.synchronize()
+        g_eager = [g.clone() for g in W.grads]
         graph.replay()
         torch.cuda.synchronize()
-        g_eager = grad.clone()
-        step()
-        torch.cuda.synchronize()
-        # every replay must reproduce the eager result
-        assert torch.allclose(grad, g_eager, rtol=1e-9, atol=1e-12 * float(g_eager.abs().max())), \
-            "graph replay differs from the eager step"
+        for g, ge in zip(W.grads, g_eager):  # the replay reproduces the eager step
+            assert torch.allclose(g, ge, rtol=1e-9, atol=1e-12 * float(ge.abs().max()) + 1e-300)
 
     # timed region: whole steps
     torch.cuda.synchronize()
@@ -134,10 +184,9 @@ def main():
         if graph is not None:
             graph.replay()
         else:
-            step()
+            W.step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
 
     # per-kernel timing with HIP events on the stream the kernels run on
     cur = torch.cuda.current_stream()
@@ -145,33 +194,30 @@ def main():
     acc = np.zeros(5)
     for _ in range(args.steps):
         ev[0].record(cur)
-        fieldA.encode_temperature(tA)
+        W.encode()
         ev[1].record(cur)
         tr.forward()
         ev[2].record(cur)
-        tr.render([target])
+        tr.render(W.targets)
         ev[3].record(cur)
-        grad.zero_()
+        for g in W.grads:
+            g.zero_()
         ev[4].record(cur)
-        tr.adjoint([grad], zero=False)
+        tr.adjoint(W.grads, zero=False)
         ev[5].record(cur)
         torch.cuda.synchronize()
         acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
     k_ms = acc / args.steps
-    # forward only (no checkpoints) + render
-    evf = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     fwd_ms = 0.0
     for _ in range(args.steps):
-        evf[0].record(cur)
-        fwd_only.forward()
-        evf[1].record(cur)
-        fwd_only.render([target])
-        evf[2].record(cur)
+        ev[0].record(cur)
+        W.fwd_only.forward()
+        W.fwd_only.render(W.targets)
+        ev[1].record(cur)
         torch.cuda.synchronize()
-        fwd_ms += evf[0].elapsed_time(evf[2])
+        fwd_ms += ev[0].elapsed_time(ev[1])
     fwd_ms /= args.steps
-    fwd_steps = int(fwd_only.n_steps[0].sum(dtype=torch.int64))
-    assert fwd_steps == ray_steps
+    assert int(sum(int(n.sum(dtype=torch.int64)) for n in W.fwd_only.n_steps)) == ray_steps
 
     adj_s = k_ms[4] * 1e-3
     achieved = FLOP_ADJ_STEP * ray_steps / adj_s / 1e12
@@ -179,6 +225,15 @@ def main():
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as f:
             traffic = json.load(f).get("adjoint_hbm_bytes_per_launch")
+    n_rays = sum(s.n_rays for s in W.scenes)
+    names = {
+        "h": "H: 128^3 room field (4x4x3 m, seeded plumes + 0.5 K/m), 1024x1024 rays, Sharma RK4 h=0.5 voxel, "
+             "<=512 steps, checkpoint stride %d, projector 1024^2" % args.ckpt,
+        "c4": "C4: 64 room scenes, grids 48-192 per axis, cameras 128-1024 per side (%d rays), one persistent "
+              "launch per kernel, hipGraph" % n_rays,
+        "c5": "C5: 256x256x192 room field, 2048x1536 rays, <=1024 steps, checkpoint stride %d" % args.ckpt,
+    }
+    ckpt_used = int(W.scenes[0].struct.ckpt_stride) if W.scenes else args.ckpt
     out = {
         "metric": METRIC,
         "value": ray_steps / (ms_step * 1e-3),
@@ -191,14 +246,16 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.dtype,
-        "data": "synthetic",
+        "data": W.data_note,
         "config": {
-            "workload": "H: 128^3 room field (4x4x3 m, seeded plumes + 0.5 K/m), 1024x1024 rays, "
-                        "Sharma RK4 h=0.5 voxel, <=512 steps, checkpoint stride %d, projector 1024^2" % args.ckpt,
-            "storage": args.dtype, "offset": args.offset, "tile": args.tile, "waves_per_block": args.wpb,
-            "persistent": bool(args.persistent), "graph": bool(args.graph),
+            "workload": names[args.workload],
+            "storage": args.dtype, "offset": args.offset, "ckpt_stride": ckpt_used,
+            "tile": [int(W.launch.tile_w), int(W.launch.tile_h)],
+            "waves_per_block": int(W.launch.waves_per_block), "persistent": bool(W.launch.persistent),
+            "graph": bool(args.graph),
         },
         "ray_steps": ray_steps,
+        "rays": n_rays,
         "loss": loss,
         "fwd_ray_steps_per_s": ray_steps / (fwd_ms * 1e-3),
         "fwd_ms": fwd_ms,
@@ -215,31 +272,49 @@ def main():
             "flop_per_ray_step": FLOP_ADJ_STEP,
         },
     }
-    if not args.no_cpu:
-        out["cpu_baseline"], out["err"] = cpu_baseline_and_errors(args, desc, TA, TB, pat_np, tr, fieldA, pat,
-                                                                 launch)
+    if hasattr(W, "tuned"):
+        out["config"]["autotune"] = W.tuned
+    if not args.no_cpu and args.workload == "h":
+        out["cpu_baseline"], out["err"] = cpu_baseline_and_errors(args, W)
+    if args.workload == "c5" and not args.no_cpu:
+        out["err"] = subsample_errors(args, W)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_and_errors(args, desc, TA, TB, pat_np, tr, fieldA, pat, launch):
+def _stored_delta(T, dtype, scale, offset):
+    import oracle
+
+    code = {"f32": oracle.CODE_F32, "f16": oracle.CODE_F16, "bf16": oracle.CODE_BF16}[dtype]
+    return oracle.decode(oracle.encode(oracle.delta_from_temperature_f32(T), code, scale, offset), code, scale, offset)
+
+
+def _gpu_subset(W, ids, dL):
+    """GPU forward + adjoint restricted to the pixel ids, with the given dL/d(u, v)."""
+    import torch
+
+    from paper_2509_14442_amd import api
+
+    sub = api.Tracer([api.Scene(W.descs[0], W.fields[0], W.pat, torch.from_numpy(ids).cuda())], W.launch)
+    sub.forward()
+    g = sub.adjoint(dL_duv=[torch.from_numpy(dL.astype("float32")).cuda()])[0]
+    torch.cuda.synchronize()
+    return sub, g.cpu().numpy()
+
+
+def cpu_baseline_and_errors(args, W):
     """The FP64 oracle (test infrastructure) timed on a bounded, evenly spread sample of the
     same rays; the GPU's outputs on that sample are compared with it."""
     import numpy as np
-    import torch
 
     import bos_inputs as bi
     import oracle
-    from paper_2509_14442_amd import api
 
     oracle.build()
-    p64 = pat_np.astype(np.float64)
-
-    def stored(T):
-        return oracle.decode(oracle.encode(oracle.delta_from_temperature_f32(T), oracle.CODE_F32),
-                             oracle.CODE_F32)
-
-    FA = oracle.grid_field(stored(TA), desc.box_lo, desc.box_hi)
-    FB = oracle.grid_field(stored(TB), desc.box_lo, desc.box_hi)
+    desc = W.descs[0]
+    p64 = W.pat_np.astype(np.float64)
+    f = W.fields[0]
+    FA = oracle.grid_field(_stored_delta(W.TA_np, args.dtype, f.scale, args.offset), desc.box_lo, desc.box_hi)
+    FB = oracle.grid_field(_stored_delta(W.TB_np, args.dtype, f.scale, args.offset), desc.box_lo, desc.box_hi)
 
     def run(ids):
         tb = oracle.trace(FB, desc, ids)
@@ -249,34 +324,29 @@ def cpu_baseline_and_errors(args, desc, TA, TB, pat_np, tr, fieldA, pat, launch)
         img, dI, st = oracle.render(desc, p64, fa["uv"], fa["status"])
         L, dL = oracle.loss(img, target, dI)
         g = oracle.adjoint(FA, desc, dL, ids)
-        return time.perf_counter() - t0, fa, dL, g, target
+        return time.perf_counter() - t0, fa, dL, g
 
     # calibrate on a small sample, then size the sample for ~cpu_seconds of oracle work
     probe = bi.strided_tiles(desc.width, desc.height, 8, 256, 7)
-    dt, fa, _, _, _ = run(probe)
+    dt, fa, _, _ = run(probe)
     per_ray = dt / max(len(probe), 1)
     n_target = int(args.cpu_seconds / max(per_ray, 1e-9))
     total_tiles = ((desc.width + 7) // 8) * ((desc.height + 7) // 8)
     keep = max(1, int(total_tiles * 64 / max(n_target, 1)))
     ids = bi.strided_tiles(desc.width, desc.height, 8, keep, 3)
-    dt, fa, dL, g_ref, target = run(ids)
+    dt, fa, dL, g_ref = run(ids)
     steps = int(fa["n_steps"].sum())
     cpu = {"value": steps / dt, "unit": "ray-steps/s", "cores": oracle.threads(), "kind": "oracle",
            "sample": f"{len(ids)} rays (every {keep}th 8x8 tile of the 1024x1024 image), "
                      f"{steps} ray-steps, fwd+render+loss+adjoint in FP64, {dt:.1f} s"}
-
-    # GPU vs oracle on the sample: exit points from the full timed run, gradient from the
-    # adjoint restricted to the sample with the oracle's dL/d(u, v)
+    tr = W.tracer
     uv = tr.uv[0].cpu().numpy().astype(np.float64)[ids]
     duv = tr.duv[0].cpu().numpy().astype(np.float64)[ids]
     ns = tr.n_steps[0].cpu().numpy()[ids]
     ok = np.isfinite(fa["uv"][:, 0])
     e_uv = np.sqrt(((uv[ok] - fa["uv"][ok]) ** 2).sum(1))
     e_duv = np.sqrt(((duv[ok] - fa["duv"][ok]) ** 2).sum(1))
-    sub = api.Tracer([api.Scene(desc, fieldA, pat, torch.from_numpy(ids).cuda())], launch)
-    sub.forward()
-    lam = torch.from_numpy(dL.astype(np.float32)).cuda()
-    g = sub.adjoint(dL_duv=[lam])[0].cpu().numpy()
+    _, g = _gpu_subset(W, ids, dL)
     l2 = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     bound = 1e-3 * np.maximum(np.abs(g_ref), 1e-2 * np.abs(g_ref).max())
     err = {
@@ -290,6 +360,38 @@ def cpu_baseline_and_errors(args, desc, TA, TB, pat_np, tr, fieldA, pat, launch)
         "grad_voxel_fail_frac": float(np.mean(np.abs(g - g_ref) > bound)),
     }
     return cpu, err
+
+
+def subsample_errors(args, W):
+    """C5: errors on a seeded 4096-ray subsample against the oracle on the dequantised
+    field (arithmetic) and on the exact FP64 field (storage + arithmetic)."""
+    import numpy as np
+
+    import bos_inputs as bi
+    import oracle
+
+    oracle.build()
+    desc = W.descs[0]
+    f = W.fields[0]
+    ids = bi.pixel_subset(desc.width * desc.height, 4096, 15)
+    rng = np.random.default_rng(16)
+    lam = rng.standard_normal((len(ids), 2))
+    _, g = _gpu_subset(W, ids, lam)
+    uv = W.tracer.uv[0].cpu().numpy().astype(np.float64)[ids]
+    out = {"sample_rays": int(len(ids)), "storage": args.dtype, "offset": args.offset, "scale": f.scale}
+    exact = oracle.delta_from_temperature(W.TA_np)
+    deq = _stored_delta(W.TA_np, args.dtype, f.scale, args.offset)
+    for name, delta in (("vs_dequantised", deq), ("vs_exact", exact)):
+        F = oracle.grid_field(delta, desc.box_lo, desc.box_hi)
+        ref = oracle.trace(F, desc, ids)
+        ok = np.isfinite(ref["uv"][:, 0])
+        e = np.sqrt(((uv[ok] - ref["uv"][ok]) ** 2).sum(1))
+        g_ref = oracle.adjoint(F, desc, lam.astype(np.float32).astype(np.float64), ids)
+        out[name] = {"exit_err_max_m": float(e.max()), "exit_err_rms_m": float(np.sqrt((e ** 2).mean())),
+                     "grad_rel_l2": float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))}
+        if name == "vs_exact":
+            out["bos_displacement_rms_m"] = float(np.sqrt((ref["duv"][ok] ** 2).sum(1).mean()))
+    return out
 
 
 if __name__ == "__main__":

@@ -135,19 +135,19 @@ def c4_max_steps(lo, hi, dims) -> int:
 
 
 def scenes_c4(n_scenes: int = 64, base_seed: int = 1000, dim_range=(48, 192),
-              ray_range=(128, 1024)) -> List[Tuple[Scene, int]]:
+              ray_range=(128, 1024)):
     """Batch of independent room scenes. Scene i draws, from seed base_seed + i and in
-    this order: nx, ny, nz ~ U{dim_range}, then W, H ~ U{ray_range}; its plume field then
-    continues from the same generator (see `plumes_room(rng=...)`). Returns
-    (scene, seed) pairs."""
+    this order: nx, ny, nz ~ U{dim_range}, then W, H ~ U{ray_range}, then its plume field
+    (as `plumes_room`) from the same generator. Returns (scene, FieldSpec) pairs."""
+    from .fields import plumes_room
+
     out = []
     for i in range(n_scenes):
-        seed = base_seed + i
-        rng = np.random.default_rng(seed)
+        rng = np.random.default_rng(base_seed + i)
         dims = tuple(int(x) for x in rng.integers(dim_range[0], dim_range[1] + 1, size=3))
         w, h = (int(x) for x in rng.integers(ray_range[0], ray_range[1] + 1, size=2))
         sc = scene_room(dims, w, h, c4_max_steps(ROOM_LO, ROOM_HI, dims), 16, name=f"c4_{i}")
-        out.append((sc, seed))
+        out.append((sc, plumes_room(lo=ROOM_LO, hi=ROOM_HI, rng=rng)))
     return out
 
 

@@ -1,0 +1,117 @@
+"""Batching: many scenes of uneven grid and ray counts in one persistent launch, graph
+capture and replay, and the autotuner. Each scene's batched output must equal its
+unbatched output (forward bitwise; FP64 gradients up to the order of atomic additions)."""
+
+import numpy as np
+import pytest
+import torch
+
+import bos_inputs as bi
+import oracle
+from _common import exit_error, stored_delta
+from paper_2509_14442_amd import api, autotune
+from test_gpu_forward import DEV, _np
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(n=5, dim_range=(12, 40), ray_range=(24, 90), ckpt=16):
+    pat = torch.from_numpy(bi.blurred_noise(12, (256, 256)).astype(np.float32)).to(DEV)
+    out = []
+    for sc, spec in bi.scenes_c4(n, 2000, dim_range, ray_range):
+        sc = sc.replace(pat_w=256, pat_h=256, ckpt_stride=ckpt)
+        T = bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32)
+        f = api.Field.from_temperature(torch.from_numpy(T).to(DEV), "f32")
+        out.append((api.Scene(sc, f, pat), T))
+    return out
+
+
+def _run(scenes, launch, lams):
+    tr = api.Tracer(scenes, launch)
+    tr.forward().render()
+    grads = tr.adjoint(dL_duv=lams)
+    torch.cuda.synchronize()
+    return tr, grads
+
+
+def test_batched_equals_single_and_oracle():
+    b = _batch()
+    scenes = [s for s, _ in b]
+    rng = np.random.default_rng(4)
+    lams = [torch.from_numpy(rng.standard_normal((s.n_rays, 2)).astype(np.float32)).to(DEV) for s in scenes]
+    trb, gb = _run(scenes, api.make_launch((8, 8), 4, persistent=True, blocks_per_cu=2), lams)
+    for i, s in enumerate(scenes):
+        tr1, g1 = _run([s], None, [lams[i]])
+        assert torch.equal(trb.uv[i], tr1.uv[0]) and torch.equal(trb.n_steps[i], tr1.n_steps[0])
+        assert torch.equal(trb.image[i], tr1.image[0])
+        d = (gb[i] - g1[0]).abs().max().item()
+        assert d <= 1e-12 * g1[0].abs().max().item(), d
+    # one batched scene against the oracle
+    s, T = b[2]
+    F = oracle.grid_field(stored_delta(T), s.desc.box_lo, s.desc.box_hi)
+    ref = oracle.trace(F, s.desc)
+    ok = np.isfinite(ref["uv"][:, 0])
+    assert exit_error(_np(trb.uv[2])[ok], ref["uv"][ok]).max() <= 1e-6
+    assert np.array_equal(_np(trb.n_steps[2]), ref["n_steps"])
+
+
+def test_graph_replay_matches_eager():
+    b = _batch(3)
+    scenes = [s for s, _ in b]
+    rng = np.random.default_rng(5)
+    targets = [torch.from_numpy(rng.random(s.n_rays).astype(np.float32)).to(DEV) for s in scenes]
+    tr = api.Tracer(scenes, api.make_launch((8, 8), 4, persistent=True, blocks_per_cu=2))
+    grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device=DEV) for s in scenes]
+
+    def step():
+        tr.forward()
+        tr.render(targets)
+        for g in grads:
+            g.zero_()
+        tr.adjoint(grads, zero=False)
+
+    step()
+    torch.cuda.synchronize()
+    ref_uv = [u.clone() for u in tr.uv]
+    ref_loss = [float(l) for l in tr.loss]
+    ref_g = [g.clone() for g in grads]
+    # capture (after a warm-up on a side stream, as graph capture requires)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    other = api.Tracer([scenes[0]])
+    for rep in range(3):
+        for u in tr.uv:
+            u.fill_(-1.0)
+        for g in grads:
+            g.fill_(123.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        for i in range(len(scenes)):
+            assert torch.equal(tr.uv[i], ref_uv[i]), (rep, i)
+            assert float(tr.loss[i]) == ref_loss[i]
+            assert (grads[i] - ref_g[i]).abs().max().item() <= 1e-12 * ref_g[i].abs().max().item()
+        other.forward()  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_autotune_picks_valid_config(tmp_path):
+    b = _batch(2)
+    scenes = [s for s, _ in b]
+    entry = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"), reps=1,
+                          launches=autotune.LAUNCHES[:2] + autotune.LAUNCHES[3:4], strides=(8, 16))
+    assert entry["ckpt_stride"] in (8, 16) and entry["ms"] > 0
+    again = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"))
+    assert again == entry  # served from the cache
+    tr = api.Tracer(scenes, autotune.launch_of(entry))
+    tr.forward()
+    ref = api.Tracer(scenes)
+    ref.forward()
+    torch.cuda.synchronize()
+    for i in range(len(scenes)):
+        assert torch.equal(tr.uv[i], ref.uv[i])
