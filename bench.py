@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: BOS ray tracing forward and forward+adjoint on one MI355X.
 
-Default workload H: the 4 x 4 x 3 m room with a 128^3 voxel field (seeded hot plumes
+Default workload (room1m): the 4 x 4 x 3 m room with a 128^3 voxel field (seeded hot plumes
 plus 0.5 K/m stratification), a 1024 x 1024 pinhole camera (1,048,576 rays), Sharma RK4
 with h = 0.5 voxel and at most 512 steps, checkpoints every 16 steps, projector pattern
 1024 x 1024 (blurred uniform noise). Inputs are synthetic and seeded.
@@ -11,9 +11,9 @@ graph: encode the field(s) from temperature, trace every ray with checkpoints, r
 L_BOS + dL/d(u, v), zero the FP64 gradient(s), adjoint. value = ray-steps / step time
 (ray-steps = sum of per-ray Sharma steps inside the box, read back from the kernels).
 
-Other workloads (--workload): c4 = 64 scenes of uneven grids (48-192 per axis) and
+Other workloads (--workload): batch64 = 64 scenes of uneven grids (48-192 per axis) and
 cameras (128-1024 per side) in one persistent launch with autotuned launch shape and
-checkpoint stride; c5 = 256 x 256 x 192 field, 2048 x 1536 rays, <= 1024 steps, with
+checkpoint stride; room256 = 256 x 256 x 192 field, 2048 x 1536 rays, <= 1024 steps, with
 16-bit storage (--dtype f16/bf16) and errors on a 4096-ray subsample.
 
 Prints one JSON line.
@@ -33,7 +33,8 @@ if ROOT not in sys.path:
 
 METRIC = "ray-steps/s fwd and fwd+adjoint (128^3 field, 1M rays) vs FP64 err; % HBM/L2"
 
-# Algorithmic FP32 work per ray-step (flops, FMA = 2); derivation in the design doc.
+# Algorithmic FP32 work per ray-step (flops, FMA = 2), counted from the operations of one
+# Sharma step (4 trilinear samples with gradient, stage arithmetic) and of its reverse.
 FLOP_FWD_STEP = 200
 FLOP_ADJ_STEP = 700
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
@@ -44,7 +45,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="h", choices=["h", "c4", "c5"])
+    p.add_argument("--workload", default="room1m", choices=["room1m", "batch64", "room256"])
     p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     p.add_argument("--offset", type=float, default=0.0, help="16-bit code offset c (eta - 1 = c + q/s)")
     p.add_argument("--ckpt", type=int, default=16)
@@ -53,7 +54,7 @@ def parse():
     p.add_argument("--persistent", type=int, default=0)
     p.add_argument("--blocks-per-cu", type=int, default=8)
     p.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
-    p.add_argument("--tune", type=int, default=1, help="c4: autotune launch shape and checkpoint stride")
+    p.add_argument("--tune", type=int, default=1, help="batch64: autotune launch shape and checkpoint stride")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per adjoint launch")
@@ -74,9 +75,9 @@ class Workload:
         tw, th = (int(x) for x in args.tile.split("x"))
         launch = api.make_launch((tw, th), args.wpb, bool(args.persistent), args.blocks_per_cu)
         self.temps, self.fields, self.scenes, self.descs = [], [], [], []
-        if args.workload in ("h", "c5"):
-            desc = (bi.scene_h() if args.workload == "h" else bi.scene_c5()).replace(ckpt_stride=args.ckpt)
-            seed_a, seed_b = (3, 4) if args.workload == "h" else (5, 6)
+        if args.workload in ("room1m", "room256"):
+            desc = (bi.scene_room_1m() if args.workload == "room1m" else bi.scene_room_256_3m()).replace(ckpt_stride=args.ckpt)
+            seed_a, seed_b = (3, 4) if args.workload == "room1m" else (5, 6)
             lo, hi, dims = desc.box_lo, desc.box_hi, desc.dims
             TA = bi.temperature_grid(bi.plumes_room(seed_a, lo, hi), lo, hi, dims).astype(np.float32)
             TB = bi.temperature_grid(bi.plumes_room(seed_b, lo, hi), lo, hi, dims).astype(np.float32)
@@ -94,10 +95,10 @@ class Workload:
             self.scenes = [api.Scene(desc, fA, pat)]
             self.pat = pat
             self.data_note = "synthetic: seeded plume fields; target = render of a second seeded field"
-        else:  # c4
+        else:  # batch64
             pat = torch.from_numpy(bi.blurred_noise(12, (1024, 1024)).astype(np.float32)).to(dev)
             self.pat = pat
-            for sc, spec in bi.scenes_c4(64):
+            for sc, spec in bi.scenes_batch(64):
                 sc = sc.replace(ckpt_stride=args.ckpt)
                 T = torch.from_numpy(bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32))
                 T = T.to(dev)
@@ -140,7 +141,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(--gpus must be 1; sharding is described in DESIGN.md)", file=sys.stderr)
+              "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -227,11 +228,11 @@ def main():
             traffic = json.load(f).get("adjoint_hbm_bytes_per_launch")
     n_rays = sum(s.n_rays for s in W.scenes)
     names = {
-        "h": "H: 128^3 room field (4x4x3 m, seeded plumes + 0.5 K/m), 1024x1024 rays, Sharma RK4 h=0.5 voxel, "
+        "room1m": "128^3 room field (4x4x3 m, seeded plumes + 0.5 K/m), 1024x1024 rays, Sharma RK4 h=0.5 voxel, "
              "<=512 steps, checkpoint stride %d, projector 1024^2" % args.ckpt,
-        "c4": "C4: 64 room scenes, grids 48-192 per axis, cameras 128-1024 per side (%d rays), one persistent "
+        "batch64": "64 room scenes, grids 48-192 per axis, cameras 128-1024 per side (%d rays), one persistent "
               "launch per kernel, hipGraph" % n_rays,
-        "c5": "C5: 256x256x192 room field, 2048x1536 rays, <=1024 steps, checkpoint stride %d" % args.ckpt,
+        "room256": "256x256x192 room field, 2048x1536 rays, <=1024 steps, checkpoint stride %d" % args.ckpt,
     }
     ckpt_used = int(W.scenes[0].struct.ckpt_stride) if W.scenes else args.ckpt
     out = {
@@ -274,9 +275,9 @@ def main():
     }
     if hasattr(W, "tuned"):
         out["config"]["autotune"] = W.tuned
-    if not args.no_cpu and args.workload == "h":
+    if not args.no_cpu and args.workload == "room1m":
         out["cpu_baseline"], out["err"] = cpu_baseline_and_errors(args, W)
-    if args.workload == "c5" and not args.no_cpu:
+    if args.workload == "room256" and not args.no_cpu:
         out["err"] = subsample_errors(args, W)
     print(json.dumps(out), flush=True)
 
@@ -363,7 +364,7 @@ def cpu_baseline_and_errors(args, W):
 
 
 def subsample_errors(args, W):
-    """C5: errors on a seeded 4096-ray subsample against the oracle on the dequantised
+    """256x256x192 room: errors on a seeded 4096-ray subsample against the oracle on the dequantised
     field (arithmetic) and on the exact FP64 field (storage + arithmetic)."""
     import numpy as np
 

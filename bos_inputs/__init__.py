@@ -12,20 +12,20 @@ stratification and random patterns stand in for them.
 
 from .scenes import (  # noqa: F401
     Scene,
-    scene_c1,
+    scene_unit_box,
     scene_room,
-    scene_c2,
-    scene_c3,
-    scene_h,
-    scene_c5,
-    scenes_c4,
+    scene_room_512,
+    scene_room_1024x768,
+    scene_room_1m,
+    scene_room_256_3m,
+    scenes_batch,
     scene_paper_geometry,
     ROOM_LO,
     ROOM_HI,
 )
 from .fields import (  # noqa: F401
     Plume,
-    plumes_c1,
+    plume_unit_box,
     plumes_room,
     temperature_grid,
     voxel_centres,

@@ -30,7 +30,7 @@ class FieldSpec:
     t0: float = T_AMBIENT
 
 
-def plumes_c1(seed: int = 1) -> FieldSpec:
+def plume_unit_box(seed: int = 1) -> FieldSpec:
     """One 5 K plume, sigma 0.15 m, centre ~ U[0.3, 0.7]^3 (unit box)."""
     rng = np.random.default_rng(seed)
     c = rng.uniform(0.3, 0.7, size=3)

@@ -75,7 +75,7 @@ def _half_voxel_step(lo: Vec3, hi: Vec3, dims) -> float:
     return 0.5 * min((h - l) / n for l, h, n in zip(lo, hi, dims))
 
 
-def scene_c1() -> Scene:
+def scene_unit_box() -> Scene:
     """32^3 on a unit box; 64x64 pinhole camera 1.5 m in front; printed wall 0.5 m behind."""
     lo, hi, dims = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (32, 32, 32)
     wall_dist = 3.0  # camera (y=-1.5) to wall (y=1.5)
@@ -88,7 +88,7 @@ def scene_c1() -> Scene:
         wall_u=(1.0, 0.0, 0.0), wall_v=(0.0, 0.0, 1.0),
         wall_mode=WALL_PRINTED, pat_w=256, pat_h=256,
         pat_extent_u=extent, pat_extent_v=extent,
-        step=_half_voxel_step(lo, hi, dims), max_steps=128, ckpt_stride=16, name="c1",
+        step=_half_voxel_step(lo, hi, dims), max_steps=128, ckpt_stride=16, name="unit_box",
     )
 
 
@@ -111,30 +111,30 @@ def scene_room(dims=(128, 128, 128), width=512, height=512, max_steps=512,
     )
 
 
-def scene_c2() -> Scene:
-    return scene_room((128, 128, 128), 512, 512, 512, 16, name="c2")
+def scene_room_512() -> Scene:
+    return scene_room((128, 128, 128), 512, 512, 512, 16, name="room_512")
 
 
-def scene_c3() -> Scene:
-    return scene_room((128, 128, 128), 1024, 768, 512, 16, name="c3")
+def scene_room_1024x768() -> Scene:
+    return scene_room((128, 128, 128), 1024, 768, 512, 16, name="room_1024x768")
 
 
-def scene_h() -> Scene:
+def scene_room_1m() -> Scene:
     """Headline workload: 128^3 room field, 1024 x 1024 = 1,048,576 rays."""
-    return scene_room((128, 128, 128), 1024, 1024, 512, 16, name="h")
+    return scene_room((128, 128, 128), 1024, 1024, 512, 16, name="room_1m")
 
 
-def scene_c5() -> Scene:
-    return scene_room((256, 256, 192), 2048, 1536, 1024, 16, name="c5")
+def scene_room_256_3m() -> Scene:
+    return scene_room((256, 256, 192), 2048, 1536, 1024, 16, name="room_256_3m")
 
 
-def c4_max_steps(lo, hi, dims) -> int:
+def batch_max_steps(lo, hi, dims) -> int:
     diag = math.sqrt(sum((h - l) ** 2 for l, h in zip(lo, hi)))
     h = _half_voxel_step(lo, hi, dims)
     return 16 * int(math.ceil(1.1 * diag / h / 16.0))
 
 
-def scenes_c4(n_scenes: int = 64, base_seed: int = 1000, dim_range=(48, 192),
+def scenes_batch(n_scenes: int = 64, base_seed: int = 1000, dim_range=(48, 192),
               ray_range=(128, 1024)):
     """Batch of independent room scenes. Scene i draws, from seed base_seed + i and in
     this order: nx, ny, nz ~ U{dim_range}, then W, H ~ U{ray_range}, then its plume field
@@ -146,7 +146,7 @@ def scenes_c4(n_scenes: int = 64, base_seed: int = 1000, dim_range=(48, 192),
         rng = np.random.default_rng(base_seed + i)
         dims = tuple(int(x) for x in rng.integers(dim_range[0], dim_range[1] + 1, size=3))
         w, h = (int(x) for x in rng.integers(ray_range[0], ray_range[1] + 1, size=2))
-        sc = scene_room(dims, w, h, c4_max_steps(ROOM_LO, ROOM_HI, dims), 16, name=f"c4_{i}")
+        sc = scene_room(dims, w, h, batch_max_steps(ROOM_LO, ROOM_HI, dims), 16, name=f"batch_{i}")
         out.append((sc, plumes_room(lo=ROOM_LO, hi=ROOM_HI, rng=rng)))
     return out
 

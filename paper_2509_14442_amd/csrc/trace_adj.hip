@@ -247,7 +247,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll 1
       for (int i = KS - 1; i >= 0; --i) {
         const bool act = lane_chunk && (c0 + i < n);
-        Cell C1, C2;
+        Cell Q1, Q2;
         float ab[3], bb[3], rs[3], ts[3], ct[8];
         int key = 0;
         if (act) {
@@ -261,25 +261,25 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             s.bh[a] = fmaf(s.jf, B.g2hi[a], B.U0hi[a]);
           }
           float K1[3], K2[3], bh[3], sm[3];
-          locate_state(S, B, s, C1);
-          force_at<DT>(S, C1, K1);
+          locate_state(S, B, s, Q1);
+          force_at<DT>(S, Q1, K1);
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             bh[a] = s.bh[a] + B.g2hi[a];
             sm[a] = small_part(B, a, s.jf + 1.0f, s.d[a] + fmaf(h_2, s.e[a], h2_8 * K1[a]));
           }
-          locate3(S, bh, sm, C2);
-          force_at<DT>(S, C2, K2);
-          Cell C3;
+          locate3(S, bh, sm, Q2);
+          force_at<DT>(S, Q2, K2);
+          Cell Q3;
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             bh[a] = bh[a] + B.g2hi[a];
             sm[a] = small_part(B, a, s.jf + 2.0f, s.d[a] + fmaf(h, s.e[a], h2_2 * K2[a]));
           }
-          locate3(S, bh, sm, C3);
+          locate3(S, bh, sm, Q3);
           // stage C = h K3: adjoint v = h dL/dC
           SampleRev R3;
-          sample_rev<DT>(S, C3, R3);
+          sample_rev<DT>(S, Q3, R3);
           float v[3], p[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -294,12 +294,12 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rs[a] = rb[a] + p[a];
             ts[a] = fmaf(h, rb[a], tb[a]) + h * p[a];
           }
-          key = cell_key(C3);
+          key = cell_key(Q3);
         }
         accumulate(S, A, act, key, ct, lane);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
           SampleRev R2;
-          sample_rev<DT>(S, C2, R2);
+          sample_rev<DT>(S, Q2, R2);
           float v[3], p[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) v[a] = h * bb[a];
@@ -310,12 +310,12 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rs[a] += p[a];
             ts[a] = fmaf(h_2, p[a], ts[a]);
           }
-          key = cell_key(C2);
+          key = cell_key(Q2);
         }
         accumulate(S, A, act, key, ct, lane);
         if (act) {  // stage A = h K1, P1 = x
           SampleRev R1;
-          sample_rev<DT>(S, C1, R1);
+          sample_rev<DT>(S, Q1, R1);
           float v[3], p[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) v[a] = h * ab[a];
@@ -325,7 +325,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rb[a] = rs[a] + p[a];
             tb[a] = ts[a];
           }
-          key = cell_key(C1);
+          key = cell_key(Q1);
         }
         accumulate(S, A, act, key, ct, lane);
       }

@@ -36,9 +36,9 @@ class Workload:
         return self.pattern.astype(np.float32)
 
 
-def c1_workload(width=64, height=64) -> Workload:
-    sc = bi.scene_c1().replace(width=width, height=height)
-    T = bi.temperature_grid(bi.plumes_c1(1), sc.box_lo, sc.box_hi, sc.dims).astype(np.float32)
+def unit_box_workload(width=64, height=64) -> Workload:
+    sc = bi.scene_unit_box().replace(width=width, height=height)
+    T = bi.temperature_grid(bi.plume_unit_box(1), sc.box_lo, sc.box_hi, sc.dims).astype(np.float32)
     return Workload(sc, T, bi.binary_dots(11))
 
 

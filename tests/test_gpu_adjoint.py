@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from _common import c1_workload, grad_errors, oracle_forward, room_workload, stored_delta
+from _common import unit_box_workload, grad_errors, oracle_forward, room_workload, stored_delta
 from paper_2509_14442_amd import api
 from test_gpu_forward import DEV, _np
 
@@ -45,10 +45,10 @@ def _oracle_loss_and_grad(w, target, dL_duv=None):
     return L, dL, g, F
 
 
-def test_loss_and_dl_duv_c1():
-    w = c1_workload()
-    from bos_inputs import plumes_c1, temperature_grid
-    T2 = temperature_grid(plumes_c1(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
+def test_loss_and_dl_duv_unit_box():
+    w = unit_box_workload()
+    from bos_inputs import plume_unit_box, temperature_grid
+    T2 = temperature_grid(plume_unit_box(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
     target = _target(w, T2)
     tr, _ = _gpu_loss_and_grad(w, target)
     L, dL, _, _ = _oracle_loss_and_grad(w, target)
@@ -59,10 +59,10 @@ def test_loss_and_dl_duv_c1():
 
 
 @pytest.mark.parametrize("ckpt", [8, 16, 32])
-def test_adjoint_c1_matches_oracle(ckpt):
-    w = c1_workload()
-    from bos_inputs import plumes_c1, temperature_grid
-    T2 = temperature_grid(plumes_c1(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
+def test_adjoint_unit_box_matches_oracle(ckpt):
+    w = unit_box_workload()
+    from bos_inputs import plume_unit_box, temperature_grid
+    T2 = temperature_grid(plume_unit_box(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
     target = _target(w, T2)
     # one dL/d(u, v) for both sides: the oracle's, as float32
     _, dL, _, _ = _oracle_loss_and_grad(w, target)
@@ -97,9 +97,9 @@ def test_adjoint_persistent_and_tiles_agree():
 
 
 def test_adjoint_against_locked_finite_differences():
-    w = c1_workload(32, 32)
-    from bos_inputs import plumes_c1, temperature_grid
-    T2 = temperature_grid(plumes_c1(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
+    w = unit_box_workload(32, 32)
+    from bos_inputs import plume_unit_box, temperature_grid
+    T2 = temperature_grid(plume_unit_box(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
     target = _target(w, T2)
     tr, g = _gpu_loss_and_grad(w, target)
     F = oracle.grid_field(stored_delta(w.T32), w.scene.box_lo, w.scene.box_hi)

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 def _batch(n=5, dim_range=(12, 40), ray_range=(24, 90), ckpt=16):
     pat = torch.from_numpy(bi.blurred_noise(12, (256, 256)).astype(np.float32)).to(DEV)
     out = []
-    for sc, spec in bi.scenes_c4(n, 2000, dim_range, ray_range):
+    for sc, spec in bi.scenes_batch(n, 2000, dim_range, ray_range):
         sc = sc.replace(pat_w=256, pat_h=256, ckpt_stride=ckpt)
         T = bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32)
         f = api.Field.from_temperature(torch.from_numpy(T).to(DEV), "f32")

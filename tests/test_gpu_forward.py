@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from _common import (CODES, RHO0G, T0, c1_workload, exit_error, oracle_forward, room_workload,
+from _common import (CODES, RHO0G, T0, unit_box_workload, exit_error, oracle_forward, room_workload,
                      stored_delta)
 from paper_2509_14442_amd import api
 
@@ -91,8 +91,8 @@ def _compare_forward(w, tr, tol_exit=1e-6, max_step_mismatch=0):
     return err, derr, ref
 
 
-def test_forward_c1_full():
-    w = c1_workload()
+def test_forward_unit_box_full():
+    w = unit_box_workload()
     tr = gpu_trace(w)
     err, derr, ref = _compare_forward(w, tr)
     # deflection accuracy far below the tolerance (double-float geometry, exact base)
@@ -100,7 +100,7 @@ def test_forward_c1_full():
     assert (ref["status"] & oracle.RAY_MISSED_BOX).sum() > 0  # some rays miss the box
 
 
-def test_forward_room_c2():
+def test_forward_room_512():
     w = room_workload()
     tr = gpu_trace(w)
     err, derr, ref = _compare_forward(w, tr, max_step_mismatch=5)
@@ -109,14 +109,14 @@ def test_forward_room_c2():
 
 
 def test_forward_ragged_camera_and_tiles():
-    w = c1_workload(67, 45)
+    w = unit_box_workload(67, 45)
     for tile in ((8, 8), (16, 4), (64, 1), (1, 64)):
         tr = gpu_trace(w, launch=api.make_launch(tile, 2))
         _compare_forward(w, tr)
 
 
 def test_forward_pixel_subsets_and_empty():
-    w = c1_workload()
+    w = unit_box_workload()
     rng = np.random.default_rng(3)
     ids = np.sort(rng.choice(64 * 64, 777, replace=False)).astype(np.int32)
     w.pixel_ids = ids
@@ -128,12 +128,12 @@ def test_forward_pixel_subsets_and_empty():
 
 
 def test_forward_statuses_truncated_and_nonfinite():
-    w = c1_workload(32, 32)
+    w = unit_box_workload(32, 32)
     w.scene = w.scene.replace(max_steps=7)
     tr = gpu_trace(w)
     _compare_forward(w, tr)
     assert (_np(tr.status[0]) & oracle.RAY_TRUNCATED).sum() > 0
-    w = c1_workload(16, 16)
+    w = unit_box_workload(16, 16)
     w.T32 = w.T32.copy()
     w.T32[10:20, 10:20, 10:20] = np.nan
     tr = gpu_trace(w)

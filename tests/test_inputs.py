@@ -47,12 +47,12 @@ def test_patterns_and_subsets():
     assert len(np.unique(st)) == len(st) and st.max() < 240
 
 
-def test_c4_batch_recipe():
-    scenes = bi.scenes_c4(4)
+def test_batch_recipe():
+    scenes = bi.scenes_batch(4)
     for sc, spec in scenes:
         assert all(48 <= n <= 192 for n in sc.dims)
         assert 128 <= sc.width <= 1024 and 128 <= sc.height <= 1024
         assert sc.max_steps % 16 == 0 and sc.max_steps * sc.step > 1.1 * 6.4
         assert 4 <= len(spec.plumes) <= 8
     # deterministic per seed
-    assert bi.scenes_c4(2)[1][1] == bi.scenes_c4(2)[1][1]
+    assert bi.scenes_batch(2)[1][1] == bi.scenes_batch(2)[1][1]

@@ -10,12 +10,12 @@ import numpy as np
 import pytest
 
 import oracle
-from bos_inputs import binary_dots, plumes_c1, scene_c1, temperature_grid
+from bos_inputs import binary_dots, plume_unit_box, scene_unit_box, temperature_grid
 
 
 def _setup(width=64, height=64, seed=1):
-    sc = scene_c1().replace(width=width, height=height)
-    T = temperature_grid(plumes_c1(seed), sc.box_lo, sc.box_hi, sc.dims)
+    sc = scene_unit_box().replace(width=width, height=height)
+    T = temperature_grid(plume_unit_box(seed), sc.box_lo, sc.box_hi, sc.dims)
     d = oracle.delta_from_temperature(T.astype(np.float32))
     return sc, oracle.grid_field(d, sc.box_lo, sc.box_hi), d
 
@@ -44,7 +44,7 @@ def test_adjoint_matches_locked_central_differences():
     sc, F, d = _setup(64, 64)
     pat = binary_dots(11)
     # target: the image of a second plume field
-    T2 = temperature_grid(plumes_c1(2), sc.box_lo, sc.box_hi, sc.dims)
+    T2 = temperature_grid(plume_unit_box(2), sc.box_lo, sc.box_hi, sc.dims)
     F2 = oracle.grid_field(oracle.delta_from_temperature(T2.astype(np.float32)), sc.box_lo, sc.box_hi)
     _, _, target = _loss_parts(F2, sc, pat, np.zeros(sc.width * sc.height))
     L, dL, _ = _loss_parts(F, sc, pat, target)
@@ -76,7 +76,7 @@ def test_gradient_zero_outside_ray_support():
 
 
 def test_homogeneous_field_constant_pattern_zero_gradient():
-    sc = scene_c1().replace(width=16, height=16)
+    sc = scene_unit_box().replace(width=16, height=16)
     nx, ny, nz = sc.dims
     F = oracle.grid_field(np.full((nz, ny, nx), 2.7e-4), sc.box_lo, sc.box_hi)
     pat = np.full((256, 256), 0.5)

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from bos_inputs import scene_c1, scene_room, voxel_centres
+from bos_inputs import scene_unit_box, scene_room, voxel_centres
 
 F_GAUSS = oracle.oracle.FIELD_GAUSSIAN
 F_ETA2 = oracle.oracle.FIELD_ETA2_LINEAR
@@ -23,7 +23,7 @@ F_HOMOG = oracle.oracle.FIELD_HOMOGENEOUS
 # --- camera --------------------------------------------------------------------------------
 
 def test_camera_centre_and_edges():
-    sc = scene_c1().replace(width=65, height=33)
+    sc = scene_unit_box().replace(width=65, height=33)
     o, d = oracle.camera_ray(sc, (33 // 2) * 65 + 65 // 2)
     assert np.allclose(o, sc.cam_pos) and np.allclose(d, sc.cam_fwd, atol=1e-15)
     # leftmost / rightmost pixel centres subtend the FOV less one pixel
@@ -42,7 +42,7 @@ def test_camera_centre_and_edges():
 # --- homogeneous medium: straight rays -----------------------------------------------------
 
 def test_homogeneous_medium_straight_rays():
-    sc = scene_c1().replace(width=24, height=20)
+    sc = scene_unit_box().replace(width=24, height=20)
     nx, ny, nz = sc.dims
     F = oracle.grid_field(np.full((nz, ny, nx), 2.7e-4), sc.box_lo, sc.box_hi)
     out = oracle.trace(F, sc)
@@ -211,7 +211,7 @@ def test_rays_bend_away_from_hot_plume():
     # hot air is less dense: lower eta; rays bend toward higher eta, i.e. away from the plume
     from bos_inputs import fields
 
-    sc = scene_c1().replace(width=1, height=1, fov_x_deg=1e-6)
+    sc = scene_unit_box().replace(width=1, height=1, fov_x_deg=1e-6)
     spec = fields.FieldSpec((fields.Plume((0.45, 0.5, 0.5), 8.0, 0.1),), 0.0)
     T = fields.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims)
     F = oracle.grid_field(oracle.delta_from_temperature(T.astype(np.float32)), sc.box_lo, sc.box_hi)
@@ -222,7 +222,7 @@ def test_rays_bend_away_from_hot_plume():
 # --- box statuses ---------------------------------------------------------------------------------
 
 def test_box_statuses():
-    sc = scene_c1().replace(width=16, height=16)
+    sc = scene_unit_box().replace(width=16, height=16)
     nx, ny, nz = sc.dims
     d = np.full((nz, ny, nx), 2.7e-4)
     F = oracle.grid_field(d, sc.box_lo, sc.box_hi)

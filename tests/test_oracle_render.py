@@ -5,11 +5,11 @@ import numpy as np
 import pytest
 
 import oracle
-from bos_inputs import scene_c1, scene_room
+from bos_inputs import scene_unit_box, scene_room
 
 
 def _printed(pat):
-    sc = scene_c1()
+    sc = scene_unit_box()
     return sc.replace(pat_h=pat.shape[0], pat_w=pat.shape[1])
 
 
