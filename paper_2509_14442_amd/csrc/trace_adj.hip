@@ -109,12 +109,40 @@ __device__ __forceinline__ float wave_sum8(const float v[8]) {
   return z;
 }
 
-// Add the accumulators of lanes with `sel` to the gradient: lanes that hold the same
-// cell are summed across the wavefront; one lane per 8-lane group then adds one corner
-// (FP64). Apron corners map to the edge voxel they repeat. Must run with all 64 lanes
-// active.
-__device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int lane) {
+// Per-wavefront cache of cell totals between the wavefront reduction and the FP64
+// atomics: a cell is left by the tile's rays over several steps (the bundle crosses a
+// face obliquely), so its partial totals are merged here and reach the gradient once.
+// Slot p holds 8 corner totals in LDS (corner a + 2b + 4c) and its key in lane p of one
+// register; slots are replaced round-robin, and every slot is written out at the end of
+// the tile.
+constexpr int PEND_SLOTS = 32;
+
+struct Pending {
+  float* vals;  // LDS, PEND_SLOTS * 8 floats, wave-private
+  int key;      // lane p < PEND_SLOTS: key of slot p; CELL_NONE when free (always for p >= PEND_SLOTS)
+  int next;     // wave-uniform: slot replaced on the next miss
+};
+
+__device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, int c) {
+  // apron corners map to the edge voxel they repeat
+  const int x = min(max((key & 1023) - 1 + (c & 1), 0), S.n[0] - 1);
+  const int y = min(max(((key >> 10) & 1023) - 1 + ((c >> 1) & 1), 0), S.n[1] - 1);
+  const int z = min(max((key >> 20) - 1 + (c >> 2), 0), S.n[2] - 1);
+  return &S.grad[((size_t)z * S.n[1] + y) * S.n[0] + x];
+}
+
+// Order this lane's LDS accesses of the cache against other lanes' (the hardware runs a
+// wavefront's LDS instructions in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Add the accumulators of lanes with `sel` to the cache: lanes that hold the same cell
+// are summed across the wavefront, then the 8 totals go into that cell's slot (a miss
+// first writes the replaced slot out with one FP64 atomic per corner). Must run with all
+// 64 lanes active.
+__device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int lane, Pending& P) {
   unsigned long long pend = __ballot(sel);
+  const int g = lane >> 3;
+  const int corner = (g & 4) | ((g & 1) << 1) | ((g >> 1) & 1);  // corner of this group's total
   while (pend) {
     const int leader = __ffsll((long long)pend) - 1;
     const int key = __builtin_amdgcn_readlane(A.key, leader);
@@ -123,24 +151,44 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = mine ? A.acc[k] : 0.0f;
     const float total = wave_sum8(v);
-    if ((lane & 7) == 0) {
-      const int g = lane >> 3;
-      const int c = (g & 4) | ((g & 1) << 1) | ((g >> 1) & 1);  // corner a + 2b + 4c of this group's value
-      const int x = min(max((key & 1023) - 1 + (c & 1), 0), S.n[0] - 1);
-      const int y = min(max(((key >> 10) & 1023) - 1 + ((c >> 1) & 1), 0), S.n[1] - 1);
-      const int z = min(max((key >> 20) - 1 + (c >> 2), 0), S.n[2] - 1);
-      unsafeAtomicAdd(&S.grad[((size_t)z * S.n[1] + y) * S.n[0] + x], (double)total);
+    const unsigned long long hit = __ballot(P.key == key);
+    if (hit) {
+      const int slot = __ffsll((long long)hit) - 1;
+      if ((lane & 7) == 0) atomicAdd(&P.vals[slot * 8 + corner], total);
+    } else {
+      const int slot = P.next;
+      P.next = (P.next + 1) & (PEND_SLOTS - 1);
+      const int old = __builtin_amdgcn_readlane(P.key, slot);
+      if (old != CELL_NONE && lane < 8) unsafeAtomicAdd(voxel_of_corner(S, old, lane), (double)P.vals[slot * 8 + lane]);
+      wave_lds_order();
+      if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
+      if (lane == slot) P.key = key;
     }
+    wave_lds_order();
     pend &= ~__ballot(mine);
   }
 }
 
+// Write every occupied slot out to the gradient and empty the cache.
+__device__ __forceinline__ void flush_pending(const SceneDev& S, Pending& P, int lane) {
+  wave_lds_order();
+#pragma unroll 1
+  for (int q = 0; q < PEND_SLOTS * 8 / 64; ++q) {
+    const int idx = q * 64 + lane, slot = idx >> 3;
+    const int key = __shfl(P.key, slot);
+    if (key != CELL_NONE) unsafeAtomicAdd(voxel_of_corner(S, key, idx & 7), (double)P.vals[idx]);
+  }
+  wave_lds_order();
+  P.key = CELL_NONE;
+  P.next = 0;
+}
+
 // Merge one sample's contributions (lanes with act) into the accumulators.
 __device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
-                                           int lane) {
+                                           int lane, Pending& P) {
   const bool change = act && key != A.key;
   const bool out = change && A.key != CELL_NONE;
-  if (__ballot(out)) flush(S, A, out, lane);
+  if (__ballot(out)) flush(S, A, out, lane, P);
   if (change) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
@@ -168,8 +216,11 @@ __device__ __forceinline__ void locate_state(const SceneDev& S, const RayBase& B
   locate3(S, st.bh, sm, C);
 }
 
-// Replayed step-start states of one chunk live in LDS, wave-private:
-// slot (i, component) of lane l at replay[(i * 6 + c) * 64 + l] (conflict-free).
+// LDS per wavefront: the replayed step-start states of one chunk, slot (i, component) of
+// lane l at replay[(i * 6 + c) * 64 + l] (conflict-free), then the cell-total cache.
+template <int KS>
+constexpr int lds_floats_per_wave() { return KS * 6 * 64 + PEND_SLOTS * 8; }
+
 template <int DT, int KS>
 __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int lane, float* __restrict__ replay) {
   int r = 0, pix = 0;
@@ -214,6 +265,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll
   for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
   A.key = CELL_NONE;
+  Pending P{replay + KS * 6 * 64, CELL_NONE, 0};
   const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6, h2_8 = S.h2_8, h2_2 = S.h2_2;
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -296,7 +348,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           key = cell_key(Q3);
         }
-        accumulate(S, A, act, key, ct, lane);
+        accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
           SampleRev R2;
           sample_rev<DT>(S, Q2, R2);
@@ -312,7 +364,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           key = cell_key(Q2);
         }
-        accumulate(S, A, act, key, ct, lane);
+        accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
           SampleRev R1;
           sample_rev<DT>(S, Q1, R1);
@@ -327,7 +379,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           key = cell_key(Q1);
         }
-        accumulate(S, A, act, key, ct, lane);
+        accumulate(S, A, act, key, ct, lane, P);
       }
     }
   }
@@ -346,12 +398,13 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
     for (int k = 0; k < 8; ++k) c0v[k] = kap * (X[k & 1] * Y[(k >> 1) & 1] * Z[k >> 2]);
     key0 = cell_key(C0);
   }
-  accumulate(S, A, active, key0, c0v, lane);
-  flush(S, A, A.key != CELL_NONE, lane);
+  accumulate(S, A, active, key0, c0v, lane, P);
+  flush(S, A, A.key != CELL_NONE, lane, P);
+  flush_pending(S, P, lane);
 }
 
 template <int DT, int KS>
-__global__ __launch_bounds__(256) void k_trace_adj(const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj(const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles,
                                                    int wpb, int nblocks) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
@@ -359,16 +412,16 @@ __global__ __launch_bounds__(256) void k_trace_adj(const SceneDev* __restrict__ 
   const int si = find_scene(scenes, n_scenes, gtile);
   const SceneDev& S = scenes[si];
   extern __shared__ float lds[];
-  adjoint_tile<DT, KS>(S, gtile - S.tile_begin, lane, lds + wave * (KS * 6 * 64));
+  adjoint_tile<DT, KS>(S, gtile - S.tile_begin, lane, lds + wave * lds_floats_per_wave<KS>());
 }
 
 template <int DT, int KS>
-__global__ __launch_bounds__(256) void k_trace_adj_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
                                                               int total_tiles, unsigned int* __restrict__ queues) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int xcd = blockIdx.x & 7;
   extern __shared__ float lds[];
-  float* replay = lds + wave * (KS * 6 * 64);
+  float* replay = lds + wave * lds_floats_per_wave<KS>();
   for (int q = 0; q < 8; ++q) {
     const int qx = (xcd + q) & 7;
     const int q_begin = (int)(((long long)total_tiles * qx) >> 3);
@@ -387,7 +440,7 @@ __global__ __launch_bounds__(256) void k_trace_adj_persistent(const SceneDev* __
 
 template <int DT, int KS>
 static hipError_t launch_adj_t(const LaunchPlan& P, hipStream_t stream) {
-  const size_t lds = sizeof(float) * KS * 6 * 64 * (size_t)P.wpb;
+  const size_t lds = sizeof(float) * lds_floats_per_wave<KS>() * (size_t)P.wpb;
   if (P.persistent) {
     hipLaunchKernelGGL((k_trace_adj_persistent<DT, KS>), dim3(P.persistent_blocks), dim3(64 * P.wpb), lds, stream,
                        P.scenes, P.n_scenes, P.total_tiles, P.queues);
