@@ -113,14 +113,18 @@ __device__ __forceinline__ float wave_sum8(const float v[8]) {
 // atomics: a cell is left by the tile's rays over several steps (the bundle crosses a
 // face obliquely), so its partial totals are merged here and reach the gradient once.
 // Slot p holds 8 corner totals in LDS (corner a + 2b + 4c) and its key in lane p of one
-// register; slots are replaced round-robin, and every slot is written out at the end of
-// the tile.
+// register. Slots are written out in batches at chunk ends (those not touched during the
+// chunk) and at the end of the tile, so the atomics' latency is exposed once per chunk
+// rather than once per cell (a non-returning atomic still counts in vmcnt, which the
+// next load waits on). A miss with every slot taken writes one slot out at once.
 constexpr int PEND_SLOTS = 32;
 
 struct Pending {
-  float* vals;  // LDS, PEND_SLOTS * 8 floats, wave-private
-  int key;      // lane p < PEND_SLOTS: key of slot p; CELL_NONE when free (always for p >= PEND_SLOTS)
-  int next;     // wave-uniform: slot replaced on the next miss
+  float* vals;                  // LDS, PEND_SLOTS * 8 floats, wave-private
+  int key;                      // lane p < PEND_SLOTS: key of slot p; CELL_NONE when free (always for p >= PEND_SLOTS)
+  int next;                     // wave-uniform: slot replaced when all are taken
+  unsigned long long occupied;  // wave-uniform slot masks
+  unsigned long long touched;   // slots hit or filled since the last chunk end
 };
 
 __device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, int c) {
@@ -136,9 +140,8 @@ __device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, i
 __device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 // Add the accumulators of lanes with `sel` to the cache: lanes that hold the same cell
-// are summed across the wavefront, then the 8 totals go into that cell's slot (a miss
-// first writes the replaced slot out with one FP64 atomic per corner). Must run with all
-// 64 lanes active.
+// are summed across the wavefront, then the 8 totals go into that cell's slot. Must run
+// with all 64 lanes active.
 __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int lane, Pending& P) {
   unsigned long long pend = __ballot(sel);
   const int g = lane >> 3;
@@ -152,35 +155,51 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
     for (int k = 0; k < 8; ++k) v[k] = mine ? A.acc[k] : 0.0f;
     const float total = wave_sum8(v);
     const unsigned long long hit = __ballot(P.key == key);
+    int slot;
     if (hit) {
-      const int slot = __ffsll((long long)hit) - 1;
+      slot = __ffsll((long long)hit) - 1;
       if ((lane & 7) == 0) atomicAdd(&P.vals[slot * 8 + corner], total);
     } else {
-      const int slot = P.next;
-      P.next = (P.next + 1) & (PEND_SLOTS - 1);
-      const int old = __builtin_amdgcn_readlane(P.key, slot);
-      if (old != CELL_NONE && lane < 8) unsafeAtomicAdd(voxel_of_corner(S, old, lane), (double)P.vals[slot * 8 + lane]);
-      wave_lds_order();
+      const unsigned long long freem = ~P.occupied & ((1ull << PEND_SLOTS) - 1);
+      if (freem) {
+        slot = __ffsll((long long)freem) - 1;
+      } else {
+        slot = P.next;
+        P.next = (P.next + 1) & (PEND_SLOTS - 1);
+        const int old = __builtin_amdgcn_readlane(P.key, slot);
+        if (lane < 8) unsafeAtomicAdd(voxel_of_corner(S, old, lane), (double)P.vals[slot * 8 + lane]);
+        wave_lds_order();
+      }
       if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
       if (lane == slot) P.key = key;
+      P.occupied |= 1ull << slot;
     }
+    P.touched |= 1ull << slot;
     wave_lds_order();
     pend &= ~__ballot(mine);
   }
 }
 
-// Write every occupied slot out to the gradient and empty the cache.
-__device__ __forceinline__ void flush_pending(const SceneDev& S, Pending& P, int lane) {
+// Write the slots in `which` out to the gradient and free them.
+__device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigned long long which, int lane) {
   wave_lds_order();
 #pragma unroll 1
   for (int q = 0; q < PEND_SLOTS * 8 / 64; ++q) {
+    if (((which >> (8 * q)) & 0xffull) == 0) continue;
     const int idx = q * 64 + lane, slot = idx >> 3;
     const int key = __shfl(P.key, slot);
-    if (key != CELL_NONE) unsafeAtomicAdd(voxel_of_corner(S, key, idx & 7), (double)P.vals[idx]);
+    if ((which >> slot) & 1ull) unsafeAtomicAdd(voxel_of_corner(S, key, idx & 7), (double)P.vals[idx]);
   }
   wave_lds_order();
-  P.key = CELL_NONE;
-  P.next = 0;
+  if ((which >> lane) & 1ull) P.key = CELL_NONE;
+  P.occupied &= ~which;
+}
+
+// Chunk end: write out the slots the chunk did not touch (cells the rays have left).
+__device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lane) {
+  const unsigned long long stale = P.occupied & ~P.touched;
+  if (stale) write_out(S, P, stale, lane);
+  P.touched = 0;
 }
 
 // Merge one sample's contributions (lanes with act) into the accumulators.
@@ -265,7 +284,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll
   for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
   A.key = CELL_NONE;
-  Pending P{replay + KS * 6 * 64, CELL_NONE, 0};
+  Pending P{replay + KS * 6 * 64, CELL_NONE, 0, 0ull, 0ull};
   const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6, h2_8 = S.h2_8, h2_2 = S.h2_2;
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -381,6 +400,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
         }
         accumulate(S, A, act, key, ct, lane, P);
       }
+      chunk_end(S, P, lane);
     }
   }
   // initial condition v0 = (1 + delta(x0)) dir: dL/d delta_c += w_c(x0) sum_a tb_a dir_a / voxel_a
@@ -400,7 +420,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   }
   accumulate(S, A, active, key0, c0v, lane, P);
   flush(S, A, A.key != CELL_NONE, lane, P);
-  flush_pending(S, P, lane);
+  if (P.occupied) write_out(S, P, P.occupied, lane);
 }
 
 template <int DT, int KS>
