@@ -20,6 +20,27 @@
 namespace rbos {
 
 // ------------------------------------------------------------------------------------
+// global-memory access through pointers read from the scene record: the compiler cannot
+// tell that they address global memory and would emit flat instructions, which also
+// count in the LDS wait counter (so every LDS wait would wait for the field gathers).
+// ------------------------------------------------------------------------------------
+#define RBOS_GLOBAL __attribute__((address_space(1)))
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const RBOS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(RBOS_GLOBAL T*)p = v;
+}
+__device__ __forceinline__ void gatomic_add(double* p, double v) {
+  __builtin_amdgcn_global_atomic_fadd_f64((RBOS_GLOBAL double*)p, v);
+}
+
+// ------------------------------------------------------------------------------------
 // double-float
 // ------------------------------------------------------------------------------------
 struct df {
@@ -172,6 +193,10 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// The same value in every lane, made visible as such to the compiler (kept in an SGPR, so
+// that the scene record it indexes is read with scalar loads).
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // scene owning global tile index t (scenes are sorted by tile_begin)
 __device__ __forceinline__ int find_scene(const SceneDev* scenes, int n_scenes, int t) {
   int lo = 0, hi = n_scenes - 1;
@@ -188,7 +213,7 @@ __device__ __forceinline__ bool tile_ray(const SceneDev& S, int tile, int lane, 
   if (S.pixel_ids) {
     r = tile * 64 + lane;
     if (r >= S.n_rays) return false;
-    pix = S.pixel_ids[r];
+    pix = gld(S.pixel_ids + r);
     return true;
   }
   int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
@@ -282,12 +307,12 @@ __device__ __forceinline__ void setup_ray(const SceneDev& S, int pix, Ray& R) {
 template <int DT>
 __device__ __forceinline__ void fetch_cell(const void* __restrict__ cell0, int cell, float c[8]) {
   if constexpr (DT == DT_F32) {
-    const float4* p = reinterpret_cast<const float4*>(cell0) + 2 * (ptrdiff_t)cell;
-    float4 a = p[0], b = p[1];
+    const f32x4* p = reinterpret_cast<const f32x4*>(cell0) + 2 * (ptrdiff_t)cell;
+    const f32x4 a = gld(p), b = gld(p + 1);
     c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
     c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
   } else {
-    uint4 w = reinterpret_cast<const uint4*>(cell0)[(ptrdiff_t)cell];
+    const u32x4 w = gld(reinterpret_cast<const u32x4*>(cell0) + (ptrdiff_t)cell);
     unsigned int v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -578,14 +603,14 @@ __device__ __forceinline__ void store_ray_header(const SceneDev& S, int r, const
   const size_t P = (size_t)S.ckpt_pad;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    p[(0 + a) * P] = B.U0hi[a];
-    p[(3 + a) * P] = B.U0lo[a];
-    p[(6 + a) * P] = B.g2hi[a];
-    p[(9 + a) * P] = B.g2lo[a];
-    p[(12 + a) * P] = B.V[a];
-    p[(15 + a) * P] = st.e[a];
+    gst(p + (0 + a) * P, B.U0hi[a]);
+    gst(p + (3 + a) * P, B.U0lo[a]);
+    gst(p + (6 + a) * P, B.g2hi[a]);
+    gst(p + (9 + a) * P, B.g2lo[a]);
+    gst(p + (12 + a) * P, B.V[a]);
+    gst(p + (15 + a) * P, st.e[a]);
   }
-  p[18 * P] = s;
+  gst(p + 18 * P, s);
 }
 
 __device__ __forceinline__ void load_ray_header(const SceneDev& S, int r, RayBase& B, float e_end[3], float& s) {
@@ -593,14 +618,14 @@ __device__ __forceinline__ void load_ray_header(const SceneDev& S, int r, RayBas
   const size_t P = (size_t)S.ckpt_pad;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    B.U0hi[a] = p[(0 + a) * P];
-    B.U0lo[a] = p[(3 + a) * P];
-    B.g2hi[a] = p[(6 + a) * P];
-    B.g2lo[a] = p[(9 + a) * P];
-    B.V[a] = p[(12 + a) * P];
-    e_end[a] = p[(15 + a) * P];
+    B.U0hi[a] = gld(p + (0 + a) * P);
+    B.U0lo[a] = gld(p + (3 + a) * P);
+    B.g2hi[a] = gld(p + (6 + a) * P);
+    B.g2lo[a] = gld(p + (9 + a) * P);
+    B.V[a] = gld(p + (12 + a) * P);
+    e_end[a] = gld(p + (15 + a) * P);
   }
-  s = p[18 * P];
+  s = gld(p + 18 * P);
 }
 
 }  // namespace rbos

@@ -20,7 +20,7 @@ __device__ __forceinline__ void texel_split(df a, int& i, float& f) {
 __device__ __forceinline__ float texel(const SceneDev& S, int row, int col, bool& inside) {
   if (row < 0 || row >= S.pat_h || col < 0 || col >= S.pat_w) return 0.0f;
   inside = true;
-  return S.pattern[(size_t)row * S.pat_w + col];
+  return gld(S.pattern + (size_t)row * S.pat_w + col);
 }
 
 // bilinear lookup at texel coordinates (a, b) = (column, row), texel centres at integers
@@ -104,29 +104,29 @@ __global__ __launch_bounds__(256) void k_render(const SceneDev* __restrict__ sce
   const int r = (blk - S.render_block_begin) * 256 + threadIdx.x;
   float res2 = 0.0f;
   if (r < S.n_rays) {
-    const int pix = S.pixel_ids ? S.pixel_ids[r] : r;
-    unsigned char st = S.status[r];
+    const int pix = S.pixel_ids ? gld(S.pixel_ids + r) : r;
+    const unsigned char st = gld(S.status + r);
     float I = 0.0f, dI[2] = {0.0f, 0.0f};
     if (!(st & (RAY_NO_WALL_HIT | RAY_NONFINITE))) {
       df dir[3], uv0[2];
       camera_ray(S, pix, dir);
       bool off = false;
       if (wall_hit_straight(S, dir, uv0)) {
-        df u = dd_add_f(uv0[0], S.duv[2 * (size_t)r]);
-        df v = dd_add_f(uv0[1], S.duv[2 * (size_t)r + 1]);
+        df u = dd_add_f(uv0[0], gld(S.duv + 2 * (size_t)r));
+        df v = dd_add_f(uv0[1], gld(S.duv + 2 * (size_t)r + 1));
         I = wall_luminance(S, u, v, dI, off);
       } else {
         off = true;
       }
-      if (off) S.status[r] = st | RAY_OFF_PATTERN;
+      if (off) gst(S.status + r, (unsigned char)(st | RAY_OFF_PATTERN));
     }
-    S.image[r] = I;
+    gst(S.image + r, I);
     if (S.target) {
-      float res = I - S.target[r];
+      float res = I - gld(S.target + r);
       res2 = res * res;
       if (S.dL_duv) {
-        S.dL_duv[2 * (size_t)r] = 2.0f * res * dI[0];
-        S.dL_duv[2 * (size_t)r + 1] = 2.0f * res * dI[1];
+        gst(S.dL_duv + 2 * (size_t)r, 2.0f * res * dI[0]);
+        gst(S.dL_duv + 2 * (size_t)r + 1, 2.0f * res * dI[1]);
       }
     }
   }
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_loss_final(const SceneDev* __restrict__
   float w = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
   __syncthreads();
-  if (threadIdx.x == 0) *S.loss = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) gst(S.loss, (red[0] + red[1]) + (red[2] + red[3]));
 }
 
 hipError_t launch_render(const LaunchPlan& P, hipStream_t stream) {

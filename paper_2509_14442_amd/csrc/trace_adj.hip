@@ -167,7 +167,7 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
         slot = P.next;
         P.next = (P.next + 1) & (PEND_SLOTS - 1);
         const int old = __builtin_amdgcn_readlane(P.key, slot);
-        if (lane < 8) unsafeAtomicAdd(voxel_of_corner(S, old, lane), (double)P.vals[slot * 8 + lane]);
+        if (lane < 8) gatomic_add(voxel_of_corner(S, old, lane), (double)P.vals[slot * 8 + lane]);
         wave_lds_order();
       }
       if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigne
     if (((which >> (8 * q)) & 0xffull) == 0) continue;
     const int idx = q * 64 + lane, slot = idx >> 3;
     const int key = __shfl(P.key, slot);
-    if ((which >> slot) & 1ull) unsafeAtomicAdd(voxel_of_corner(S, key, idx & 7), (double)P.vals[idx]);
+    if ((which >> slot) & 1ull) gatomic_add(voxel_of_corner(S, key, idx & 7), (double)P.vals[idx]);
   }
   wave_lds_order();
   if ((which >> lane) & 1ull) P.key = CELL_NONE;
@@ -223,8 +223,8 @@ __device__ __forceinline__ void load_ckpt(const SceneDev& S, int r, int slot, St
   const float* ck = S.ckpt + (size_t)(RAY_HEADER + slot * 6) * (size_t)S.ckpt_pad + (size_t)r;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    st.d[a] = ck[(size_t)a * S.ckpt_pad];
-    st.e[a] = ck[(size_t)(3 + a) * S.ckpt_pad];
+    st.d[a] = gld(ck + (size_t)a * S.ckpt_pad);
+    st.e[a] = gld(ck + (size_t)(3 + a) * S.ckpt_pad);
   }
 }
 
@@ -249,9 +249,9 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   RayBase B;
   float rb[3] = {0.0f, 0.0f, 0.0f}, tb[3] = {0.0f, 0.0f, 0.0f};  // dL/dd, dL/de (grid units)
   if (valid) {
-    n = S.n_steps[r];
-    const unsigned char st = S.status[r];
-    const float lu = S.adj_dL_duv[2 * (size_t)r], lv = S.adj_dL_duv[2 * (size_t)r + 1];
+    n = gld(S.n_steps + r);
+    const unsigned char st = gld(S.status + r);
+    const float lu = gld(S.adj_dL_duv + 2 * (size_t)r), lv = gld(S.adj_dL_duv + 2 * (size_t)r + 1);
     active = n > 0 && !(st & (RAY_NO_WALL_HIT | RAY_NONFINITE | RAY_MISSED_BOX)) && !(lu == 0.0f && lv == 0.0f);
     if (active) {
       // wall step X = x + s v: lambda_x = lambda_X - n (v . lambda_X)/(v . n),
@@ -426,7 +426,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 template <int DT, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj(const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles,
                                                    int wpb, int nblocks) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
   if (gtile >= total_tiles) return;  // whole wavefront
   const int si = find_scene(scenes, n_scenes, gtile);
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 template <int DT, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
                                                               int total_tiles, unsigned int* __restrict__ queues) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   const int xcd = blockIdx.x & 7;
   extern __shared__ float lds[];
   float* replay = lds + wave * lds_floats_per_wave<KS>();
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     while (true) {
       int t = 0;
       if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
-      t = __shfl(t, 0) + q_begin;
+      t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
       if (t >= q_end) break;
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];

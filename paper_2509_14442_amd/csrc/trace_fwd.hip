@@ -46,8 +46,8 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
         size_t base = (size_t)(n / K - 1) * 6 * (size_t)S.ckpt_pad;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          ck[base + (size_t)a * S.ckpt_pad] = st.d[a];
-          ck[base + (size_t)(3 + a) * S.ckpt_pad] = st.e[a];
+          gst(ck + base + (size_t)a * S.ckpt_pad, st.d[a]);
+          gst(ck + base + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
         }
       }
       sharma_step<DT>(S, B, st, C);
@@ -95,20 +95,20 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
     u = v = __builtin_nanf("");
     uvd[0] = uvd[1] = __builtin_nanf("");
   }
-  S.uv[2 * (size_t)r] = u;
-  S.uv[2 * (size_t)r + 1] = v;
+  gst(S.uv + 2 * (size_t)r, u);
+  gst(S.uv + 2 * (size_t)r + 1, v);
   if (S.duv) {
-    S.duv[2 * (size_t)r] = uvd[0];
-    S.duv[2 * (size_t)r + 1] = uvd[1];
+    gst(S.duv + 2 * (size_t)r, uvd[0]);
+    gst(S.duv + 2 * (size_t)r + 1, uvd[1]);
   }
-  S.n_steps[r] = n;
-  S.status[r] = status;
+  gst(S.n_steps + r, n);
+  gst(S.status + r, status);
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ scenes, int n_scenes,
                                                    int total_tiles, int wpb, int nblocks) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
   if (gtile >= total_tiles) return;
   const int si = find_scene(scenes, n_scenes, gtile);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __
     while (true) {
       int t = 0;
       if (lane == 0) t = (int)atomicAdd(&queues[qx], 1u);
-      t = __shfl(t, 0) + q_begin;
+      t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
       if (t >= q_end) break;
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];
