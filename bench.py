@@ -48,11 +48,15 @@ def parse():
     p.add_argument("--workload", default="room1m", choices=["room1m", "batch64", "room256"])
     p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     p.add_argument("--offset", type=float, default=0.0, help="16-bit code offset c (eta - 1 = c + q/s)")
-    p.add_argument("--ckpt", type=int, default=16)
-    p.add_argument("--tile", default="8x8")
-    p.add_argument("--wpb", type=int, default=4)
-    p.add_argument("--persistent", type=int, default=0)
-    p.add_argument("--blocks-per-cu", type=int, default=8)
+    p.add_argument("--ckpt", type=int, default=8, help="checkpoint stride (steps)")
+    p.add_argument("--tile", default="8x8", help="forward: rays per wavefront tile")
+    p.add_argument("--wpb", type=int, default=4, help="forward: wavefronts per block")
+    p.add_argument("--persistent", type=int, default=0, help="forward: persistent blocks with tile queues")
+    p.add_argument("--blocks-per-cu", type=int, default=0, help="persistent: 0 = the kernel's occupancy limit")
+    p.add_argument("--adj-tile", default="8x8")
+    p.add_argument("--adj-wpb", type=int, default=2)
+    p.add_argument("--adj-persistent", type=int, default=1)
+    p.add_argument("--adj-blocks-per-cu", type=int, default=0)
     p.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
     p.add_argument("--tune", type=int, default=1, help="batch64: autotune launch shape and checkpoint stride")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
@@ -81,7 +85,20 @@ def adjoint_source_hash() -> str:
     return h.hexdigest()
 
 
-def read_traffic(path, args):
+def launch_desc(l) -> dict:
+    return {"tile": [int(l.tile_w), int(l.tile_h)], "waves_per_block": int(l.waves_per_block),
+            "persistent": bool(l.persistent), "blocks_per_cu": int(l.blocks_per_cu)}
+
+
+def traffic_config(args, W) -> dict:
+    """What the adjoint's counters depend on: workload, storage, stride and its launch."""
+    l = W.adj_launch
+    return {"workload": args.workload, "dtype": args.dtype, "ckpt_stride": str(W.ckpt_stride),
+            "adj_launch": "%dx%d wpb %d persistent %d bpc %d" % (l.tile_w, l.tile_h, l.waves_per_block,
+                                                                 l.persistent, l.blocks_per_cu)}
+
+
+def read_traffic(path, args, W):
     """HBM bytes per adjoint launch from the counter summary, or None when there is none,
     it was taken on another configuration, or the kernel has changed since."""
     if not path or not os.path.exists(path):
@@ -92,9 +109,7 @@ def read_traffic(path, args):
             if line.startswith("    ") and ": " in line:
                 k, v = line.strip().split(": ", 1)
                 kv[k] = v
-    want = {"workload": args.workload, "dtype": args.dtype, "ckpt_stride": str(args.ckpt), "tile": args.tile,
-            "waves_per_block": str(args.wpb), "persistent": str(args.persistent),
-            "source_sha256": adjoint_source_hash()}
+    want = dict(traffic_config(args, W), source_sha256=adjoint_source_hash())
     if any(kv.get(k) != v for k, v in want.items()) or "hbm_bytes_per_launch" not in kv:
         return None
     return float(kv["hbm_bytes_per_launch"])
@@ -126,6 +141,8 @@ class Workload:
         self.args = args
         tw, th = (int(x) for x in args.tile.split("x"))
         launch = api.make_launch((tw, th), args.wpb, bool(args.persistent), args.blocks_per_cu)
+        tw, th = (int(x) for x in args.adj_tile.split("x"))
+        adj_launch = api.make_launch((tw, th), args.adj_wpb, bool(args.adj_persistent), args.adj_blocks_per_cu)
         self.temps, self.fields, self.scenes, self.descs = [], [], [], []
         if args.workload in ("room1m", "room256"):
             desc = (bi.scene_room_1m() if args.workload == "room1m" else bi.scene_room_256_3m()).replace(ckpt_stride=args.ckpt)
@@ -168,11 +185,13 @@ class Workload:
                 sub = self.scenes[::8]
                 entry = autotune.tune(sub, "fwd+adj", [self.targets[i] for i in range(0, 64, 8)], reps=1)
                 launch = autotune.launch_of(entry)
+                adj_launch = autotune.launch_of(entry, "adj")
                 for s in self.scenes:
                     s.struct.ckpt_stride = entry["ckpt_stride"]
                 self.tuned = entry
-        self.launch = launch
-        self.tracer = api.Tracer(self.scenes, launch, checkpoints=True)
+        self.launch, self.adj_launch = launch, adj_launch
+        self.ckpt_stride = int(self.scenes[0].struct.ckpt_stride)
+        self.tracer = api.Tracer(self.scenes, launch, checkpoints=True, adjoint_launch=adj_launch)
         self.fwd_only = api.Tracer(self.scenes, launch, checkpoints=False)
         self.grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device=dev) for s in self.scenes]
 
@@ -277,16 +296,15 @@ def main():
 
     adj_s = k_ms[4] * 1e-3
     achieved = FLOP_ADJ_STEP * ray_steps / adj_s / 1e12
-    traffic = read_traffic(args.traffic, args)
+    traffic = read_traffic(args.traffic, args, W)
     n_rays = sum(s.n_rays for s in W.scenes)
     names = {
         "room1m": "128^3 room field (4x4x3 m, seeded plumes + 0.5 K/m), 1024x1024 rays, Sharma RK4 h=0.5 voxel, "
-             "<=512 steps, checkpoint stride %d, projector 1024^2" % args.ckpt,
+             "<=512 steps, checkpoint stride %d, projector 1024^2" % W.ckpt_stride,
         "batch64": "64 room scenes, grids 48-192 per axis, cameras 128-1024 per side (%d rays), one persistent "
               "launch per kernel, hipGraph" % n_rays,
-        "room256": "256x256x192 room field, 2048x1536 rays, <=1024 steps, checkpoint stride %d" % args.ckpt,
+        "room256": "256x256x192 room field, 2048x1536 rays, <=1024 steps, checkpoint stride %d" % W.ckpt_stride,
     }
-    ckpt_used = int(W.scenes[0].struct.ckpt_stride) if W.scenes else args.ckpt
     out = {
         "metric": METRIC,
         "value": ray_steps / (ms_step * 1e-3),
@@ -302,9 +320,8 @@ def main():
         "data": W.data_note,
         "config": {
             "workload": names[args.workload],
-            "storage": args.dtype, "offset": args.offset, "ckpt_stride": ckpt_used,
-            "tile": [int(W.launch.tile_w), int(W.launch.tile_h)],
-            "waves_per_block": int(W.launch.waves_per_block), "persistent": bool(W.launch.persistent),
+            "storage": args.dtype, "offset": args.offset, "ckpt_stride": W.ckpt_stride,
+            "fwd_launch": launch_desc(W.launch), "adj_launch": launch_desc(W.adj_launch),
             "graph": bool(args.graph),
         },
         "ray_steps": ray_steps,
@@ -347,7 +364,8 @@ def _gpu_subset(W, ids, dL):
 
     from paper_2509_14442_amd import api
 
-    sub = api.Tracer([api.Scene(W.descs[0], W.fields[0], W.pat, torch.from_numpy(ids).cuda())], W.launch)
+    sub = api.Tracer([api.Scene(W.descs[0], W.fields[0], W.pat, torch.from_numpy(ids).cuda())], W.launch,
+                     adjoint_launch=W.adj_launch)
     sub.forward()
     g = sub.adjoint(dL_duv=[torch.from_numpy(dL.astype("float32")).cuda()])[0]
     torch.cuda.synchronize()

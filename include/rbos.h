@@ -141,7 +141,8 @@ typedef struct rbos_launch {
   int32_t tile_w, tile_h;     /* rays per wavefront tile, tile_w * tile_h == 64 */
   int32_t waves_per_block;    /* 1, 2 or 4 */
   int32_t persistent;         /* 1: persistent blocks pulling tiles from per-XCD queues */
-  int32_t blocks_per_cu;      /* persistent mode: resident blocks per compute unit (1-16) */
+  int32_t blocks_per_cu;      /* persistent mode: resident blocks per compute unit (1-16), or 0 for as
+                                 many as each kernel's registers and LDS allow */
 } rbos_launch;
 
 /* Library and ABI version (RBOS_ABI_VERSION). */

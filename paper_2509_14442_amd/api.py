@@ -166,7 +166,7 @@ class Scene:
         self.struct.dtype, self.struct.enc_scale, self.struct.enc_offset = field.code, field.scale, field.offset
 
 
-def make_launch(tile=(8, 8), waves_per_block=4, persistent=False, blocks_per_cu=8) -> L.rbos_launch:
+def make_launch(tile=(8, 8), waves_per_block=4, persistent=False, blocks_per_cu=0) -> L.rbos_launch:
     l = L.rbos_launch()
     l.tile_w, l.tile_h = tile
     l.waves_per_block = waves_per_block
@@ -178,10 +178,14 @@ def make_launch(tile=(8, 8), waves_per_block=4, persistent=False, blocks_per_cu=
 class Tracer:
     """Output buffers, workspace and the three ABI calls for a batch of scenes."""
 
-    def __init__(self, scenes: List[Scene], launch: Optional[L.rbos_launch] = None, checkpoints: bool = True):
+    def __init__(self, scenes: List[Scene], launch: Optional[L.rbos_launch] = None, checkpoints: bool = True,
+                 adjoint_launch: Optional[L.rbos_launch] = None):
+        """`launch` shapes the forward trace and, unless `adjoint_launch` is given, the
+        adjoint too (checkpoints are stored per ray, so the two may differ)."""
         self.scenes = scenes
         self.n = len(scenes)
         self.launch = launch
+        self.adjoint_launch = adjoint_launch if adjoint_launch is not None else launch
         self._arr = (L.rbos_scene * max(self.n, 1))(*[s.struct for s in scenes])
         dev = scenes[0].field.buf.device if scenes else torch.device("cuda")
         ws = lib().rbos_workspace_bytes(self._arr, self.n)
@@ -213,6 +217,9 @@ class Tracer:
 
     def _launch_ptr(self):
         return C.byref(self.launch) if self.launch is not None else None
+
+    def _adjoint_launch_ptr(self):
+        return C.byref(self.adjoint_launch) if self.adjoint_launch is not None else None
 
     def forward(self, stream=None):
         L.check(lib().rbos_trace_forward(self._arr, self.n, self._outs, self._launch_ptr(),
@@ -265,7 +272,7 @@ class Tracer:
             d = dL[i].to(device=dev, dtype=torch.float32).contiguous()
             keep.append(d)
             io[i].dL_duv, io[i].grad = _ptr(d), _ptr(grads[i])
-        L.check(lib().rbos_trace_adjoint(self._arr, self.n, self._outs, io, self._launch_ptr(),
+        L.check(lib().rbos_trace_adjoint(self._arr, self.n, self._outs, io, self._adjoint_launch_ptr(),
                                          _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
         self._keep_adj = keep
         return grads

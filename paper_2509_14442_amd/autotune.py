@@ -20,13 +20,14 @@ from . import api
 DEFAULT_CACHE = os.environ.get("RBOS_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "rbos", "autotune.json"))
 
-# (tile, waves per block, persistent, blocks per CU)
+# (tile, waves per block, persistent, blocks per CU; 0 = each kernel's occupancy limit)
 LAUNCHES: List[Tuple[Tuple[int, int], int, bool, int]] = [
-    ((8, 8), 4, False, 8),
-    ((8, 8), 2, False, 8),
-    ((16, 4), 4, False, 8),
-    ((8, 8), 4, True, 3),
-    ((8, 8), 4, True, 6),
+    ((8, 8), 4, False, 0),
+    ((8, 8), 2, False, 0),
+    ((16, 4), 4, False, 0),
+    ((8, 8), 4, True, 0),
+    ((8, 8), 2, True, 0),
+    ((8, 8), 4, True, 2),
 ]
 STRIDES = (8, 16, 32)
 
@@ -41,7 +42,7 @@ def cache_key(scenes: Sequence[api.Scene], mode: str) -> str:
     vox = sum(s.dims[0] * s.dims[1] * s.dims[2] for s in scenes) / max(len(scenes), 1)
     rays = sum(s.n_rays for s in scenes)
     dtype = scenes[0].field.dtype if scenes else "f32"
-    return f"{arch}|{dtype}|g{_bucket(vox)}|r{_bucket(rays)}|n{len(scenes)}|{mode}"
+    return f"v2|{arch}|{dtype}|g{_bucket(vox)}|r{_bucket(rays)}|n{len(scenes)}|{mode}"
 
 
 def ckpt_bytes(scenes: Sequence[api.Scene], stride: int) -> int:
@@ -66,11 +67,22 @@ def _time(fn, reps: int) -> float:
     return best
 
 
+def _entry_of(launch_t) -> Dict:
+    (tw, th), wpb, pers, bpc = launch_t
+    return {"tile": [tw, th], "waves_per_block": wpb, "persistent": bool(pers), "blocks_per_cu": bpc}
+
+
 def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[torch.Tensor]] = None,
          strides: Sequence[int] = STRIDES, launches=LAUNCHES, hbm_budget: Optional[int] = None,
          reps: int = 2, cache: Optional[str] = DEFAULT_CACHE, force: bool = False) -> Dict:
-    """Pick (launch, checkpoint stride) for these scenes; returns the cached or new entry
-    {"tile", "waves_per_block", "persistent", "blocks_per_cu", "ckpt_stride", "ms"}."""
+    """Pick launch shapes and the checkpoint stride for these scenes; returns the cached or
+    new entry {"fwd": launch, "adj": launch, "ckpt_stride", "ms"} (a launch is {"tile",
+    "waves_per_block", "persistent", "blocks_per_cu"}; "adj" is absent for mode "fwd").
+
+    Stage 1 times the forward trace (with checkpoints at stride 16 unless mode is "fwd")
+    for every launch shape, stage 2 the adjoint alone for every shape after one forward
+    with the best forward shape, stage 3 the whole forward + render + adjoint for every
+    stride whose checkpoints fit `hbm_budget` (default: half the free device memory)."""
     key = cache_key(scenes, mode)
     db = {}
     if cache and os.path.exists(cache):
@@ -83,46 +95,52 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
         hbm_budget = int(free * 0.5)
     if targets is None:
         targets = [None] * len(scenes)
-    best = None
+    tg = [t if t is not None else torch.zeros(s.n_rays, device="cuda") for t, s in zip(targets, scenes)]
+    adj = mode != "fwd"
 
-    def run_cfg(launch_t, stride):
-        launch = api.make_launch(*launch_t)
+    def tracer(fwd_t, adj_t, stride):
         for s in scenes:
             s.struct.ckpt_stride = stride
-        tr = api.Tracer(scenes, launch, checkpoints=(mode != "fwd"))
-        if mode == "fwd":
-            return _time(lambda: tr.forward(), reps)
-        tg = [t if t is not None else torch.zeros(s.n_rays, device="cuda") for t, s in zip(targets, scenes)]
-        grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device="cuda") for s in scenes]
+        return api.Tracer(scenes, api.make_launch(*fwd_t), checkpoints=adj,
+                          adjoint_launch=api.make_launch(*adj_t) if adj_t is not None else None)
 
-        def step():
+    default_stride = 16 if adj else 0
+    fwd_ms = [(_time(tracer(lt, None, default_stride).forward, reps), lt) for lt in launches]
+    fwd_ms.sort(key=lambda x: x[0])
+    best_fwd = fwd_ms[0][1]
+    entry = {"fwd": _entry_of(best_fwd), "ckpt_stride": default_stride, "ms": fwd_ms[0][0]}
+    if adj:
+        grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device="cuda") for s in scenes]
+        adj_ms = []
+        for lt in launches:
+            tr = tracer(best_fwd, lt, default_stride)
             tr.forward()
             tr.render(tg)
-            tr.adjoint(grads, zero=False)
+            adj_ms.append((_time(lambda: tr.adjoint(grads, zero=False), reps), lt))
+            del tr
+        adj_ms.sort(key=lambda x: x[0])
+        best_adj = adj_ms[0][1]
 
-        return _time(step, reps)
+        def whole(stride):
+            tr = tracer(best_fwd, best_adj, stride)
 
-    # stage 1: launch shape at the default stride; stage 2: stride with the best shape
-    default_stride = 16 if mode != "fwd" else 0
-    results = []
-    for lt in launches:
-        ms = run_cfg(lt, default_stride)
-        results.append((ms, lt, default_stride))
-    results.sort(key=lambda x: x[0])
-    best_lt = results[0][1]
-    best = results[0]
-    if mode != "fwd":
+            def step():
+                tr.forward()
+                tr.render(tg)
+                tr.adjoint(grads, zero=False)
+
+            return _time(step, reps)
+
+        best = (whole(default_stride), default_stride)
         for st in strides:
             if st == default_stride or ckpt_bytes(scenes, st) > hbm_budget:
                 continue
-            ms = run_cfg(best_lt, st)
+            ms = whole(st)
             if ms < best[0]:
-                best = (ms, best_lt, st)
+                best = (ms, st)
+        entry.update({"adj": _entry_of(best_adj), "ckpt_stride": best[1], "ms": best[0]})
     for s in scenes:
-        s.struct.ckpt_stride = best[2]
-    (tw, th), wpb, pers, bpc = best[1]
-    entry = {"tile": [tw, th], "waves_per_block": wpb, "persistent": bool(pers), "blocks_per_cu": bpc,
-             "ckpt_stride": best[2], "ms": best[0]}
+        s.struct.ckpt_stride = entry["ckpt_stride"]
     if cache:
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         db[key] = entry
@@ -131,6 +149,7 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
     return entry
 
 
-def launch_of(entry: Dict):
-    return api.make_launch(tuple(entry["tile"]), entry["waves_per_block"], entry["persistent"],
-                           entry["blocks_per_cu"])
+def launch_of(entry: Dict, which: str = "fwd"):
+    """The tuned launch of the forward ("fwd") or adjoint ("adj") kernel."""
+    e = entry[which]
+    return api.make_launch(tuple(e["tile"]), e["waves_per_block"], e["persistent"], e["blocks_per_cu"])

@@ -52,7 +52,7 @@ bool pow2(double s) {
 }
 
 struct Launch {
-  int tile_w = 8, tile_h = 8, wpb = 4, persistent = 0, blocks_per_cu = 8;
+  int tile_w = 8, tile_h = 8, wpb = 4, persistent = 0, blocks_per_cu = 0;
 };
 
 int check_launch(const rbos_launch* L, Launch& out) {
@@ -63,8 +63,8 @@ int check_launch(const rbos_launch* L, Launch& out) {
   if (L->waves_per_block != 1 && L->waves_per_block != 2 && L->waves_per_block != 4)
     return fail(RBOS_E_RANGE, "launch: waves_per_block must be 1, 2 or 4 (got %d)", L->waves_per_block);
   if (L->persistent != 0 && L->persistent != 1) return fail(RBOS_E_RANGE, "launch: persistent must be 0 or 1");
-  if (L->persistent && (L->blocks_per_cu < 1 || L->blocks_per_cu > 16))
-    return fail(RBOS_E_RANGE, "launch: blocks_per_cu must be in [1, 16] (got %d)", L->blocks_per_cu);
+  if (L->persistent && (L->blocks_per_cu < 0 || L->blocks_per_cu > 16))
+    return fail(RBOS_E_RANGE, "launch: blocks_per_cu must be in [0, 16] (got %d)", L->blocks_per_cu);
   out.tile_w = L->tile_w;
   out.tile_h = L->tile_h;
   out.wpb = L->waves_per_block;
@@ -291,7 +291,7 @@ int prepare(const rbos_scene* scenes, int32_t n_scenes, const rbos_launch* launc
   return RBOS_OK;
 }
 
-int persistent_blocks(const Launch& L) {
+int compute_units() {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0, v = 0;
@@ -299,7 +299,7 @@ int persistent_blocks(const Launch& L) {
       cus = v;
     if (cus <= 0) cus = 256;
   }
-  return cus * L.blocks_per_cu;
+  return cus;
 }
 
 int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::LaunchPlan& plan) {
@@ -312,7 +312,8 @@ int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::Launch
   plan.wpb = P.L.wpb;
   plan.dtype = P.table.empty() ? 0 : P.table[0].dtype;
   plan.persistent = P.L.persistent;
-  plan.persistent_blocks = P.L.persistent ? persistent_blocks(P.L) : 0;
+  plan.blocks_per_cu = P.L.blocks_per_cu;
+  plan.n_cus = compute_units();
   plan.queues = reinterpret_cast<unsigned int*>(ws + P.Y.queues);
   plan.total_render_blocks = P.Y.total_render_blocks;
   plan.partials = reinterpret_cast<float*>(ws + P.Y.partials);

@@ -15,12 +15,28 @@ struct LaunchPlan {
   int wpb;                  // wavefronts per block
   int dtype;                // storage type shared by all scenes of the call
   int persistent;           // 1: persistent blocks + per-XCD tile queues
-  int persistent_blocks;
+  int blocks_per_cu;        // persistent: resident blocks per compute unit; 0 = the kernel's occupancy limit
+  int n_cus;                // compute units of the device
   unsigned int* queues;     // 8 counters (zeroed before the launch)
   int ckpt_k;               // checkpoint stride shared by all scenes (adjoint)
   int total_render_blocks;  // render: sum of per-scene blocks
   float* partials;          // render: per-block partial loss sums
 };
+
+// Grid of a persistent kernel: blocks_per_cu blocks on every compute unit, or as many as
+// the kernel's registers and LDS let reside at once.
+template <class Kernel>
+inline int persistent_grid(Kernel kernel, const LaunchPlan& P, size_t lds_bytes) {
+  int bpc = P.blocks_per_cu;
+  if (bpc <= 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kernel), 64 * P.wpb,
+                                                     lds_bytes) != hipSuccess || n < 1)
+      n = 1;
+    bpc = n;
+  }
+  return bpc * P.n_cus;
+}
 
 hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream);
 hipError_t launch_render(const LaunchPlan& P, hipStream_t stream);

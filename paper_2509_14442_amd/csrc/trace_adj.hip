@@ -462,7 +462,8 @@ template <int DT, int KS>
 static hipError_t launch_adj_t(const LaunchPlan& P, hipStream_t stream) {
   const size_t lds = sizeof(float) * lds_floats_per_wave<KS>() * (size_t)P.wpb;
   if (P.persistent) {
-    hipLaunchKernelGGL((k_trace_adj_persistent<DT, KS>), dim3(P.persistent_blocks), dim3(64 * P.wpb), lds, stream,
+    const int grid = persistent_grid(k_trace_adj_persistent<DT, KS>, P, lds);
+    hipLaunchKernelGGL((k_trace_adj_persistent<DT, KS>), dim3(grid), dim3(64 * P.wpb), lds, stream,
                        P.scenes, P.n_scenes, P.total_tiles, P.queues);
   } else {
     int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;

@@ -144,25 +144,28 @@ __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __
   }
 }
 
-hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream) {
-  if (P.total_tiles == 0) return hipSuccess;
+template <int DT>
+static hipError_t launch_fwd_t(const LaunchPlan& P, hipStream_t stream) {
+  const dim3 block(64 * P.wpb);
   if (P.persistent) {
-    dim3 grid(P.persistent_blocks), block(64 * P.wpb);
-    switch (P.dtype) {
-      case DT_F32: hipLaunchKernelGGL(k_trace_fwd_persistent<DT_F32>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.queues); break;
-      case DT_F16: hipLaunchKernelGGL(k_trace_fwd_persistent<DT_F16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.queues); break;
-      default: hipLaunchKernelGGL(k_trace_fwd_persistent<DT_BF16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.queues); break;
-    }
+    const dim3 grid(persistent_grid(k_trace_fwd_persistent<DT>, P, 0));
+    hipLaunchKernelGGL(k_trace_fwd_persistent<DT>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles,
+                       P.queues);
   } else {
-    int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
-    dim3 grid(nblocks), block(64 * P.wpb);
-    switch (P.dtype) {
-      case DT_F32: hipLaunchKernelGGL(k_trace_fwd<DT_F32>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb, nblocks); break;
-      case DT_F16: hipLaunchKernelGGL(k_trace_fwd<DT_F16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb, nblocks); break;
-      default: hipLaunchKernelGGL(k_trace_fwd<DT_BF16>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb, nblocks); break;
-    }
+    const int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
+    hipLaunchKernelGGL(k_trace_fwd<DT>, dim3(nblocks), block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb,
+                       nblocks);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream) {
+  if (P.total_tiles == 0) return hipSuccess;
+  switch (P.dtype) {
+    case DT_F32: return launch_fwd_t<DT_F32>(P, stream);
+    case DT_F16: return launch_fwd_t<DT_F16>(P, stream);
+    default: return launch_fwd_t<DT_BF16>(P, stream);
+  }
 }
 
 }  // namespace rbos

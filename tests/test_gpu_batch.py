@@ -106,12 +106,18 @@ def test_autotune_picks_valid_config(tmp_path):
     entry = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"), reps=1,
                           launches=autotune.LAUNCHES[:2] + autotune.LAUNCHES[3:4], strides=(8, 16))
     assert entry["ckpt_stride"] in (8, 16) and entry["ms"] > 0
+    assert {"fwd", "adj"} <= set(entry)
     again = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"))
     assert again == entry  # served from the cache
-    tr = api.Tracer(scenes, autotune.launch_of(entry))
+    tr = api.Tracer(scenes, autotune.launch_of(entry), adjoint_launch=autotune.launch_of(entry, "adj"))
     tr.forward()
     ref = api.Tracer(scenes)
     ref.forward()
+    rng = np.random.default_rng(4)
+    lam = [torch.from_numpy(rng.standard_normal((s.n_rays, 2)).astype(np.float32)).cuda() for s in scenes]
+    g = tr.adjoint(dL_duv=lam)
+    g_ref = ref.adjoint(dL_duv=lam)
     torch.cuda.synchronize()
     for i in range(len(scenes)):
         assert torch.equal(tr.uv[i], ref.uv[i])
+        assert torch.linalg.norm(g[i] - g_ref[i]) <= 1e-5 * torch.linalg.norm(g_ref[i])
