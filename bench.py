@@ -40,7 +40,7 @@ FLOP_ADJ_STEP = 700
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
 
 
-def parse():
+def parse(argv=None):
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
@@ -65,7 +65,18 @@ def parse():
                    help="summary of the FETCH_SIZE / WRITE_SIZE counter runs of the adjoint kernel")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
-    return p.parse_args()
+    return p.parse_args(argv)
+
+
+def launches(args):
+    """(forward launch, adjoint launch) given by the command line."""
+    from paper_2509_14442_amd import api
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    fwd = api.make_launch((tw, th), args.wpb, bool(args.persistent), args.blocks_per_cu)
+    tw, th = (int(x) for x in args.adj_tile.split("x"))
+    adj = api.make_launch((tw, th), args.adj_wpb, bool(args.adj_persistent), args.adj_blocks_per_cu)
+    return fwd, adj
 
 
 # HBM traffic of the adjoint kernel on the default workload, from two rocprofv3 --pmc runs.
@@ -139,10 +150,7 @@ class Workload:
         from paper_2509_14442_amd import api
 
         self.args = args
-        tw, th = (int(x) for x in args.tile.split("x"))
-        launch = api.make_launch((tw, th), args.wpb, bool(args.persistent), args.blocks_per_cu)
-        tw, th = (int(x) for x in args.adj_tile.split("x"))
-        adj_launch = api.make_launch((tw, th), args.adj_wpb, bool(args.adj_persistent), args.adj_blocks_per_cu)
+        launch, adj_launch = launches(args)
         self.temps, self.fields, self.scenes, self.descs = [], [], [], []
         if args.workload in ("room1m", "room256"):
             desc = (bi.scene_room_1m() if args.workload == "room1m" else bi.scene_room_256_3m()).replace(ckpt_stride=args.ckpt)

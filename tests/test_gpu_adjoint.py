@@ -109,3 +109,26 @@ def test_adjoint_against_locked_finite_differences():
     fd = oracle.fd_voxels(F, w.scene, w.pattern32.astype(np.float64), target.astype(np.float64), vox, h=1e-7)
     ref = g.ravel()[vox]
     assert np.allclose(ref, fd, rtol=1e-3, atol=1e-3 * np.abs(g).max()), np.c_[ref, fd]
+
+
+def test_bos_loss_autograd():
+    """torch.autograd through BOSLoss: the loss equals the oracle's and the gradient
+    d(3 L)/d(eta - 1) equals 3 x the tracer's adjoint and the oracle's."""
+    w = unit_box_workload(48, 48)
+    from bos_inputs import plume_unit_box, temperature_grid
+    T2 = temperature_grid(plume_unit_box(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims).astype(np.float32)
+    target = _target(w, T2)
+    d32 = oracle.delta_from_temperature_f32(w.T32)
+    delta = torch.from_numpy(d32.astype(np.float32)).to(DEV).requires_grad_(True)
+    field = api.Field.from_delta(delta.detach(), "f32")
+    sc = api.Scene(w.scene, field, torch.from_numpy(w.pattern32).to(DEV))
+    tr = api.Tracer([sc])
+    tgt = torch.from_numpy(target).to(DEV)
+    L = api.bos_loss(delta, tr, tgt)
+    (3.0 * L).backward()
+    torch.cuda.synchronize()
+    L_ref, dL, g_ref, _ = _oracle_loss_and_grad(w, target)
+    assert float(L) == pytest.approx(L_ref, rel=1e-5)
+    g = _np(delta.grad).astype(np.float64) / 3.0
+    l2, frac = grad_errors(g, g_ref)
+    assert l2 < 1e-3, (l2, frac)
