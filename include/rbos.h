@@ -103,8 +103,9 @@ typedef struct rbos_scene {
   double proj_pos[3], proj_fwd[3], proj_right[3], proj_up[3];  /* projector pinhole */
   double proj_fov_x_deg;
   /* integrator: Sharma RK4 step h in the ray parameter t (at most 4 voxels), step cap
-     (1 .. 65536), checkpoint stride k (0 = no checkpoints; else a multiple of 8 up to
-     256; rbos_trace_adjoint needs k > 0) */
+     (1 .. 65536), checkpoint stride k (0 = no checkpoints; 1 = every step's state is
+     stored and the adjoint reads it instead of replaying: 24 B per ray-step; else a
+     multiple of 8 up to 256, replayed in chunks of 8; rbos_trace_adjoint needs k > 0) */
   double step;
   int32_t max_steps;
   int32_t ckpt_stride;

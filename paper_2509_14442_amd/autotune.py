@@ -29,7 +29,7 @@ LAUNCHES: List[Tuple[Tuple[int, int], int, bool, int]] = [
     ((8, 8), 2, True, 0),
     ((8, 8), 4, True, 2),
 ]
-STRIDES = (8, 16, 32)
+STRIDES = (1, 8, 16, 32)  # 1: every step stored (24 B per ray-step), no replay
 
 
 def _bucket(x: float) -> int:
@@ -46,10 +46,15 @@ def cache_key(scenes: Sequence[api.Scene], mode: str) -> str:
 
 
 def ckpt_bytes(scenes: Sequence[api.Scene], stride: int) -> int:
+    """Checkpoint bytes of the scenes at this stride (as the library sizes them)."""
+    import ctypes as C
+
     tot = 0
     for s in scenes:
-        slots = (s.desc.max_steps - 1) // stride
-        tot += (19 + 6 * slots) * s.n_rays * 4
+        st = C.c_int32(s.struct.ckpt_stride)
+        s.struct.ckpt_stride = stride
+        tot += api.lib().rbos_ckpt_bytes(C.byref(s.struct))
+        s.struct.ckpt_stride = st.value
     return tot
 
 

@@ -107,8 +107,9 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
     return fail(RBOS_E_RANGE, "scene %d: step must be in (0, 4 * smallest voxel]", idx);
   if (S->max_steps < 1 || S->max_steps > (1 << 16))
     return fail(RBOS_E_RANGE, "scene %d: max_steps must be in [1, 65536]", idx);
-  if (S->ckpt_stride != 0 && !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
-    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0 or a multiple of 8 up to 256 (got %d)", idx,
+  if (S->ckpt_stride != 0 && S->ckpt_stride != 1 &&
+      !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
+    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 1 or a multiple of 8 up to 256 (got %d)", idx,
                 S->ckpt_stride);
   if (need_render) {
     if (!S->pattern) return fail(RBOS_E_NULL, "scene %d: pattern is NULL", idx);
@@ -137,6 +138,13 @@ long long tiles_of(const rbos_scene* S, const Launch& L, int* tiles_x) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// entries per checkpoint component: the image in 8 x 8 pixel blocks, or the ray list
+// rounded up to 64
+long long ckpt_entries(const rbos_scene* S) {
+  if (S->pixel_ids) return ((long long)S->n_rays + 63) / 64 * 64;
+  return (long long)((S->width + 7) / 8) * ((S->height + 7) / 8) * 64;
+}
 
 struct Layout {
   size_t table, queues, partials, total;
@@ -233,7 +241,8 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.tiles_x = tx;
   d.n_tiles = (int)nt;
   d.tile_begin = tile_begin;
-  d.ckpt_pad = S->n_rays;
+  d.ckpt_pad = ckpt_entries(S);
+  d.ckpt_tx = (S->width + 7) / 8;
   d.wall_mode = S->wall_mode;
   d.pattern = S->pattern;
   d.pat_w = S->pat_w;
@@ -371,7 +380,7 @@ size_t rbos_ckpt_bytes(const rbos_scene* S) {
   // a per-ray header, then checkpoint slots for steps k, 2k, ... below max_steps
   // (6 floats per ray and slot)
   size_t slots = (size_t)((S->max_steps - 1) / S->ckpt_stride);
-  return (rbos::RAY_HEADER + slots * 6) * (size_t)S->n_rays * sizeof(float);
+  return (rbos::RAY_HEADER + slots * 6) * (size_t)ckpt_entries(S) * sizeof(float);
 }
 
 size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes) {

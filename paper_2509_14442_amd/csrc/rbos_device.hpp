@@ -134,7 +134,8 @@ struct SceneDev {
   df h;                // step in t
   float hf, h_2, h_6, h2_8, h2_2, h2_6;
   int max_steps, ckpt_k, ckpt_slots;
-  long long ckpt_pad;  // rays per checkpoint component (tiles * 64)
+  long long ckpt_pad;  // entries per checkpoint component (a multiple of 64)
+  int ckpt_tx;         // full image: 8 x 8 pixel blocks per image row
   // camera
   df cam_pos[3], cam_fwd[3], cam_right[3], cam_up[3];
   df cam_ax;           // tan(fov_x / 2) / width
@@ -206,6 +207,15 @@ __device__ __forceinline__ int find_scene(const SceneDev* scenes, int n_scenes, 
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Entry of ray r (pixel pix) in every checkpoint component: the image in 8 x 8 pixel
+// blocks, row-major over blocks and within a block, so the 64 rays of an 8 x 8 tile read
+// and write one contiguous 256-byte run; with a pixel-id list, r itself.
+__device__ __forceinline__ int ckpt_entry(const SceneDev& S, int r, int pix) {
+  if (S.pixel_ids) return r;
+  const int row = pix / S.width, col = pix - row * S.width;
+  return (((row >> 3) * S.ckpt_tx + (col >> 3)) << 6) + ((row & 7) << 3) + (col & 7);
 }
 
 // ray index r and pixel of lane `lane` in scene tile `tile`; false if none

@@ -244,6 +244,7 @@ template <int DT, int KS>
 __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int lane, float* __restrict__ replay) {
   int r = 0, pix = 0;
   const bool valid = tile_ray(S, tile, lane, r, pix);
+  const int q = valid ? ckpt_entry(S, r, pix) : 0;  // checkpoint entry
   int n = 0;
   bool active = false;
   RayBase B;
@@ -257,7 +258,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
       // wall step X = x + s v: lambda_x = lambda_X - n (v . lambda_X)/(v . n),
       // lambda_v = s lambda_x (metres); grid units multiply by the voxel size
       float e_end[3], s;
-      load_ray_header(S, r, B, e_end, s);
+      load_ray_header(S, q, B, e_end, s);
       float v[3], lX[3], vn = 0.0f, vl = 0.0f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -275,9 +276,13 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
       }
     }
   }
+  // Stride 1: every step's start state is in the checkpoints and a chunk is filled from
+  // them; otherwise a segment of K steps is replayed from its checkpoint in chunks.
   const int K = S.ckpt_k;
-  const int m_chunks = K / KS;
-  const int nseg_lane = active ? (n + K - 1) / K : 0;
+  const bool stored = K == 1;
+  const int seg_len = stored ? KS : K;
+  const int m_chunks = seg_len / KS;
+  const int nseg_lane = active ? (n + seg_len - 1) / seg_len : 0;
   const int nseg = wave_max_nonneg(nseg_lane);
 
   Accum A;
@@ -289,9 +294,30 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
     for (int ch = m_chunks - 1; ch >= 0; --ch) {
-      const int c0 = seg * K + ch * KS;  // first step of the chunk
+      const int c0 = seg * seg_len + ch * KS;  // first step of the chunk
       const bool lane_chunk = active && c0 < n;
-      if (lane_chunk) {
+      if (lane_chunk && stored) {
+        // step j starts from slot j - 1 (zero deviation at j = 0); all loads first
+        float v[KS][6];
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+          const int j = c0 + i;
+          State st;
+          if (j >= 1 && j < n) {
+            load_ckpt(S, q, j - 1, st);
+          } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
+          }
+#pragma unroll
+          for (int a = 0; a < 3; ++a) { v[i][a] = st.d[a]; v[i][3 + a] = st.e[a]; }
+        }
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) replay[(i * 6 + c) * 64 + lane] = v[i][c];
+        }
+      } else if (lane_chunk) {
         State st;
         Cell C;
         state_at_step(B, seg * K, st);
@@ -299,7 +325,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll
           for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
         } else {
-          load_ckpt(S, r, seg - 1, st);
+          load_ckpt(S, q, seg - 1, st);
         }
         locate_state(S, B, st, C);
 #pragma unroll 1

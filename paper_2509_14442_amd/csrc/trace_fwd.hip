@@ -6,8 +6,9 @@
 namespace rbos {
 
 // Trace one ray; writes its outputs. With checkpoints the buffer holds, component-major
-// (component c of ray r at [c * n_rays + r]): the ray header (see store_ray_header), then
-// the states (d, e) before steps k, 2k, ... (6 components per slot).
+// (component c of the ray at [c * ckpt_pad + ckpt_entry]): the ray header (see
+// store_ray_header), then the states (d, e) before steps k, 2k, ... (6 components per
+// slot).
 template <int DT>
 __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   int n = 0;
@@ -38,20 +39,25 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
     state_at_step(B, 0, st);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
-    const int K = S.ckpt_k;
-    float* ck = S.ckpt ? S.ckpt + (size_t)RAY_HEADER * S.ckpt_pad + (size_t)r : nullptr;
+    // checkpoint slot s holds the state after (s + 1) K steps; kc counts down to the next
+    const int q = ckpt_entry(S, r, pix);
+    float* ck = S.ckpt ? S.ckpt + (size_t)RAY_HEADER * S.ckpt_pad + (size_t)q : nullptr;
+    const size_t slot_stride = 6 * (size_t)S.ckpt_pad;
+    int kc = S.ckpt_k;
     bool exited = false;
     while (n < S.max_steps) {
-      if (ck && n > 0 && (n % K) == 0) {
-        size_t base = (size_t)(n / K - 1) * 6 * (size_t)S.ckpt_pad;
+      if (ck && kc == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          gst(ck + base + (size_t)a * S.ckpt_pad, st.d[a]);
-          gst(ck + base + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
+          gst(ck + (size_t)a * S.ckpt_pad, st.d[a]);
+          gst(ck + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
         }
+        ck += slot_stride;
+        kc = S.ckpt_k;
       }
       sharma_step<DT>(S, B, st, C);
       ++n;
+      --kc;
       if (!state_finite(st)) {
         status |= RAY_NONFINITE;
         exited = true;
@@ -66,7 +72,7 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
     if (!(status & RAY_NONFINITE)) {
       float dX[3], s = 0.0f;
       const bool hit = wall_deflection(S, B, st, dX, &s);
-      if (ck) store_ray_header(S, r, B, st, s);
+      if (ck) store_ray_header(S, ckpt_entry(S, r, pix), B, st, s);
       if (hit) {
         uvd[0] = dX[0] * S.wall_u_f[0] + dX[1] * S.wall_u_f[1] + dX[2] * S.wall_u_f[2];
         uvd[1] = dX[0] * S.wall_v_f[0] + dX[1] * S.wall_v_f[1] + dX[2] * S.wall_v_f[2];

@@ -93,6 +93,7 @@ def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
     (lambda s: setattr(s, "step", 1.0), -3),
     (lambda s: setattr(s, "max_steps", 0), -3),
     (lambda s: setattr(s, "ckpt_stride", 12), -7),
+    (lambda s: setattr(s, "ckpt_stride", 4), -7),
     (lambda s: setattr(s, "ckpt_stride", 264), -7),
 ])
 def test_forward_validation(lib, mutate, code):
@@ -154,8 +155,16 @@ def test_field_validation_and_sizes(lib):
                                            C.c_void_p(0x20), None) == -3
     assert lib.rbos_field_encode(4, 4, 4, C.c_void_p(0x10), 3, 1.0, 0.0, C.c_void_p(0x20), None) == -4
     s = _valid_scene()
-    # a 19-float ray header plus 6 floats per checkpoint slot, per ray
-    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + ((64 - 1) // 16) * 6) * 16 * 4
+    # a 19-float ray header plus 6 floats per checkpoint slot, per entry: the image in
+    # 8 x 8 pixel blocks (4 x 4 pixels: one block of 64 entries)
+    assert (s.width, s.height, s.pixel_ids) == (4, 4, None)
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + ((64 - 1) // 16) * 6) * 64 * 4
+    s.ckpt_stride = 1  # every step's state
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 64 * 4
+    s.width, s.height, s.n_rays = 17, 9, 17 * 9  # 3 x 2 blocks
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 6 * 64 * 4
+    s.pixel_ids, s.n_rays = 0x40, 65  # ray list: 65 -> 128 entries
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 128 * 4
     s.ckpt_stride = 0
     assert lib.rbos_ckpt_bytes(C.byref(s)) == 0
     assert lib.rbos_workspace_bytes(C.byref(s), 1) >= 256
