@@ -207,10 +207,6 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.P01 = (S->nx + 1) * (S->ny + 1);
   d.dtype = S->dtype;
   d.field = S->field;
-  {
-    const size_t rec = S->dtype == RBOS_F32 ? 32 : 16;
-    d.cell0 = static_cast<const unsigned char*>(S->field) + rec * (size_t)(1 + d.P0 + d.P01);
-  }
   d.dec = (float)dec;
   d.inv_dec = (float)scale;
   d.off = (float)S->enc_offset;

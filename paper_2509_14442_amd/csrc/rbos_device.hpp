@@ -117,8 +117,7 @@ struct SceneDev {
   int n[3];            // voxels per axis
   int P0, P01;         // record strides of the padded cell grid: (nx+1), (nx+1)(ny+1)
   int dtype;
-  const void* field;   // cell records
-  const void* cell0;   // record of cell (0, 0, 0); cells -1 .. n-1 exist on every axis
+  const void* field;   // cell records, starting with cell (-1, -1, -1); cells -1 .. n-1 on every axis
   float dec;           // 1 / enc_scale
   float inv_dec;       // enc_scale
   float one_plus_off;  // 1 + enc_offset (binary32)
@@ -315,14 +314,17 @@ __device__ __forceinline__ void setup_ray(const SceneDev& S, int pix, Ray& R) {
 // FP32: 8 floats (32 B). FP16/BF16: 8 x 16-bit (16 B), two per 32-bit word.
 // `cell` is relative to the record of cell (0, 0, 0) and may be negative.
 template <int DT>
-__device__ __forceinline__ void fetch_cell(const void* __restrict__ cell0, int cell, float c[8]) {
+__device__ __forceinline__ void fetch_cell(const void* __restrict__ field, unsigned int rec, float c[8]) {
+  // 32-bit byte offset from the array start (at most 449^3 records of 32 B < 4 GiB), so
+  // the load takes the array base from SGPRs and the offset from one VGPR
+  const unsigned char* base = static_cast<const unsigned char*>(field);
   if constexpr (DT == DT_F32) {
-    const f32x4* p = reinterpret_cast<const f32x4*>(cell0) + 2 * (ptrdiff_t)cell;
+    const f32x4* p = reinterpret_cast<const f32x4*>(base + (rec << 5));
     const f32x4 a = gld(p), b = gld(p + 1);
     c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
     c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
   } else {
-    const u32x4 w = gld(reinterpret_cast<const u32x4*>(cell0) + (ptrdiff_t)cell);
+    const u32x4 w = gld(reinterpret_cast<const u32x4*>(base + (rec << 4)));
     unsigned int v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -342,28 +344,31 @@ __device__ __forceinline__ void fetch_cell(const void* __restrict__ cell0, int c
 // exact, so f carries one rounding (~3e-8 voxel). The index is clamped to [-1, n-1]:
 // apron cells repeat the edge voxels, so there the field is constant along the axis
 // (edge value, zero derivative) for any f -- clamp-to-edge with half-open cells.
-__device__ __forceinline__ void locate(float bhi, float small, int n, int& i, float& f) {
+// Returns the cell's padded index p = i + 1 in [0, n] (cell i in [-1, n-1]).
+__device__ __forceinline__ void locate(float bhi, float small, int n, int& p, float& f) {
   float fl = floorf(bhi);
   float ff = (bhi - fl) + small;
   float t = floorf(ff);
   f = ff - t;
-  int ii = (int)(fl + t);
-  i = min(max(ii, -1), n - 1);
+  int pp = (int)((fl + t) + 1.0f);  // integers well below 2^24: exact
+  p = min(max(pp, 0), n);
 }
 
 struct Cell {
-  int i[3];
-  float f[3];
+  int p[3];    // padded cell index i + 1 per axis, 0 .. n
+  float f[3];  // fraction within the cell
 };
 
 __device__ __forceinline__ void locate3(const SceneDev& S, const float bhi[3], const float small[3], Cell& C) {
-  locate(bhi[0], small[0], S.n[0], C.i[0], C.f[0]);
-  locate(bhi[1], small[1], S.n[1], C.i[1], C.f[1]);
-  locate(bhi[2], small[2], S.n[2], C.i[2], C.f[2]);
+  locate(bhi[0], small[0], S.n[0], C.p[0], C.f[0]);
+  locate(bhi[1], small[1], S.n[1], C.p[1], C.f[1]);
+  locate(bhi[2], small[2], S.n[2], C.p[2], C.f[2]);
 }
 
-__device__ __forceinline__ int cell_index(const SceneDev& S, const Cell& C) {
-  return C.i[0] + S.P0 * C.i[1] + S.P01 * C.i[2];
+// record of cell C counted from the array start (cell (-1, -1, -1)); 24-bit multiplies
+// (full rate) suffice: indices <= 448, strides <= 449^2
+__device__ __forceinline__ unsigned int cell_index(const SceneDev& S, const Cell& C) {
+  return (unsigned)C.p[0] + __umul24((unsigned)C.p[1], (unsigned)S.P0) + __umul24((unsigned)C.p[2], (unsigned)S.P01);
 }
 
 // Trilinear value q and its grid-unit gradient from the 8 corners.
@@ -404,7 +409,7 @@ __device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], 
 template <int DT>
 __device__ __forceinline__ void force_at(const SceneDev& S, const Cell& C, float K[3]) {
   float c[8];
-  fetch_cell<DT>(S.cell0, cell_index(S, C), c);
+  fetch_cell<DT>(S.field, cell_index(S, C), c);
   float q, g[3];
   trilinear(c, C.f, q, g);
   float eta = fmaf(q, S.dec, S.one_plus_off);
@@ -439,7 +444,7 @@ __device__ __forceinline__ void make_base(const SceneDev& S, const Ray& R, RayBa
   }
   locate3(S, bh, small, C0);
   float c[8];
-  fetch_cell<DT>(S.cell0, cell_index(S, C0), c);
+  fetch_cell<DT>(S.field, cell_index(S, C0), c);
   float q, g[3];
   trilinear(c, C0.f, q, g);
   float delta = fmaf(q, S.dec, S.off);

@@ -27,7 +27,7 @@ struct SampleRev {
 template <int DT>
 __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, SampleRev& R) {
   float c[8];
-  fetch_cell<DT>(S.cell0, cell_index(S, C), c);
+  fetch_cell<DT>(S.field, cell_index(S, C), c);
   float q;
   trilinear_h(c, C.f, q, R.g, R.H);
   R.eta = fmaf(q, S.dec, S.one_plus_off);
@@ -79,7 +79,7 @@ struct Accum {
 };
 
 __device__ __forceinline__ int cell_key(const Cell& C) {
-  return ((C.i[2] + 1) << 20) | ((C.i[1] + 1) << 10) | (C.i[0] + 1);
+  return (C.p[2] << 20) | (C.p[1] << 10) | C.p[0];
 }
 
 // Sum 8 per-lane values over the 64 lanes, all eight at once: each exchange step halves
@@ -240,7 +240,7 @@ __device__ __forceinline__ void locate_state(const SceneDev& S, const RayBase& B
 template <int KS>
 constexpr int lds_floats_per_wave() { return KS * 6 * 64 + PEND_SLOTS * 8; }
 
-template <int DT, int KS>
+template <int DT, int KS, bool STORED>
 __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int lane, float* __restrict__ replay) {
   int r = 0, pix = 0;
   const bool valid = tile_ray(S, tile, lane, r, pix);
@@ -276,11 +276,11 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
       }
     }
   }
-  // Stride 1: every step's start state is in the checkpoints and a chunk is filled from
-  // them; otherwise a segment of K steps is replayed from its checkpoint in chunks.
+  // STORED (stride 1): every step's start state is in the checkpoints and a chunk is
+  // filled from them; otherwise a segment of K steps is replayed from its checkpoint in
+  // chunks.
   const int K = S.ckpt_k;
-  const bool stored = K == 1;
-  const int seg_len = stored ? KS : K;
+  const int seg_len = STORED ? KS : K;
   const int m_chunks = seg_len / KS;
   const int nseg_lane = active ? (n + seg_len - 1) / seg_len : 0;
   const int nseg = wave_max_nonneg(nseg_lane);
@@ -296,7 +296,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
     for (int ch = m_chunks - 1; ch >= 0; --ch) {
       const int c0 = seg * seg_len + ch * KS;  // first step of the chunk
       const bool lane_chunk = active && c0 < n;
-      if (lane_chunk && stored) {
+      if (STORED && lane_chunk) {
         // step j starts from slot j - 1 (zero deviation at j = 0); all loads first
         float v[KS][6];
 #pragma unroll
@@ -317,7 +317,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll
           for (int c = 0; c < 6; ++c) replay[(i * 6 + c) * 64 + lane] = v[i][c];
         }
-      } else if (lane_chunk) {
+      } else if (!STORED && lane_chunk) {
         State st;
         Cell C;
         state_at_step(B, seg * K, st);
@@ -449,21 +449,21 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   if (P.occupied) write_out(S, P, P.occupied, lane);
 }
 
-template <int DT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj(const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles,
-                                                   int wpb, int nblocks) {
+template <int DT, int KS, bool STORED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj(
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, int wpb, int nblocks) {
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
   if (gtile >= total_tiles) return;  // whole wavefront
   const int si = find_scene(scenes, n_scenes, gtile);
   const SceneDev& S = scenes[si];
   extern __shared__ float lds[];
-  adjoint_tile<DT, KS>(S, gtile - S.tile_begin, lane, lds + wave * lds_floats_per_wave<KS>());
+  adjoint_tile<DT, KS, STORED>(S, gtile - S.tile_begin, lane, lds + wave * lds_floats_per_wave<KS>());
 }
 
-template <int DT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
-                                                              int total_tiles, unsigned int* __restrict__ queues) {
+template <int DT, int KS, bool STORED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj_persistent(
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, unsigned int* __restrict__ queues) {
   const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   const int xcd = blockIdx.x & 7;
   extern __shared__ float lds[];
@@ -479,33 +479,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (t >= q_end) break;
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];
-      adjoint_tile<DT, KS>(S, t - S.tile_begin, lane, replay);
+      adjoint_tile<DT, KS, STORED>(S, t - S.tile_begin, lane, replay);
     }
   }
 }
 
-template <int DT, int KS>
+template <int DT, int KS, bool STORED>
 static hipError_t launch_adj_t(const LaunchPlan& P, hipStream_t stream) {
   const size_t lds = sizeof(float) * lds_floats_per_wave<KS>() * (size_t)P.wpb;
   if (P.persistent) {
-    const int grid = persistent_grid(k_trace_adj_persistent<DT, KS>, P, lds);
-    hipLaunchKernelGGL((k_trace_adj_persistent<DT, KS>), dim3(grid), dim3(64 * P.wpb), lds, stream,
+    const int grid = persistent_grid(k_trace_adj_persistent<DT, KS, STORED>, P, lds);
+    hipLaunchKernelGGL((k_trace_adj_persistent<DT, KS, STORED>), dim3(grid), dim3(64 * P.wpb), lds, stream,
                        P.scenes, P.n_scenes, P.total_tiles, P.queues);
   } else {
     int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
-    hipLaunchKernelGGL((k_trace_adj<DT, KS>), dim3(nblocks), dim3(64 * P.wpb), lds, stream, P.scenes, P.n_scenes,
-                       P.total_tiles, P.wpb, nblocks);
+    hipLaunchKernelGGL((k_trace_adj<DT, KS, STORED>), dim3(nblocks), dim3(64 * P.wpb), lds, stream, P.scenes,
+                       P.n_scenes, P.total_tiles, P.wpb, nblocks);
   }
   return hipGetLastError();
 }
 
+template <int DT>
+static hipError_t launch_adj_dt(const LaunchPlan& P, hipStream_t stream) {
+  // chunks of 8 step-start states in LDS: stride 1 fills them from the checkpoints,
+  // strides 8, 16, ... replay them
+  return P.ckpt_k == 1 ? launch_adj_t<DT, 8, true>(P, stream) : launch_adj_t<DT, 8, false>(P, stream);
+}
+
 hipError_t launch_trace_adj(const LaunchPlan& P, hipStream_t stream) {
   if (P.total_tiles == 0) return hipSuccess;
-  // LDS chunk of 8 step-start states; strides 16, 32, ... replay in chunks of 8
   switch (P.dtype) {
-    case DT_F32: return launch_adj_t<DT_F32, 8>(P, stream);
-    case DT_F16: return launch_adj_t<DT_F16, 8>(P, stream);
-    default: return launch_adj_t<DT_BF16, 8>(P, stream);
+    case DT_F32: return launch_adj_dt<DT_F32>(P, stream);
+    case DT_F16: return launch_adj_dt<DT_F16>(P, stream);
+    default: return launch_adj_dt<DT_BF16>(P, stream);
   }
 }
 
