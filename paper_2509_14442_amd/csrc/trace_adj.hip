@@ -344,7 +344,10 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll 1
       for (int i = KS - 1; i >= 0; --i) {
         const bool act = lane_chunk && (c0 + i < n);
-        Cell Q1, Q2;
+        // the samples of stages A and B: their forces K1, K2 locate P2 and P3 (the same
+        // arithmetic as the forward's), their derivatives serve the reverse of the stage
+        SampleRev R1, R2;
+        Cell Q1;
         float ab[3], bb[3], rs[3], ts[3], ct[8];
         int key = 0;
         if (act) {
@@ -359,14 +362,19 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           float K1[3], K2[3], bh[3], sm[3];
           locate_state(S, B, s, Q1);
-          force_at<DT>(S, Q1, K1);
+          sample_rev<DT>(S, Q1, R1);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) K1[a] = R1.eta * (R1.g[a] * S.km[a]);  // as force_at
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             bh[a] = s.bh[a] + B.g2hi[a];
             sm[a] = small_part(B, a, s.jf + 1.0f, s.d[a] + fmaf(h_2, s.e[a], h2_8 * K1[a]));
           }
+          Cell Q2;
           locate3(S, bh, sm, Q2);
-          force_at<DT>(S, Q2, K2);
+          sample_rev<DT>(S, Q2, R2);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) K2[a] = R2.eta * (R2.g[a] * S.km[a]);  // as force_at
           Cell Q3;
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -395,8 +403,6 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
-          SampleRev R2;
-          sample_rev<DT>(S, Q2, R2);
           float v[3], p[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) v[a] = h * bb[a];
@@ -407,12 +413,10 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rs[a] += p[a];
             ts[a] = fmaf(h_2, p[a], ts[a]);
           }
-          key = cell_key(Q2);
+          key = cell_key(R2.C);
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
-          SampleRev R1;
-          sample_rev<DT>(S, Q1, R1);
           float v[3], p[3];
 #pragma unroll
           for (int a = 0; a < 3; ++a) v[a] = h * ab[a];
@@ -422,7 +426,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rb[a] = rs[a] + p[a];
             tb[a] = ts[a];
           }
-          key = cell_key(Q1);
+          key = cell_key(R1.C);
         }
         accumulate(S, A, act, key, ct, lane, P);
       }
