@@ -182,7 +182,8 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
     d.km[a] = (float)(dec / (vox * vox));
     d.vox[a] = (float)vox;
     d.lo_f[a] = (float)S->box_lo[a];
-    d.hi_bound[a] = (float)n[a] - 0.5f;
+    d.hi_bound[a] = (float)n[a] + 0.5f;
+    d.n_f[a] = (float)n[a];
     d.lo[a] = to_df(S->box_lo[a]);
     d.hi[a] = to_df(S->box_hi[a]);
     d.inv_vox[a] = to_df(1.0 / vox);

@@ -125,7 +125,8 @@ struct SceneDev {
   float km[3];         // dec / voxel^2: force factor in grid units
   float vox[3];        // voxel size (m)
   float lo_f[3];       // box lo (m)
-  float hi_bound[3];   // n - 1/2: box faces in grid units are -1/2 and n - 1/2
+  float hi_bound[3];   // n + 1/2: box faces in grid units are 1/2 and n + 1/2
+  float n_f[3];        // n (binary32)
   df lo[3];            // box lo (m)
   df hi[3];            // box hi (m)
   df inv_vox[3];       // 1 / voxel size
@@ -240,7 +241,7 @@ __device__ __forceinline__ bool tile_ray(const SceneDev& S, int tile, int lane, 
 struct Ray {
   df dir[3];     // unit camera ray direction
   bool entered;  // meets the field box
-  df U0[3];      // box entry point in grid units, u = (x - lo)/voxel - 1/2
+  df U0[3];      // box entry point in grid units, u = (x - lo)/voxel + 1/2
   bool wall0;    // the undeflected camera ray hits the wall
   df uv0[2];     // its wall coordinates
 };
@@ -301,7 +302,7 @@ __device__ __forceinline__ void setup_ray(const SceneDev& S, int pix, Ray& R) {
   if (R.entered) {
     for (int a = 0; a < 3; ++a) {
       df x = dd_add(S.cam_pos[a], dd_mul(t_in, R.dir[a]));
-      R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), -0.5f);
+      R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), 0.5f);
     }
   }
 }
@@ -345,19 +346,20 @@ __device__ __forceinline__ void fetch_cell(const void* __restrict__ field, unsig
   }
 }
 
-// Locate one axis: the point is (bhi + small) grid units with bhi exact. The cell is
-// i = floor(u) and f = u - i, computed without rounding u itself: bhi - floor(bhi) is
-// exact, so f carries one rounding (~3e-8 voxel). The index is clamped to [-1, n-1]:
-// apron cells repeat the edge voxels, so there the field is constant along the axis
-// (edge value, zero derivative) for any f -- clamp-to-edge with half-open cells.
-// Returns the cell's padded index p = i + 1 in [0, n] (cell i in [-1, n-1]).
-__device__ __forceinline__ void locate(float bhi, float small, int n, int& p, float& f) {
-  float fl = floorf(bhi);
-  float ff = (bhi - fl) + small;
-  float t = floorf(ff);
+// Locate one axis: the point is u = bhi + small grid units (grid units count from one
+// cell below the first voxel centre: u = (x - lo) / voxel + 1/2), with bhi exact. The
+// padded cell index is p = floor(u) (cell i = p - 1 between centres i and i + 1) and
+// f = u - p, computed without rounding u itself: bhi - floor(bhi) is exact, so f carries
+// one rounding (~3e-8 voxel). p is clamped to [0, n]: the apron cells 0 and n repeat
+// the edge voxels, so there the field is constant along the axis (edge value, zero
+// derivative) for any f -- clamp-to-edge with half-open cells.
+__device__ __forceinline__ void locate(float bhi, float small, float n_f, int& p, float& f) {
+  const float fl = floorf(bhi);
+  const float ff = (bhi - fl) + small;
+  const float t = floorf(ff);
   f = ff - t;
-  int pp = (int)((fl + t) + 1.0f);  // integers well below 2^24: exact
-  p = min(max(pp, 0), n);
+  // integers far below 2^24 (or a non-finite position, mapped into [0, n])
+  p = (int)__builtin_amdgcn_fmed3f(fl + t, 0.0f, n_f);
 }
 
 struct Cell {
@@ -366,9 +368,9 @@ struct Cell {
 };
 
 __device__ __forceinline__ void locate3(const SceneDev& S, const float bhi[3], const float small[3], Cell& C) {
-  locate(bhi[0], small[0], S.n[0], C.p[0], C.f[0]);
-  locate(bhi[1], small[1], S.n[1], C.p[1], C.f[1]);
-  locate(bhi[2], small[2], S.n[2], C.p[2], C.f[2]);
+  locate(bhi[0], small[0], S.n_f[0], C.p[0], C.f[0]);
+  locate(bhi[1], small[1], S.n_f[1], C.p[1], C.f[1]);
+  locate(bhi[2], small[2], S.n_f[2], C.p[2], C.f[2]);
 }
 
 // record of cell C counted from the array start (cell (-1, -1, -1)); 24-bit multiplies
@@ -526,8 +528,8 @@ __device__ __forceinline__ bool outside_box(const SceneDev& S, const RayBase& B,
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float sm = small_part(B, a, st.jf, st.d[a]);
-    float lo_gap = (st.bh[a] + 0.5f) + sm;            // u + 1/2, first term exact
-    float hi_gap = (st.bh[a] - S.hi_bound[a]) + sm;   // u - (n - 1/2), first term exact
+    float lo_gap = (st.bh[a] - 0.5f) + sm;            // u - 1/2, first term exact
+    float hi_gap = (st.bh[a] - S.hi_bound[a]) + sm;   // u - (n + 1/2), first term exact
     inside = inside && (lo_gap >= 0.0f) && (hi_gap <= 0.0f);
   }
   return !inside;
@@ -552,7 +554,7 @@ __device__ __forceinline__ bool wall_deflection(const SceneDev& S, const RayBase
     dm[a] = st.d[a] * S.vox[a];
     em[a] = st.e[a] * S.vox[a];
     float u = st.bh[a] + fmaf(st.jf, B.g2lo[a], B.U0lo[a]);
-    Rb[a] = S.lo_f[a] + (u + 0.5f) * S.vox[a];
+    Rb[a] = S.lo_f[a] + (u - 0.5f) * S.vox[a];
     b += B.V[a] * S.wall_n_f[a];
     dn += dm[a] * S.wall_n_f[a];
     en += em[a] * S.wall_n_f[a];

@@ -27,7 +27,7 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         df x = dd_add(S.cam_pos[a], dd_mul(t_in, R.dir[a]));
-        R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), -0.5f);
+        R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), 0.5f);
       }
       make_base<DT>(S, R, B, C);
     }
