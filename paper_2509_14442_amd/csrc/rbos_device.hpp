@@ -535,10 +535,10 @@ __device__ __forceinline__ bool outside_box(const SceneDev& S, const RayBase& B,
   return !inside;
 }
 
+// A non-finite component makes the sum non-finite (inf - inf is NaN); the deviations
+// stay within a few hundred grid units, so the sum of finite ones cannot overflow.
 __device__ __forceinline__ bool state_finite(const State& st) {
-  float s = st.d[0] + st.d[1] + st.d[2] + st.e[0] + st.e[1] + st.e[2];
-  return isfinite(s) && isfinite(st.d[0]) && isfinite(st.d[1]) && isfinite(st.d[2]) && isfinite(st.e[0]) &&
-         isfinite(st.e[1]) && isfinite(st.e[2]);
+  return isfinite(((st.d[0] + st.d[1]) + (st.d[2] + st.e[0])) + (st.e[1] + st.e[2]));
 }
 
 // Deviation of the wall hit from the undeflected hit, from the last state:
