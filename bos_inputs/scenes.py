@@ -57,6 +57,7 @@ class Scene:
     step: float = 0.0  # RK4 step h in the ray parameter t (metres)
     max_steps: int = 512
     ckpt_stride: int = 16
+    tracer: int = 0  # 0: nonlinear (Eq. 1 coupled), 1: quasi-linear (forces on the entry line)
     name: str = ""
 
     @property

@@ -303,6 +303,61 @@ static void sharma_step(const or_field* F, double h, const double* x, const doub
     for (int k = 0; k < 3; ++k) locks[k] = st->s[k].cell;
 }
 
+/* Quasi-linear form (Sec. 2.B): the path is approximated by the straight line
+   L(t) = x0 + v0 t from the entry state; the field is queried on L to give the
+   approximate velocity, which then drives the position. The same update as above, with
+   the force taken on L at the stage times:
+     A = h D(L(t)),  B = h D(L(t + h/2)),  C = h D(L(t + h)),
+     x <- x + h (v + (A + 2B)/6),  v <- v + (A + 4B + C)/6.
+   (With the force a function of t alone, the update is Simpson's rule for v and exact
+   for cubic forcing.) */
+static void quasi_step(const or_field* F, double h, const double* x0, const double* v0, double t,
+                       const double* x, const double* v, cell_t* locks, int use_locks, double* x_new,
+                       double* v_new, stages_t* st) {
+  stages_t local;
+  if (!st) st = &local;
+  const double ts[3] = {t, t + 0.5 * h, t + h};
+  double D[3];
+  for (int k = 0; k < 3; ++k) {
+    for (int i = 0; i < 3; ++i) st->P[k][i] = x0[i] + ts[k] * v0[i];
+    sample_field(F, st->P[k], use_locks ? &locks[k] : NULL, &st->s[k]);
+    force(&st->s[k], D);
+    for (int i = 0; i < 3; ++i) st->K[k][i] = h * D[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    x_new[i] = x[i] + h * (v[i] + (st->K[0][i] + 2.0 * st->K[1][i]) / 6.0);
+    v_new[i] = v[i] + (st->K[0][i] + 4.0 * st->K[1][i] + st->K[2][i]) / 6.0;
+  }
+  if (locks && !use_locks)
+    for (int k = 0; k < 3; ++k) locks[k] = st->s[k].cell;
+}
+
+/* Step n of a ray that entered at (x0, v0), in the scene's tracer form. */
+static void ray_step(const or_field* F, const or_scene* S, const double* x0, const double* v0, int n,
+                     const double* x, const double* v, cell_t* locks, int use_locks, double* x_new,
+                     double* v_new, stages_t* st) {
+  if (S->tracer == OR_TRACER_QUASILINEAR)
+    quasi_step(F, S->step, x0, v0, n * S->step, x, v, locks, use_locks, x_new, v_new, st);
+  else
+    sharma_step(F, S->step, x, v, locks, use_locks, x_new, v_new, st);
+}
+
+int or_integrate_quasi(const or_field* F, const double* x0, const double* v0, double h, int32_t nsteps,
+                       double* x_out, double* v_out) {
+  if (!F || !x0 || !v0 || !x_out || !v_out || nsteps < 0) return -1;
+  double x[3], v[3], xn[3], vn[3];
+  memcpy(x, x0, sizeof x);
+  memcpy(v, v0, sizeof v);
+  for (int n = 0; n < nsteps; ++n) {
+    quasi_step(F, h, x0, v0, n * h, x, v, NULL, 0, xn, vn, NULL);
+    memcpy(x, xn, sizeof x);
+    memcpy(v, vn, sizeof v);
+  }
+  memcpy(x_out, x, sizeof x);
+  memcpy(v_out, v, sizeof v);
+  return 0;
+}
+
 int or_integrate(const or_field* F, const double* x0, const double* v0, double h, int32_t nsteps,
                  double* x_out, double* v_out) {
   if (!F || !x0 || !v0 || !x_out || !v_out || nsteps < 0) return -1;
@@ -507,12 +562,15 @@ static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, tape_t*
     if (tp && !locked) tp->cells[0] = s0.cell;
     for (int i = 0; i < 3; ++i) v[i] = (1.0 + s0.delta) * dir[i];
     if (tp) { memcpy(tp->x0, x, sizeof x); memcpy(&tp->x[0], x, sizeof x); memcpy(&tp->v[0], v, sizeof v); }
+    double x_in[3], v_in[3];
+    memcpy(x_in, x, sizeof x);
+    memcpy(v_in, v, sizeof v);
     int n_run = locked ? tp->n_steps : S->max_steps;
     int n = 0;
     for (; n < n_run; ++n) {
       double xn[3], vn[3];
       cell_t* lk = tp ? &tp->cells[1 + 3 * n] : NULL;
-      sharma_step(F, S->step, x, v, lk, locked, xn, vn, NULL);
+      ray_step(F, S, x_in, v_in, n, x, v, lk, locked, xn, vn, NULL);
       memcpy(x, xn, sizeof x);
       memcpy(v, vn, sizeof v);
       if (tp) { memcpy(&tp->x[3 * (n + 1)], x, sizeof x); memcpy(&tp->v[3 * (n + 1)], v, sizeof v); }
@@ -655,11 +713,15 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, const
     r[i] = lX[i] - S->wall_normal[i] * vl / vn;
     tau[i] = s * r[i];
   }
+  const int quasi = S->tracer == OR_TRACER_QUASILINEAR;
+  const double* x0 = &tp->x[0];
+  const double* v0 = &tp->v[0];
+  double lv0[3] = {0.0, 0.0, 0.0}; /* quasi-linear: dL/dv0 through the stage points on L */
   /* Sharma steps in reverse */
   for (int n = N - 1; n >= 0; --n) {
     stages_t st;
     double xn[3], vn2[3];
-    sharma_step(F, h, &tp->x[3 * n], &tp->v[3 * n], &tp->cells[1 + 3 * n], 1, xn, vn2, &st);
+    ray_step(F, S, x0, v0, n, &tp->x[3 * n], &tp->v[3 * n], &tp->cells[1 + 3 * n], 1, xn, vn2, &st);
     double abar[3], bbar[3], cbar[3], rbar[3], tbar[3];
     for (int i = 0; i < 3; ++i) {
       abar[i] = h / 6.0 * r[i] + tau[i] / 6.0;
@@ -669,6 +731,21 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, const
       tbar[i] = h * r[i] + tau[i];
     }
     double J[3][3], p[3];
+    if (quasi) {
+      /* stage points P_k = x0 + t_k v0 do not depend on the state: each stage adds its
+         corner derivatives and t_k h J(P_k) bar_k to dL/dv0 */
+      const double ts[3] = {n * h, n * h + 0.5 * h, n * h + h};
+      const double* bars[3] = {abar, bbar, cbar};
+      for (int k = 2; k >= 0; --k) {
+        force_jacobian(&st.s[k], J);
+        matvec3(J, bars[k], p);
+        scatter_force(F, &st.s[k], bars[k], h, g);
+        axpy3(lv0, ts[k] * h, p);
+      }
+      memcpy(r, rbar, sizeof r);
+      memcpy(tau, tbar, sizeof tau);
+      continue;
+    }
     /* stage C = h D(P3), P3 = x + h v + h/2 B */
     force_jacobian(&st.s[2], J);
     matvec3(J, cbar, p);
@@ -690,7 +767,8 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, const
     memcpy(r, rbar, sizeof r);
     memcpy(tau, tbar, sizeof tau);
   }
-  /* initial condition v_0 = (1 + delta(x_0)) d */
+  /* initial condition v_0 = (1 + delta(x_0)) d (quasi-linear: also the direction of L) */
+  for (int i = 0; i < 3; ++i) tau[i] += lv0[i];
   sample_t s0;
   sample_field(F, tp->x0, &tp->cells[0], &s0);
   scatter_value(F, &s0, dot3(tau, tp->dir), g);
@@ -779,12 +857,29 @@ static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, const
         voxel_index(F, &s0.cell, a, b, k, &idx);
         dd0 += s0.w[0][a] * s0.w[1][b] * s0.w[2][k] * vf[idx];
       }
-  double dx[3] = {0.0, 0.0, 0.0}, dv[3];
-  for (int i = 0; i < 3; ++i) dv[i] = dd0 * tp->dir[i];
+  double dx[3] = {0.0, 0.0, 0.0}, dv[3], dv0[3];
+  for (int i = 0; i < 3; ++i) dv[i] = dv0[i] = dd0 * tp->dir[i];
+  const int quasi = S->tracer == OR_TRACER_QUASILINEAR;
   for (int n = 0; n < tp->n_steps; ++n) {
     stages_t st;
     double xn[3], vn[3], dA[3], dB[3], dC[3], dP[3], dD[3];
-    sharma_step(F, h, &tp->x[3 * n], &tp->v[3 * n], &tp->cells[1 + 3 * n], 1, xn, vn, &st);
+    ray_step(F, S, &tp->x[0], &tp->v[0], n, &tp->x[3 * n], &tp->v[3 * n], &tp->cells[1 + 3 * n], 1, xn, vn,
+             &st);
+    if (quasi) {
+      /* stage points x0 + t_k v0 move with v0 only */
+      double* dK[3] = {dA, dB, dC};
+      const double ts[3] = {n * h, n * h + 0.5 * h, n * h + h};
+      for (int k = 0; k < 3; ++k) {
+        for (int i = 0; i < 3; ++i) dP[i] = ts[k] * dv0[i];
+        force_tangent(F, &st.s[k], dP, vf, dD);
+        for (int i = 0; i < 3; ++i) dK[k][i] = h * dD[i];
+      }
+      for (int i = 0; i < 3; ++i) {
+        dx[i] = dx[i] + h * (dv[i] + (dA[i] + 2.0 * dB[i]) / 6.0);
+        dv[i] = dv[i] + (dA[i] + 4.0 * dB[i] + dC[i]) / 6.0;
+      }
+      continue;
+    }
     force_tangent(F, &st.s[0], dx, vf, dD);
     for (int i = 0; i < 3; ++i) dA[i] = h * dD[i];
     for (int i = 0; i < 3; ++i) dP[i] = dx[i] + 0.5 * h * dv[i] + 0.125 * h * dA[i];

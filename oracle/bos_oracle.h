@@ -29,6 +29,10 @@ enum { OR_WALL_PRINTED = 0, OR_WALL_PROJECTOR = 1 };
 
 enum { OR_CODE_F32 = 0, OR_CODE_F16 = 1, OR_CODE_BF16 = 2 };
 
+/* Ray integration, Sec. 2.B: nonlinear (Eq. 1 fully coupled, the force sampled at the
+   state) or quasi-linear (the force sampled on the straight line from the entry state). */
+enum { OR_TRACER_NONLINEAR = 0, OR_TRACER_QUASILINEAR = 1 };
+
 typedef struct {
   int32_t mode;          /* OR_FIELD_* */
   int32_t n[3];          /* voxels per axis (grid mode), each >= 2 */
@@ -54,6 +58,7 @@ typedef struct {
   double proj_pos[3], proj_fwd[3], proj_right[3], proj_up[3], proj_fov_x_deg;
   double step;           /* RK4 step h in the ray parameter t */
   int32_t max_steps;
+  int32_t tracer;        /* OR_TRACER_* */
   const double* pattern; /* [pat_h][pat_w], row 0 at the top */
 } or_scene;
 
@@ -78,6 +83,9 @@ int or_camera_ray(const or_scene* S, int32_t pixel, double* org, double* dir);
 /* nsteps Sharma steps from (x0, v0) with no box and no exit test. */
 int or_integrate(const or_field* F, const double* x0, const double* v0, double h, int32_t nsteps,
                  double* x_out, double* v_out);
+/* nsteps quasi-linear steps from (x0, v0): forces on the line x0 + v0 t. */
+int or_integrate_quasi(const or_field* F, const double* x0, const double* v0, double h, int32_t nsteps,
+                       double* x_out, double* v_out);
 
 /* Forward: per ray wall coordinates (u, v), deflection (u, v) - (u0, v0) against the
    undeflected camera ray, step count and status. exit_xv (nullable) gets [x(3), v(3)]

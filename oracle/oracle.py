@@ -20,6 +20,7 @@ _LIB = os.path.join(_HERE, "libbos_oracle.so")
 RAY_MISSED_BOX, RAY_TRUNCATED, RAY_NO_WALL_HIT, RAY_NONFINITE, RAY_OFF_PATTERN = 1, 2, 4, 8, 16
 CODE_F32, CODE_F16, CODE_BF16 = 0, 1, 2
 FIELD_GRID, FIELD_HOMOGENEOUS, FIELD_LINEAR, FIELD_ETA2_LINEAR, FIELD_GAUSSIAN = 0, 1, 2, 3, 4
+TRACER_NONLINEAR, TRACER_QUASILINEAR = 0, 1
 
 D3 = C.c_double * 3
 
@@ -42,7 +43,7 @@ class _Scene(C.Structure):
         ("pat_extent_u", C.c_double), ("pat_extent_v", C.c_double),
         ("proj_pos", D3), ("proj_fwd", D3), ("proj_right", D3), ("proj_up", D3),
         ("proj_fov_x_deg", C.c_double),
-        ("step", C.c_double), ("max_steps", C.c_int32),
+        ("step", C.c_double), ("max_steps", C.c_int32), ("tracer", C.c_int32),
         ("pattern", C.POINTER(C.c_double)),
     ]
 
@@ -83,6 +84,7 @@ def load():
             "or_sample": [P, P, P, P, P],
             "or_camera_ray": [P, C.c_int32, P, P],
             "or_integrate": [P, P, P, C.c_double, C.c_int32, P, P],
+            "or_integrate_quasi": [P, P, P, C.c_double, C.c_int32, P, P],
             "or_trace": [P, P, P, C.c_int32, P, P, P, P, P],
             "or_render": [P, P, C.c_int32, P, P, P, P],
             "or_loss": [P, P, P, C.c_int32, P, P],
@@ -172,6 +174,7 @@ class _SceneHolder:
         s.pat_extent_u, s.pat_extent_v = scene.pat_extent_u, scene.pat_extent_v
         s.step = scene.step
         s.max_steps = scene.max_steps
+        s.tracer = getattr(scene, "tracer", TRACER_NONLINEAR)
         self.pattern = None
         if pattern is not None:
             p = np.ascontiguousarray(pattern, dtype=np.float64)
@@ -241,12 +244,15 @@ def camera_ray(scene, pixel: int):
     return o, d
 
 
-def integrate(field: Field, x0, v0, h: float, nsteps: int):
+def integrate(field: Field, x0, v0, h: float, nsteps: int, quasi: bool = False):
+    """nsteps steps from (x0, v0) with no box: nonlinear, or quasi-linear (forces on the
+    line x0 + v0 t)."""
     x0 = np.ascontiguousarray(x0, np.float64)
     v0 = np.ascontiguousarray(v0, np.float64)
     x = np.zeros(3)
     v = np.zeros(3)
-    _check(load().or_integrate(field.ref, _ptr(x0), _ptr(v0), h, nsteps, _ptr(x), _ptr(v)), "integrate")
+    fn = load().or_integrate_quasi if quasi else load().or_integrate
+    _check(fn(field.ref, _ptr(x0), _ptr(v0), h, nsteps, _ptr(x), _ptr(v)), "integrate")
     return x, v
 
 
