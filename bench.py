@@ -34,10 +34,16 @@ if ROOT not in sys.path:
 METRIC = "ray-steps/s fwd and fwd+adjoint (128^3 field, 1M rays) vs FP64 err; % HBM/L2"
 
 # Algorithmic FP32 work per ray-step (flops, FMA = 2), counted from the operations of one
-# Sharma step (4 trilinear samples with gradient, stage arithmetic) and of its reverse.
+# Sharma step (3 trilinear samples with gradient, stage arithmetic) and of its reverse
+# (replay, 3 samples with second derivatives and their reverse).
 FLOP_FWD_STEP = 200
 FLOP_ADJ_STEP = 700
+# Quasi-linear: 2 samples per step (a step's end point starts the next), and an adjoint
+# without replay (2 samples with second derivatives and their reverse per step).
+FLOP_FWD_STEP_QL = 150
+FLOP_ADJ_STEP_QL = 320
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+TRACERS = {"nonlinear": 0, "quasilinear": 1}
 
 
 def parse(argv=None):
@@ -47,6 +53,8 @@ def parse(argv=None):
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="room1m", choices=["room1m", "batch64", "room256"])
     p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    p.add_argument("--tracer", default="nonlinear", choices=list(TRACERS),
+                   help="nonlinear (Eq. 1 coupled) or quasi-linear (forces on the straight entry line)")
     p.add_argument("--offset", type=float, default=0.0, help="16-bit code offset c (eta - 1 = c + q/s)")
     p.add_argument("--ckpt", type=int, default=8, help="checkpoint stride (steps)")
     p.add_argument("--tile", default="8x8", help="forward: rays per wavefront tile")
@@ -104,7 +112,8 @@ def launch_desc(l) -> dict:
 def traffic_config(args, W) -> dict:
     """What the adjoint's counters depend on: workload, storage, stride and its launch."""
     l = W.adj_launch
-    return {"workload": args.workload, "dtype": args.dtype, "ckpt_stride": str(W.ckpt_stride),
+    return {"workload": args.workload, "tracer": args.tracer, "dtype": args.dtype,
+            "ckpt_stride": str(W.ckpt_stride),
             "adj_launch": "%dx%d wpb %d persistent %d bpc %d" % (l.tile_w, l.tile_h, l.waves_per_block,
                                                                  l.persistent, l.blocks_per_cu)}
 
@@ -153,7 +162,8 @@ class Workload:
         launch, adj_launch = launches(args)
         self.temps, self.fields, self.scenes, self.descs = [], [], [], []
         if args.workload in ("room1m", "room256"):
-            desc = (bi.scene_room_1m() if args.workload == "room1m" else bi.scene_room_256_3m()).replace(ckpt_stride=args.ckpt)
+            desc = (bi.scene_room_1m() if args.workload == "room1m" else bi.scene_room_256_3m()).replace(
+                ckpt_stride=args.ckpt, tracer=TRACERS[args.tracer])
             seed_a, seed_b = (3, 4) if args.workload == "room1m" else (5, 6)
             lo, hi, dims = desc.box_lo, desc.box_hi, desc.dims
             TA = bi.temperature_grid(bi.plumes_room(seed_a, lo, hi), lo, hi, dims).astype(np.float32)
@@ -176,7 +186,7 @@ class Workload:
             pat = torch.from_numpy(bi.blurred_noise(12, (1024, 1024)).astype(np.float32)).to(dev)
             self.pat = pat
             for sc, spec in bi.scenes_batch(64):
-                sc = sc.replace(ckpt_stride=args.ckpt)
+                sc = sc.replace(ckpt_stride=args.ckpt, tracer=TRACERS[args.tracer])
                 T = torch.from_numpy(bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32))
                 T = T.to(dev)
                 f = api.Field.from_temperature(T, args.dtype, None, args.offset)
@@ -303,7 +313,8 @@ def main():
     assert int(sum(int(n.sum(dtype=torch.int64)) for n in W.fwd_only.n_steps)) == ray_steps
 
     adj_s = k_ms[4] * 1e-3
-    achieved = FLOP_ADJ_STEP * ray_steps / adj_s / 1e12
+    flop_adj = FLOP_ADJ_STEP_QL if args.tracer == "quasilinear" else FLOP_ADJ_STEP
+    achieved = flop_adj * ray_steps / adj_s / 1e12
     traffic = read_traffic(args.traffic, args, W)
     n_rays = sum(s.n_rays for s in W.scenes)
     names = {
@@ -327,7 +338,8 @@ def main():
         "dtype": args.dtype,
         "data": W.data_note,
         "config": {
-            "workload": names[args.workload],
+            "workload": names[args.workload] + (", quasi-linear tracer" if args.tracer == "quasilinear" else ""),
+            "tracer": args.tracer,
             "storage": args.dtype, "offset": args.offset, "ckpt_stride": W.ckpt_stride,
             "fwd_launch": launch_desc(W.launch), "adj_launch": launch_desc(W.adj_launch),
             "graph": bool(args.graph),
@@ -347,7 +359,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic,
-            "flop_per_ray_step": FLOP_ADJ_STEP,
+            "flop_per_ray_step": flop_adj,
         },
     }
     if hasattr(W, "tuned"):

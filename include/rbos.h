@@ -65,6 +65,12 @@ enum { RBOS_F32 = 0, RBOS_F16 = 1, RBOS_BF16 = 2 };
 /* back-wall luminance model (Sec. 2.C) */
 enum { RBOS_WALL_PRINTED = 0, RBOS_WALL_PROJECTOR = 1 };
 
+/* ray integration (Sec. 2.B): NONLINEAR integrates Eq. (1) fully coupled, the force taken
+   at the traced state; QUASILINEAR takes the force on the straight line x0 + v0 t from
+   the entry state (x0, v0) at the same stage times, which drives velocity and position
+   with the same Sharma update (two field samples per step, no state-dependent gathers). */
+enum { RBOS_TRACER_NONLINEAR = 0, RBOS_TRACER_QUASILINEAR = 1 };
+
 /* per-ray status bits */
 enum {
   RBOS_RAY_MISSED_BOX = 1,  /* camera ray does not meet the field box: straight, 0 steps */
@@ -105,10 +111,14 @@ typedef struct rbos_scene {
   /* integrator: Sharma RK4 step h in the ray parameter t (at most 4 voxels), step cap
      (1 .. 65536), checkpoint stride k (0 = no checkpoints; 1 = every step's state is
      stored and the adjoint reads it instead of replaying: 24 B per ray-step; else a
-     multiple of 8 up to 256, replayed in chunks of 8; rbos_trace_adjoint needs k > 0) */
+     multiple of 8 up to 256, replayed in chunks of 8; rbos_trace_adjoint needs k > 0).
+     With the quasi-linear tracer the adjoint needs no states: any k > 0 stores only the
+     per-ray header. */
   double step;
   int32_t max_steps;
   int32_t ckpt_stride;
+  int32_t tracer;                /* RBOS_TRACER_NONLINEAR / RBOS_TRACER_QUASILINEAR; all scenes
+                                    of one call share it */
 } rbos_scene;
 
 /* Per-scene forward outputs, indexed by ray r (pixel_ids[r], or pixel r). */

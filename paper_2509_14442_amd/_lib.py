@@ -12,6 +12,7 @@ D3 = C.c_double * 3
 
 RBOS_F32, RBOS_F16, RBOS_BF16 = 0, 1, 2
 RBOS_WALL_PRINTED, RBOS_WALL_PROJECTOR = 0, 1
+RBOS_TRACER_NONLINEAR, RBOS_TRACER_QUASILINEAR = 0, 1
 RAY_MISSED_BOX, RAY_TRUNCATED, RAY_NO_WALL_HIT, RAY_NONFINITE, RAY_OFF_PATTERN = 1, 2, 4, 8, 16
 
 STATUS = {
@@ -36,7 +37,7 @@ class rbos_scene(C.Structure):
         ("pat_extent_u", C.c_double), ("pat_extent_v", C.c_double),
         ("proj_pos", D3), ("proj_fwd", D3), ("proj_right", D3), ("proj_up", D3),
         ("proj_fov_x_deg", C.c_double),
-        ("step", C.c_double), ("max_steps", C.c_int32), ("ckpt_stride", C.c_int32),
+        ("step", C.c_double), ("max_steps", C.c_int32), ("ckpt_stride", C.c_int32), ("tracer", C.c_int32),
     ]
 
 

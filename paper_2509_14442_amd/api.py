@@ -152,6 +152,7 @@ class Scene:
         s.step = desc.step
         s.max_steps = desc.max_steps
         s.ckpt_stride = desc.ckpt_stride if ckpt_stride is None else int(ckpt_stride)
+        s.tracer = int(getattr(desc, "tracer", L.RBOS_TRACER_NONLINEAR))
         self.struct = s
         self.desc = desc
         self.field = field

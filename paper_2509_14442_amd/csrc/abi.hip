@@ -107,6 +107,8 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
     return fail(RBOS_E_RANGE, "scene %d: step must be in (0, 4 * smallest voxel]", idx);
   if (S->max_steps < 1 || S->max_steps > (1 << 16))
     return fail(RBOS_E_RANGE, "scene %d: max_steps must be in [1, 65536]", idx);
+  if (S->tracer != RBOS_TRACER_NONLINEAR && S->tracer != RBOS_TRACER_QUASILINEAR)
+    return fail(RBOS_E_RANGE, "scene %d: tracer must be RBOS_TRACER_NONLINEAR or RBOS_TRACER_QUASILINEAR", idx);
   if (S->ckpt_stride != 0 && S->ckpt_stride != 1 &&
       !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
     return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 1 or a multiple of 8 up to 256 (got %d)", idx,
@@ -138,6 +140,13 @@ long long tiles_of(const rbos_scene* S, const Launch& L, int* tiles_x) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// checkpoint slots per ray: states at steps k, 2k, ... below max_steps; the quasi-linear
+// adjoint needs only the ray header
+int ckpt_slots(const rbos_scene* S) {
+  if (S->ckpt_stride <= 0 || S->tracer == RBOS_TRACER_QUASILINEAR) return 0;
+  return (S->max_steps - 1) / S->ckpt_stride;
+}
 
 // entries per checkpoint component: the image in 8 x 8 pixel blocks, or the ray list
 // rounded up to 64
@@ -222,7 +231,8 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.h2_6 = (float)(h * h / 6.0);
   d.max_steps = S->max_steps;
   d.ckpt_k = S->ckpt_stride > 0 ? S->ckpt_stride : 1;
-  d.ckpt_slots = S->ckpt_stride > 0 ? (S->max_steps - 1) / S->ckpt_stride : 0;
+  d.ckpt_slots = ckpt_slots(S);
+  d.tracer = S->tracer;
   const double t = std::tan(0.5 * S->cam_fov_x_deg * M_PI / 180.0);
   d.cam_ax = to_df(t / S->width);
   d.cam_cx = to_df(t);
@@ -278,6 +288,8 @@ int prepare(const rbos_scene* scenes, int32_t n_scenes, const rbos_launch* launc
     if (rc) return rc;
     if (scenes[i].dtype != scenes[0].dtype)
       return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one call must share the storage dtype", i);
+    if (scenes[i].tracer != scenes[0].tracer)
+      return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one call must share the tracer", i);
   }
   P.Y = layout(scenes, n_scenes, P.L);
   if (P.Y.total_tiles > (1LL << 30)) return fail(RBOS_E_SHAPE, "too many rays in one call");
@@ -324,6 +336,7 @@ int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::Launch
   plan.total_render_blocks = P.Y.total_render_blocks;
   plan.partials = reinterpret_cast<float*>(ws + P.Y.partials);
   plan.ckpt_k = P.table.empty() ? 0 : P.table[0].ckpt_k;
+  plan.tracer = P.table.empty() ? 0 : P.table[0].tracer;
   if (P.L.persistent) {
     e = rbos::launch_fill_u32(plan.queues, 0u, 16, stream);
     if (e != hipSuccess) return fail(RBOS_E_HIP, "queue reset failed: %s", hipGetErrorString(e));
@@ -375,9 +388,8 @@ int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, in
 size_t rbos_ckpt_bytes(const rbos_scene* S) {
   if (!S || S->ckpt_stride <= 0 || S->max_steps < 1 || S->n_rays < 0) return 0;
   // a per-ray header, then checkpoint slots for steps k, 2k, ... below max_steps
-  // (6 floats per ray and slot)
-  size_t slots = (size_t)((S->max_steps - 1) / S->ckpt_stride);
-  return (rbos::RAY_HEADER + slots * 6) * (size_t)ckpt_entries(S) * sizeof(float);
+  // (6 floats per ray and slot; none for the quasi-linear tracer)
+  return (rbos::RAY_HEADER + (size_t)ckpt_slots(S) * 6) * (size_t)ckpt_entries(S) * sizeof(float);
 }
 
 size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes) {
@@ -509,7 +521,7 @@ size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields) {
            OFF(rbos_scene, pattern), OFF(rbos_scene, pat_w), OFF(rbos_scene, pat_h), OFF(rbos_scene, pat_extent_u),
            OFF(rbos_scene, pat_extent_v), OFF(rbos_scene, proj_pos), OFF(rbos_scene, proj_fwd),
            OFF(rbos_scene, proj_right), OFF(rbos_scene, proj_up), OFF(rbos_scene, proj_fov_x_deg),
-           OFF(rbos_scene, step), OFF(rbos_scene, max_steps), OFF(rbos_scene, ckpt_stride)};
+           OFF(rbos_scene, step), OFF(rbos_scene, max_steps), OFF(rbos_scene, ckpt_stride), OFF(rbos_scene, tracer)};
       sz = sizeof(rbos_scene);
       break;
     case 1:

@@ -134,6 +134,7 @@ struct SceneDev {
   df h;                // step in t
   float hf, h_2, h_6, h2_8, h2_2, h2_6;
   int max_steps, ckpt_k, ckpt_slots;
+  int tracer;          // 0 nonlinear, 1 quasi-linear (forces on the entry line)
   long long ckpt_pad;  // entries per checkpoint component (a multiple of 64)
   int ckpt_tx;         // full image: 8 x 8 pixel blocks per image row
   // camera
@@ -520,6 +521,40 @@ __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B,
   st.jf += 2.0f;
   for (int a = 0; a < 3; ++a) sm[a] = small_part(B, a, st.jf, st.d[a]);
   locate3(S, st.bh, sm, C);
+}
+
+// One quasi-linear step (Sec. 2.B): the forces are taken on the straight entry line, at
+// its half-step points j = 2n, 2n + 1, 2n + 2 (exact base plus its small part, no
+// deviation), and drive the same update as sharma_step. Kc carries the force at the
+// step's start point, which the previous step computed as its end point.
+template <int DT>
+__device__ __forceinline__ void ql_step(const SceneDev& S, const RayBase& B, State& st, float Kc[3]) {
+  float K2[3], K3[3], bh2[3], bh3[3], sm[3];
+  Cell C;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bh2[a] = st.bh[a] + B.g2hi[a];
+    sm[a] = small_part(B, a, st.jf + 1.0f, 0.0f);
+  }
+  locate3(S, bh2, sm, C);
+  force_at<DT>(S, C, K2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bh3[a] = bh2[a] + B.g2hi[a];
+    sm[a] = small_part(B, a, st.jf + 2.0f, 0.0f);
+  }
+  locate3(S, bh3, sm, C);
+  force_at<DT>(S, C, K3);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float dn = st.d[a] + fmaf(S.hf, st.e[a], S.h2_6 * fmaf(2.0f, K2[a], Kc[a]));
+    float en = st.e[a] + S.h_6 * (fmaf(4.0f, K2[a], Kc[a]) + K3[a]);
+    st.d[a] = dn;
+    st.e[a] = en;
+    st.bh[a] = bh3[a];
+    Kc[a] = K3[a];
+  }
+  st.jf += 2.0f;
 }
 
 // Position strictly outside the box on some axis (or not a number).

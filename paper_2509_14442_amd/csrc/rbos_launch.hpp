@@ -19,6 +19,7 @@ struct LaunchPlan {
   int n_cus;                // compute units of the device
   unsigned int* queues;     // 8 counters (zeroed before the launch)
   int ckpt_k;               // checkpoint stride shared by all scenes (adjoint)
+  int tracer;               // shared by all scenes: 0 nonlinear, 1 quasi-linear
   int total_render_blocks;  // render: sum of per-scene blocks
   float* partials;          // render: per-block partial loss sums
 };

@@ -240,42 +240,83 @@ __device__ __forceinline__ void locate_state(const SceneDev& S, const RayBase& B
 template <int KS>
 constexpr int lds_floats_per_wave() { return KS * 6 * 64 + PEND_SLOTS * 8; }
 
+// Ray setup of the adjoint: the ray of this lane, its step count and whether it carries
+// a gradient, its straight-line base from the header, and the adjoint of the last state
+// through the wall step X = x + s v:
+//   lambda_x = lambda_X - n (v . lambda_X)/(v . n),  lambda_v = s lambda_x
+// (metres; grid units multiply by the voxel size), returned as rb = dL/dd, tb = dL/de.
+struct AdjRay {
+  int r, q, n;  // ray, its checkpoint entry, its step count
+  bool active;
+  RayBase B;
+  float rb[3], tb[3];
+};
+
+__device__ __forceinline__ void adjoint_ray_setup(const SceneDev& S, int tile, int lane, AdjRay& R) {
+  int pix = 0;
+  R.r = 0;
+  R.q = 0;
+  R.n = 0;
+  R.active = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) R.rb[a] = R.tb[a] = 0.0f;
+  if (!tile_ray(S, tile, lane, R.r, pix)) return;
+  const int r = R.r;
+  R.q = ckpt_entry(S, r, pix);
+  R.n = gld(S.n_steps + r);
+  const unsigned char st = gld(S.status + r);
+  const float lu = gld(S.adj_dL_duv + 2 * (size_t)r), lv = gld(S.adj_dL_duv + 2 * (size_t)r + 1);
+  R.active = R.n > 0 && !(st & (RAY_NO_WALL_HIT | RAY_NONFINITE | RAY_MISSED_BOX)) && !(lu == 0.0f && lv == 0.0f);
+  if (!R.active) return;
+  float e_end[3], s;
+  load_ray_header(S, R.q, R.B, e_end, s);
+  float v[3], lX[3], vn = 0.0f, vl = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    v[a] = R.B.V[a] + e_end[a] * S.vox[a];
+    lX[a] = lu * S.wall_u_f[a] + lv * S.wall_v_f[a];
+    vn += v[a] * S.wall_n_f[a];
+    vl += v[a] * lX[a];
+  }
+  const float qv = vl / vn;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lx = lX[a] - S.wall_n_f[a] * qv;
+    R.rb[a] = lx * S.vox[a];
+    R.tb[a] = s * R.rb[a];
+  }
+}
+
+// Initial condition v0 = (1 + delta(x0)) dir: dL/d delta_c += w_c(x0) sum_a tb0_a dir_a /
+// voxel_a, with tb0 = dL/dv0 in grid units. Contributions of lanes with `active`.
+__device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, bool active, const float tb0[3],
+                                           Accum& A, Pending& P, int lane) {
+  int key0 = 0;
+  float c0v[8];
+  if (active) {
+    Cell C0;
+    locate3(S, B.U0hi, B.U0lo, C0);
+    const float vn = sqrtf(B.V[0] * B.V[0] + B.V[1] * B.V[1] + B.V[2] * B.V[2]);
+    float kap = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) kap = fmaf(tb0[a], (B.V[a] / vn) * dd_to_f(S.inv_vox[a]), kap);
+    const float X[2] = {1.0f - C0.f[0], C0.f[0]}, Y[2] = {1.0f - C0.f[1], C0.f[1]}, Z[2] = {1.0f - C0.f[2], C0.f[2]};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c0v[k] = kap * (X[k & 1] * Y[(k >> 1) & 1] * Z[k >> 2]);
+    key0 = cell_key(C0);
+  }
+  accumulate(S, A, active, key0, c0v, lane, P);
+}
+
 template <int DT, int KS, bool STORED>
 __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int lane, float* __restrict__ replay) {
-  int r = 0, pix = 0;
-  const bool valid = tile_ray(S, tile, lane, r, pix);
-  const int q = valid ? ckpt_entry(S, r, pix) : 0;  // checkpoint entry
-  int n = 0;
-  bool active = false;
-  RayBase B;
-  float rb[3] = {0.0f, 0.0f, 0.0f}, tb[3] = {0.0f, 0.0f, 0.0f};  // dL/dd, dL/de (grid units)
-  if (valid) {
-    n = gld(S.n_steps + r);
-    const unsigned char st = gld(S.status + r);
-    const float lu = gld(S.adj_dL_duv + 2 * (size_t)r), lv = gld(S.adj_dL_duv + 2 * (size_t)r + 1);
-    active = n > 0 && !(st & (RAY_NO_WALL_HIT | RAY_NONFINITE | RAY_MISSED_BOX)) && !(lu == 0.0f && lv == 0.0f);
-    if (active) {
-      // wall step X = x + s v: lambda_x = lambda_X - n (v . lambda_X)/(v . n),
-      // lambda_v = s lambda_x (metres); grid units multiply by the voxel size
-      float e_end[3], s;
-      load_ray_header(S, q, B, e_end, s);
-      float v[3], lX[3], vn = 0.0f, vl = 0.0f;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        v[a] = B.V[a] + e_end[a] * S.vox[a];
-        lX[a] = lu * S.wall_u_f[a] + lv * S.wall_v_f[a];
-        vn += v[a] * S.wall_n_f[a];
-        vl += v[a] * lX[a];
-      }
-      const float q = vl / vn;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float lx = lX[a] - S.wall_n_f[a] * q;
-        rb[a] = lx * S.vox[a];
-        tb[a] = s * rb[a];
-      }
-    }
-  }
+  AdjRay R;
+  adjoint_ray_setup(S, tile, lane, R);
+  const int q = R.q, n = R.n;
+  const bool active = R.active;
+  const RayBase& B = R.B;
+  float* rb = R.rb;
+  float* tb = R.tb;
   // STORED (stride 1): every step's start state is in the checkpoints and a chunk is
   // filled from them; otherwise a segment of K steps is replayed from its checkpoint in
   // chunks.
@@ -433,24 +474,137 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
       chunk_end(S, P, lane);
     }
   }
-  // initial condition v0 = (1 + delta(x0)) dir: dL/d delta_c += w_c(x0) sum_a tb_a dir_a / voxel_a
-  int key0 = 0;
-  float c0v[8];
-  if (active) {
-    Cell C0;
-    locate3(S, B.U0hi, B.U0lo, C0);
-    const float vn = sqrtf(B.V[0] * B.V[0] + B.V[1] * B.V[1] + B.V[2] * B.V[2]);
-    float kap = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) kap = fmaf(tb[a], (B.V[a] / vn) * dd_to_f(S.inv_vox[a]), kap);
-    const float X[2] = {1.0f - C0.f[0], C0.f[0]}, Y[2] = {1.0f - C0.f[1], C0.f[1]}, Z[2] = {1.0f - C0.f[2], C0.f[2]};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) c0v[k] = kap * (X[k & 1] * Y[(k >> 1) & 1] * Z[k >> 2]);
-    key0 = cell_key(C0);
-  }
-  accumulate(S, A, active, key0, c0v, lane, P);
+  entry_term(S, B, active, tb, A, P, lane);
   flush(S, A, A.key != CELL_NONE, lane, P);
   if (P.occupied) write_out(S, P, P.occupied, lane);
+}
+
+// Quasi-linear form: the stage points lie on the entry line, at its half-step points
+// j = 0 .. 2n (P(j) = U0 + j g2, g2 = V h / 2 in grid units), so the reverse needs no
+// states. The state recursion is linear: with r = dL/dd and tau_k = dL/de after step k,
+// r stays rb and tau_k = tb + (n - k) h rb. The force at P(j) gets the adjoint
+//   even j = 2m: h (h/6 r + tau_{m+1}/6) [stage A of step m, m < n]
+//                + h tau_m / 6 [stage C of step m - 1, m > 0]
+//   odd  j = 2k + 1: h (h/3 r + 2/3 tau_{k+1}) [stage B of step k]
+// and passes it to the 8 corner voxels and, through the point's dependence on the
+// entry velocity, j h/2 times its position adjoint to dL/dv0.
+template <int DT>
+__device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int lane, float* __restrict__ cache) {
+  AdjRay R;
+  adjoint_ray_setup(S, tile, lane, R);
+  const int n = R.n;
+  const bool active = R.active;
+  const RayBase& B = R.B;
+  const int npts = wave_max_nonneg(active ? 2 * n + 1 : 0);
+  const float h = S.hf, h_6 = S.h_6;
+  Accum A;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
+  A.key = CELL_NONE;
+  Pending P{cache, CELL_NONE, 0, 0ull, 0ull};
+  float pv[3] = {0.0f, 0.0f, 0.0f};  // dL/dv0 through the stage points (grid units)
+#pragma unroll 1
+  for (int j = 0; j < npts; ++j) {
+    const bool act = active && j <= 2 * n;
+    int key = 0;
+    float ct[8];
+    if (act) {
+      float v[3];
+      const int m = j >> 1;
+      if ((j & 1) == 0) {
+        const float ca = (float)(n - m - 1) * h, cc = (float)(n - m) * h;  // tau_{m+1}, tau_m
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float tA = fmaf(ca, R.rb[a], R.tb[a]), tC = fmaf(cc, R.rb[a], R.tb[a]);
+          const float wa = m < n ? h * fmaf(h_6, R.rb[a], tA * (1.0f / 6.0f)) : 0.0f;
+          const float wc = m > 0 ? h * (tC * (1.0f / 6.0f)) : 0.0f;
+          v[a] = wa + wc;
+        }
+      } else {
+        const float cb = (float)(n - m - 1) * h;  // tau_{m+1}
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float tB = fmaf(cb, R.rb[a], R.tb[a]);
+          v[a] = h * fmaf(h * (1.0f / 3.0f), R.rb[a], tB * (2.0f / 3.0f));
+        }
+      }
+      const float jf = (float)j;
+      float bh[3], sm[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bh[a] = fmaf(jf, B.g2hi[a], B.U0hi[a]);
+        sm[a] = small_part(B, a, jf, 0.0f);
+      }
+      Cell C;
+      locate3(S, bh, sm, C);
+      SampleRev Rs;
+      sample_rev<DT>(S, C, Rs);
+      float p[3];
+      force_rev(S, Rs, v, p, ct);
+      const float tj = jf * (0.5f * h);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) pv[a] = fmaf(tj, p[a], pv[a]);
+      key = cell_key(C);
+    }
+    accumulate(S, A, act, key, ct, lane, P);
+    if ((j & 15) == 15) chunk_end(S, P, lane);
+  }
+  float tb0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) tb0[a] = fmaf((float)n * h, R.rb[a], R.tb[a]) + pv[a];
+  entry_term(S, B, active, tb0, A, P, lane);
+  flush(S, A, A.key != CELL_NONE, lane, P);
+  if (P.occupied) write_out(S, P, P.occupied, lane);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_trace_adj_ql(const SceneDev* __restrict__ scenes, int n_scenes,
+                                                      int total_tiles, int wpb, int nblocks) {
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
+  if (gtile >= total_tiles) return;  // whole wavefront
+  const int si = find_scene(scenes, n_scenes, gtile);
+  const SceneDev& S = scenes[si];
+  extern __shared__ float lds[];
+  adjoint_tile_ql<DT>(S, gtile - S.tile_begin, lane, lds + wave * (PEND_SLOTS * 8));
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_trace_adj_ql_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
+                                                                 int total_tiles, unsigned int* __restrict__ queues) {
+  const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
+  const int xcd = blockIdx.x & 7;
+  extern __shared__ float lds[];
+  float* cache = lds + wave * (PEND_SLOTS * 8);
+  for (int q = 0; q < 8; ++q) {
+    const int qx = (xcd + q) & 7;
+    const int q_begin = (int)(((long long)total_tiles * qx) >> 3);
+    const int q_end = (int)(((long long)total_tiles * (qx + 1)) >> 3);
+    while (true) {
+      int t = 0;
+      if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
+      t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
+      if (t >= q_end) break;
+      const int si = find_scene(scenes, n_scenes, t);
+      const SceneDev& S = scenes[si];
+      adjoint_tile_ql<DT>(S, t - S.tile_begin, lane, cache);
+    }
+  }
+}
+
+template <int DT>
+static hipError_t launch_adj_ql(const LaunchPlan& P, hipStream_t stream) {
+  const size_t lds = sizeof(float) * PEND_SLOTS * 8 * (size_t)P.wpb;
+  if (P.persistent) {
+    const int grid = persistent_grid(k_trace_adj_ql_persistent<DT>, P, lds);
+    hipLaunchKernelGGL((k_trace_adj_ql_persistent<DT>), dim3(grid), dim3(64 * P.wpb), lds, stream, P.scenes,
+                       P.n_scenes, P.total_tiles, P.queues);
+  } else {
+    int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
+    hipLaunchKernelGGL((k_trace_adj_ql<DT>), dim3(nblocks), dim3(64 * P.wpb), lds, stream, P.scenes, P.n_scenes,
+                       P.total_tiles, P.wpb, nblocks);
+  }
+  return hipGetLastError();
 }
 
 template <int DT, int KS, bool STORED>
@@ -505,6 +659,7 @@ static hipError_t launch_adj_t(const LaunchPlan& P, hipStream_t stream) {
 
 template <int DT>
 static hipError_t launch_adj_dt(const LaunchPlan& P, hipStream_t stream) {
+  if (P.tracer == 1) return launch_adj_ql<DT>(P, stream);
   // chunks of 8 step-start states in LDS: stride 1 fills them from the checkpoints,
   // strides 8, 16, ... replay them
   return P.ckpt_k == 1 ? launch_adj_t<DT, 8, true>(P, stream) : launch_adj_t<DT, 8, false>(P, stream);

@@ -9,7 +9,7 @@ namespace rbos {
 // (component c of the ray at [c * ckpt_pad + ckpt_entry]): the ray header (see
 // store_ray_header), then the states (d, e) before steps k, 2k, ... (6 components per
 // slot).
-template <int DT>
+template <int DT, bool QL>
 __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   int n = 0;
   unsigned char status = 0;
@@ -45,8 +45,10 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
     const size_t slot_stride = 6 * (size_t)S.ckpt_pad;
     int kc = S.ckpt_k;
     bool exited = false;
+    float Kc[3];  // quasi-linear: force at the current point of the entry line
+    if constexpr (QL) force_at<DT>(S, C, Kc);
     while (n < S.max_steps) {
-      if (ck && kc == 0) {
+      if (!QL && ck && kc == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           gst(ck + (size_t)a * S.ckpt_pad, st.d[a]);
@@ -55,7 +57,11 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
         ck += slot_stride;
         kc = S.ckpt_k;
       }
-      sharma_step<DT>(S, B, st, C);
+      if constexpr (QL) {
+        ql_step<DT>(S, B, st, Kc);
+      } else {
+        sharma_step<DT>(S, B, st, C);
+      }
       ++n;
       --kc;
       if (!state_finite(st)) {
@@ -111,7 +117,7 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   gst(S.status + r, status);
 }
 
-template <int DT>
+template <int DT, bool QL>
 __global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ scenes, int n_scenes,
                                                    int total_tiles, int wpb, int nblocks) {
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -122,12 +128,12 @@ __global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ 
   const int tile = gtile - S.tile_begin;
   int r, pix;
   if (!tile_ray(S, tile, lane, r, pix)) return;
-  trace_one<DT>(S, r, pix);
+  trace_one<DT, QL>(S, r, pix);
 }
 
 // Persistent form: blocks pull tiles from per-XCD queues (contiguous tile ranges), and
 // steal from the other XCDs' ranges once their own is drained.
-template <int DT>
+template <int DT, bool QL>
 __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
                                                               int total_tiles, unsigned int* __restrict__ queues) {
   const int lane = threadIdx.x & 63;
@@ -145,32 +151,37 @@ __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __
       const SceneDev& S = scenes[si];
       const int tile = t - S.tile_begin;
       int r, pix;
-      if (tile_ray(S, tile, lane, r, pix)) trace_one<DT>(S, r, pix);
+      if (tile_ray(S, tile, lane, r, pix)) trace_one<DT, QL>(S, r, pix);
     }
   }
 }
 
-template <int DT>
+template <int DT, bool QL>
 static hipError_t launch_fwd_t(const LaunchPlan& P, hipStream_t stream) {
   const dim3 block(64 * P.wpb);
   if (P.persistent) {
-    const dim3 grid(persistent_grid(k_trace_fwd_persistent<DT>, P, 0));
-    hipLaunchKernelGGL(k_trace_fwd_persistent<DT>, grid, block, 0, stream, P.scenes, P.n_scenes, P.total_tiles,
-                       P.queues);
+    const dim3 grid(persistent_grid(k_trace_fwd_persistent<DT, QL>, P, 0));
+    hipLaunchKernelGGL((k_trace_fwd_persistent<DT, QL>), grid, block, 0, stream, P.scenes, P.n_scenes,
+                       P.total_tiles, P.queues);
   } else {
     const int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
-    hipLaunchKernelGGL(k_trace_fwd<DT>, dim3(nblocks), block, 0, stream, P.scenes, P.n_scenes, P.total_tiles, P.wpb,
-                       nblocks);
+    hipLaunchKernelGGL((k_trace_fwd<DT, QL>), dim3(nblocks), block, 0, stream, P.scenes, P.n_scenes, P.total_tiles,
+                       P.wpb, nblocks);
   }
   return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t launch_fwd_dt(const LaunchPlan& P, hipStream_t stream) {
+  return P.tracer == 1 ? launch_fwd_t<DT, true>(P, stream) : launch_fwd_t<DT, false>(P, stream);
 }
 
 hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream) {
   if (P.total_tiles == 0) return hipSuccess;
   switch (P.dtype) {
-    case DT_F32: return launch_fwd_t<DT_F32>(P, stream);
-    case DT_F16: return launch_fwd_t<DT_F16>(P, stream);
-    default: return launch_fwd_t<DT_BF16>(P, stream);
+    case DT_F32: return launch_fwd_dt<DT_F32>(P, stream);
+    case DT_F16: return launch_fwd_dt<DT_F16>(P, stream);
+    default: return launch_fwd_dt<DT_BF16>(P, stream);
   }
 }
 

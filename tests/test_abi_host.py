@@ -94,6 +94,7 @@ def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
     (lambda s: setattr(s, "max_steps", 0), -3),
     (lambda s: setattr(s, "ckpt_stride", 12), -7),
     (lambda s: setattr(s, "ckpt_stride", 4), -7),
+    (lambda s: setattr(s, "tracer", 2), -3),
     (lambda s: setattr(s, "ckpt_stride", 264), -7),
 ])
 def test_forward_validation(lib, mutate, code):
@@ -165,6 +166,9 @@ def test_field_validation_and_sizes(lib):
     assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 6 * 64 * 4
     s.pixel_ids, s.n_rays = 0x40, 65  # ray list: 65 -> 128 entries
     assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 128 * 4
+    s.tracer = L.RBOS_TRACER_QUASILINEAR  # the quasi-linear adjoint needs only the ray header
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == 19 * 128 * 4
+    s.tracer = L.RBOS_TRACER_NONLINEAR
     s.ckpt_stride = 0
     assert lib.rbos_ckpt_bytes(C.byref(s)) == 0
     assert lib.rbos_workspace_bytes(C.byref(s), 1) >= 256
