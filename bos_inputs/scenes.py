@@ -58,6 +58,9 @@ class Scene:
     max_steps: int = 512
     ckpt_stride: int = 16
     tracer: int = 0  # 0: nonlinear (Eq. 1 coupled), 1: quasi-linear (forces on the entry line)
+    spp: int = 1  # rays per pixel (Eq. 2 pixel integral; 1 = one ray through the pixel centre)
+    seed: int = 0  # sub-pixel sample generator key
+    radiometry: int = 0  # 1: weight each ray by |<n_w, v_w>| / |X_w - camera|
     name: str = ""
 
     @property

@@ -21,7 +21,11 @@ from .oracle import (  # noqa: F401
     integrate,
     trace,
     render,
+    render_pixels,
     loss,
+    loss_pixels,
+    philox4x32,
+    sample_offset,
     adjoint,
     tangent,
     fd_voxels,

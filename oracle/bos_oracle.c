@@ -377,12 +377,56 @@ int or_integrate(const or_field* F, const double* x0, const double* v0, double h
 /* ------------------------------------------------------------------------------------ */
 /* Sec. 2.C: camera, box, wall, wall luminance                                           */
 /* ------------------------------------------------------------------------------------ */
-/* Pinhole camera, horizontal field of view, rays through pixel centres. */
-static void camera_ray(const or_scene* S, int32_t pix, double* org, double* dir) {
+/* Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as
+   1, 2, 3", SC'11): ten rounds, each two 32 x 32 -> 64-bit products of the even counter
+   words with fixed multipliers, the high halves mixed into the odd words with the key;
+   the key advances by a Weyl sequence between rounds. */
+static void philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k0 += W0; k1 += W1; }
+    uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+int or_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  if (!ctr || !key || !out) return -1;
+  philox4x32_10(ctr, key, out);
+  return 0;
+}
+
+/* Inverse CDF of the triangular density 1 - |x| on [-1, 1]. */
+static double tent_inverse(double u) { return u < 0.5 ? sqrt(2.0 * u) - 1.0 : 1.0 - sqrt(2.0 - 2.0 * u); }
+
+static void sample_offset(uint32_t seed, int32_t pixel, int32_t sample, double* ox, double* oy) {
+  const uint32_t ctr[4] = {(uint32_t)pixel, (uint32_t)sample, 0u, 0u}, key[2] = {seed, 0u};
+  uint32_t x[4];
+  philox4x32_10(ctr, key, x);
+  *ox = tent_inverse((double)(x[0] >> 8) * 0x1p-24);
+  *oy = tent_inverse((double)(x[1] >> 8) * 0x1p-24);
+}
+
+int or_sample_offset(uint32_t seed, int32_t pixel, int32_t sample, double* ox, double* oy) {
+  if (!ox || !oy || pixel < 0 || sample < 0) return -1;
+  sample_offset(seed, pixel, sample, ox, oy);
+  return 0;
+}
+
+/* Pinhole camera, horizontal field of view. With one sample per pixel the ray goes
+   through the pixel centre; with more, through the centre plus the sample's offset
+   (Eq. (2): the triangular camera filter, sampled by inverting its CDF). */
+static void camera_ray(const or_scene* S, int32_t pix, int32_t sample, double* org, double* dir) {
   int col = pix % S->width, row = pix / S->width;
+  double ox = 0.0, oy = 0.0;
+  if (S->spp > 1) sample_offset(S->seed, pix, sample, &ox, &oy);
   double t = tan(0.5 * S->fov_x_deg * OR_PI / 180.0);
-  double px = (2.0 * (col + 0.5) / S->width - 1.0) * t;
-  double py = (1.0 - 2.0 * (row + 0.5) / S->height) * t * S->height / S->width;
+  double px = (2.0 * (col + 0.5 + ox) / S->width - 1.0) * t;
+  double py = (1.0 - 2.0 * (row + 0.5 + oy) / S->height) * t * S->height / S->width;
   for (int i = 0; i < 3; ++i) {
     org[i] = S->cam_pos[i];
     dir[i] = S->cam_fwd[i] + px * S->cam_right[i] + py * S->cam_up[i];
@@ -393,7 +437,7 @@ static void camera_ray(const or_scene* S, int32_t pix, double* org, double* dir)
 
 int or_camera_ray(const or_scene* S, int32_t pixel, double* org, double* dir) {
   if (!S || !org || !dir || pixel < 0 || pixel >= S->width * S->height) return -1;
-  camera_ray(S, pixel, org, dir);
+  camera_ray(S, pixel, 0, org, dir);
   return 0;
 }
 
@@ -537,10 +581,10 @@ typedef struct {
 } ray_result_t;
 
 /* Trace one ray. With locked != 0 the tape's cells and step count are replayed. */
-static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, tape_t* tp, int locked,
+static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, tape_t* tp, int locked,
                       ray_result_t* out) {
   double org[3], dir[3];
-  camera_ray(S, pix, org, dir);
+  camera_ray(S, pix, sample, org, dir);
   out->status = 0;
   out->n_steps = 0;
   double X[3];
@@ -595,21 +639,34 @@ static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, tape_t*
 }
 
 static int check_args(const or_field* F, const or_scene* S, const int32_t* ids, int32_t n_rays) {
-  if (!F || !S || n_rays < 0) return -1;
+  if (!F || !S || n_rays < 0 || S->spp < 1 || n_rays % S->spp) return -1;
   if (F->mode == OR_FIELD_GRID && (!F->delta || F->n[0] < 2 || F->n[1] < 2 || F->n[2] < 2)) return -1;
   if (S->width < 1 || S->height < 1 || !(S->step > 0.0) || S->max_steps < 1) return -1;
-  if (!ids && n_rays != S->width * S->height) return -1;
+  if (!ids && n_rays != S->width * S->height * S->spp) return -1;
   return 0;
 }
 
+/* Ray r of n_rays is sample r / P of pixel index r % P (P = n_rays / spp pixels). */
+static void ray_pixel(const or_scene* S, const int32_t* ids, int32_t n_rays, int32_t r, int32_t* pix,
+                      int32_t* sample) {
+  int32_t P = n_rays / S->spp, i = r % P;
+  *sample = r / P;
+  *pix = ids ? ids[i] : i;
+}
+
 int or_trace(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv) {
+             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv, double* vdir) {
   if (check_args(F, S, pixel_ids, n_rays)) return -1;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t r = 0; r < n_rays; ++r) {
-    int32_t pix = pixel_ids ? pixel_ids[r] : r;
+    int32_t pix, sample;
+    ray_pixel(S, pixel_ids, n_rays, r, &pix, &sample);
     ray_result_t res;
-    trace_ray(F, S, pix, NULL, 0, &res);
+    trace_ray(F, S, pix, sample, NULL, 0, &res);
+    if (vdir) {
+      double len = sqrt(dot3(res.v, res.v));
+      for (int i = 0; i < 3; ++i) vdir[3 * r + i] = res.v[i] / len;
+    }
     if (uv) { uv[2 * r] = res.uv[0]; uv[2 * r + 1] = res.uv[1]; }
     if (duv) { duv[2 * r] = res.uv[0] - res.uv0[0]; duv[2 * r + 1] = res.uv[1] - res.uv0[1]; }
     if (n_steps) n_steps[r] = res.n_steps;
@@ -655,6 +712,85 @@ int or_loss(const double* image, const double* target, const double* dI_duv, int
   return 0;
 }
 
+/* Eq. (2) weight of a ray reaching the wall at (u, v) with unit direction d:
+   w = |<n_w, d>| / |X_w - c| (c the camera centre; the path length read as the distance
+   from the camera to the hit), and its derivatives w.r.t. (u, v) and d. */
+static double radiometric(const or_scene* S, const double* uv, const double* d, double* dw_duv, double* dw_dd) {
+  double r[3];
+  for (int i = 0; i < 3; ++i)
+    r[i] = S->wall_origin[i] + uv[0] * S->wall_u[i] + uv[1] * S->wall_v[i] - S->cam_pos[i];
+  double dist = sqrt(dot3(r, r)), c = dot3(S->wall_normal, d), ac = fabs(c);
+  double k = -ac / (dist * dist * dist);
+  dw_duv[0] = k * dot3(r, S->wall_u);
+  dw_duv[1] = k * dot3(r, S->wall_v);
+  double sg = c < 0.0 ? -1.0 : 1.0;
+  for (int i = 0; i < 3; ++i) dw_dd[i] = sg * S->wall_normal[i] / dist;
+  return ac / dist;
+}
+
+/* Radiance carried by one ray (the integrand of Eq. (2) for that sample) and its
+   derivatives w.r.t. (u, v) and the unit direction at the wall. */
+static double ray_radiance(const or_scene* S, const double* uv, const double* d, int* tex, int lock, double* dI,
+                           double* dId, int* off) {
+  double L = wall_luminance(S, uv, tex, lock, dI, off);
+  dId[0] = dId[1] = dId[2] = 0.0;
+  if (!S->radiometry) return L;
+  double dw[2], dwd[3];
+  double w = radiometric(S, uv, d, dw, dwd);
+  dI[0] = dI[0] * w + L * dw[0];
+  dI[1] = dI[1] * w + L * dw[1];
+  for (int k = 0; k < 3; ++k) dId[k] = L * dwd[k];
+  return L * w;
+}
+
+int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, const double* vdir, uint8_t* status,
+                     double* image, double* dI_duv, double* dI_ddir) {
+  if (!S || !uv || !image || n_pixels < 0 || S->spp < 1 || !S->pattern || S->pat_w < 1 || S->pat_h < 1) return -1;
+  if (S->radiometry && !vdir) return -1;
+  const int spp = S->spp;
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n_pixels; ++i) {
+    double sum = 0.0;
+    for (int s = 0; s < spp; ++s) {
+      int64_t r = (int64_t)s * n_pixels + i;
+      double dI[2] = {0.0, 0.0}, dId[3] = {0.0, 0.0, 0.0}, I = 0.0;
+      uint8_t st = status ? status[r] : 0;
+      if (!(st & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE))) {
+        int tex[2], off = 0;
+        I = ray_radiance(S, &uv[2 * r], vdir ? &vdir[3 * r] : NULL, tex, 0, dI, dId, &off);
+        if (off && status) status[r] |= OR_RAY_OFF_PATTERN;
+      }
+      sum += I;
+      if (dI_duv) { dI_duv[2 * r] = dI[0] / spp; dI_duv[2 * r + 1] = dI[1] / spp; }
+      if (dI_ddir)
+        for (int k = 0; k < 3; ++k) dI_ddir[3 * r + k] = dId[k] / spp;
+    }
+    image[i] = sum / spp;
+  }
+  return 0;
+}
+
+int or_loss_pixels(const double* image, const double* target, int32_t n_pixels, int32_t spp, const double* dI_duv,
+                   const double* dI_ddir, double* loss, double* dL_duv, double* dL_ddir) {
+  if (!image || !target || n_pixels < 0 || spp < 1) return -1;
+  double L = 0.0;
+  for (int32_t i = 0; i < n_pixels; ++i) {
+    double res = image[i] - target[i];
+    L += res * res;
+    for (int s = 0; s < spp; ++s) {
+      int64_t r = (int64_t)s * n_pixels + i;
+      if (dL_duv && dI_duv) {
+        dL_duv[2 * r] = 2.0 * res * dI_duv[2 * r];
+        dL_duv[2 * r + 1] = 2.0 * res * dI_duv[2 * r + 1];
+      }
+      if (dL_ddir && dI_ddir)
+        for (int k = 0; k < 3; ++k) dL_ddir[3 * r + k] = 2.0 * res * dI_ddir[3 * r + k];
+    }
+  }
+  if (loss) *loss = L;
+  return 0;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* Sec. 2.D: exact gradient of the discrete forward map (reverse mode)                   */
 /* ------------------------------------------------------------------------------------ */
@@ -691,13 +827,15 @@ static void scatter_value(const or_field* F, const sample_t* s, double scale, do
 }
 
 /* Reverse one ray given lambda = dL/d(u, v). */
-static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, const double* lam_uv,
-                        tape_t* tp, double* g) {
+static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, const double* lam_uv,
+                        const double* lam_dir, tape_t* tp, double* g) {
   ray_result_t res;
-  trace_ray(F, S, pix, tp, 0, &res);
+  trace_ray(F, S, pix, sample, tp, 0, &res);
   if (!tp->entered) return;                                   /* straight camera ray */
   if (res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE)) return; /* rendered as 0 */
-  if (lam_uv[0] == 0.0 && lam_uv[1] == 0.0) return;
+  if (lam_uv[0] == 0.0 && lam_uv[1] == 0.0 && (!lam_dir || (lam_dir[0] == 0.0 && lam_dir[1] == 0.0 &&
+                                                            lam_dir[2] == 0.0)))
+    return;
   int N = tp->n_steps;
   double h = S->step;
   const double* xN = &tp->x[3 * N];
@@ -712,6 +850,13 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, const
   for (int i = 0; i < 3; ++i) {
     r[i] = lX[i] - S->wall_normal[i] * vl / vn;
     tau[i] = s * r[i];
+  }
+  if (lam_dir) {
+    /* the unit direction at the wall, d = v / |v|: dL/dv += (I - d d^T) dL/dd / |v| */
+    double len = sqrt(dot3(vN, vN)), d[3];
+    for (int i = 0; i < 3; ++i) d[i] = vN[i] / len;
+    double dl = dot3(d, lam_dir);
+    for (int i = 0; i < 3; ++i) tau[i] += (lam_dir[i] - d[i] * dl) / len;
   }
   const int quasi = S->tracer == OR_TRACER_QUASILINEAR;
   const double* x0 = &tp->x[0];
@@ -775,7 +920,7 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, const
 }
 
 int or_adjoint(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* dL_duv, double* grad) {
+               const double* dL_duv, const double* dL_ddir, double* grad) {
   if (check_args(F, S, pixel_ids, n_rays) || F->mode != OR_FIELD_GRID || !dL_duv || !grad) return -1;
   int64_t nvox = (int64_t)F->n[0] * F->n[1] * F->n[2];
   int nth = omp_get_max_threads();
@@ -796,8 +941,9 @@ int or_adjoint(const or_field* F, const or_scene* S, const int32_t* pixel_ids, i
     if (!fail) {
 #pragma omp for schedule(static, 16)
       for (int32_t r = 0; r < n_rays; ++r) {
-        int32_t pix = pixel_ids ? pixel_ids[r] : r;
-        adjoint_ray(F, S, pix, &dL_duv[2 * r], &tp, part[t]);
+        int32_t pix, sample;
+        ray_pixel(S, pixel_ids, n_rays, r, &pix, &sample);
+        adjoint_ray(F, S, pix, sample, &dL_duv[2 * r], dL_ddir ? &dL_ddir[3 * r] : NULL, &tp, part[t]);
       }
     }
     if (ok) tape_free(&tp);
@@ -840,11 +986,12 @@ static void force_tangent(const or_field* F, const sample_t* s, const double* dP
   for (int i = 0; i < 3; ++i) dD[i] += dd * s->grad[i] + eta * gd[i];
 }
 
-static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, const double* vf, tape_t* tp,
-                        double* out) {
+static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, const double* vf,
+                        tape_t* tp, double* out, double* out_dir) {
   ray_result_t res;
-  trace_ray(F, S, pix, tp, 0, &res);
+  trace_ray(F, S, pix, sample, tp, 0, &res);
   out[0] = out[1] = 0.0;
+  if (out_dir) out_dir[0] = out_dir[1] = out_dir[2] = 0.0;
   if (!tp->entered || (res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE))) return;
   double h = S->step;
   sample_t s0;
@@ -903,10 +1050,17 @@ static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, const
   for (int i = 0; i < 3; ++i) dX[i] = dx[i] + ds * v[i] + s * dv[i];
   out[0] = dot3(dX, S->wall_u);
   out[1] = dot3(dX, S->wall_v);
+  if (out_dir) {
+    /* d = v / |v|: dd = (I - d d^T) dv / |v| */
+    double len = sqrt(dot3(v, v)), d[3];
+    for (int i = 0; i < 3; ++i) d[i] = v[i] / len;
+    double dd = dot3(d, dv);
+    for (int i = 0; i < 3; ++i) out_dir[i] = (dv[i] - d[i] * dd) / len;
+  }
 }
 
 int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* vfield, double* duv_dot) {
+               const double* vfield, double* duv_dot, double* ddir_dot) {
   if (check_args(F, S, pixel_ids, n_rays) || F->mode != OR_FIELD_GRID || !vfield || !duv_dot) return -1;
   int fail = 0;
 #pragma omp parallel
@@ -920,8 +1074,9 @@ int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, i
 #pragma omp for schedule(dynamic, 16)
     for (int32_t r = 0; r < n_rays; ++r) {
       if (!ok) continue;
-      int32_t pix = pixel_ids ? pixel_ids[r] : r;
-      tangent_ray(F, S, pix, vfield, &tp, &duv_dot[2 * r]);
+      int32_t pix, sample;
+      ray_pixel(S, pixel_ids, n_rays, r, &pix, &sample);
+      tangent_ray(F, S, pix, sample, vfield, &tp, &duv_dot[2 * r], ddir_dot ? &ddir_dot[3 * r] : NULL);
     }
     if (ok) tape_free(&tp);
   }
@@ -931,19 +1086,17 @@ int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, i
 /* ------------------------------------------------------------------------------------ */
 /* Central finite differences of L_BOS with respect to single voxels                     */
 /* ------------------------------------------------------------------------------------ */
-/* Contribution of one ray to L_BOS: (I - I*)^2, optionally replaying a tape. */
-static double ray_loss(const or_field* F, const or_scene* S, int32_t pix, double target, tape_t* tp,
-                       int locked, int* tex) {
+/* Radiance of one ray (its sample of Eq. (2)), optionally replaying a tape. */
+static double ray_value(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, tape_t* tp, int locked,
+                        int* tex) {
   ray_result_t res;
-  trace_ray(F, S, pix, tp, locked, &res);
-  double I = 0.0;
-  if (!(res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE))) {
-    double dI[2];
-    int off;
-    I = wall_luminance(S, res.uv, tex, locked, dI, &off);
-  }
-  double r = I - target;
-  return r * r;
+  trace_ray(F, S, pix, sample, tp, locked, &res);
+  if (res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE)) return 0.0;
+  double dI[2], dId[3], d[3];
+  int off;
+  double len = sqrt(dot3(res.v, res.v));
+  for (int i = 0; i < 3; ++i) d[i] = res.v[i] / len;
+  return ray_radiance(S, res.uv, d, tex, locked, dI, dId, &off);
 }
 
 static int ray_touches(const or_field* F, const tape_t* tp, int64_t vox) {
@@ -966,8 +1119,9 @@ int or_fd_voxels(const or_field* F, const or_scene* S, const int32_t* pixel_ids,
   if (check_args(F, S, pixel_ids, n_rays) || F->mode != OR_FIELD_GRID || !target || !voxels || !fd ||
       n_vox < 0 || n_vox > 64 || !(h > 0.0) || !S->pattern)
     return -1;
-  /* pass 1: which rays can see which voxel */
-  uint64_t* mask = (uint64_t*)calloc((size_t)(n_rays > 0 ? n_rays : 1), sizeof(uint64_t));
+  const int32_t spp = S->spp, P = n_rays / spp;
+  /* pass 1: which pixels (through any of their rays) can see which voxel */
+  uint64_t* mask = (uint64_t*)calloc((size_t)(P > 0 ? P : 1), sizeof(uint64_t));
   if (!mask) return -3;
   int fail = 0;
 #pragma omp parallel
@@ -979,20 +1133,22 @@ int or_fd_voxels(const or_field* F, const or_scene* S, const int32_t* pixel_ids,
       fail = 1;
     }
 #pragma omp for schedule(dynamic, 64)
-    for (int32_t r = 0; r < n_rays; ++r) {
+    for (int32_t i = 0; i < P; ++i) {
       if (!ok) continue;
-      int32_t pix = pixel_ids ? pixel_ids[r] : r;
-      ray_result_t res;
-      trace_ray(F, S, pix, &tp, 0, &res);
+      int32_t pix = pixel_ids ? pixel_ids[i] : i;
       uint64_t m = 0;
-      for (int v = 0; v < n_vox; ++v)
-        if (ray_touches(F, &tp, voxels[v])) m |= (uint64_t)1 << v;
-      mask[r] = m;
+      for (int32_t smp = 0; smp < spp; ++smp) {
+        ray_result_t res;
+        trace_ray(F, S, pix, smp, &tp, 0, &res);
+        for (int v = 0; v < n_vox; ++v)
+          if (ray_touches(F, &tp, voxels[v])) m |= (uint64_t)1 << v;
+      }
+      mask[i] = m;
     }
     if (ok) tape_free(&tp);
   }
   if (fail) { free(mask); return -3; }
-  /* pass 2: perturbed traces of the touching rays only */
+  /* pass 2: perturbed pixel values (all samples) of the touching pixels only */
   for (int v = 0; v < n_vox; ++v) {
     double acc = 0.0;
 #pragma omp parallel reduction(+ : acc)
@@ -1003,20 +1159,23 @@ int or_fd_voxels(const or_field* F, const or_scene* S, const int32_t* pixel_ids,
       Fp.pert_index = voxels[v]; Fp.pert_value = h;
       Fm.pert_index = voxels[v]; Fm.pert_value = -h;
 #pragma omp for schedule(dynamic, 8)
-      for (int32_t r = 0; r < n_rays; ++r) {
-        if (!ok || !(mask[r] >> v & 1)) continue;
-        int32_t pix = pixel_ids ? pixel_ids[r] : r;
-        int tex[2];
-        if (locked) {
-          (void)ray_loss(F, S, pix, target[r], &tp, 0, tex); /* record branches */
-          double lp = ray_loss(&Fp, S, pix, target[r], &tp, 1, tex);
-          double lm = ray_loss(&Fm, S, pix, target[r], &tp, 1, tex);
-          acc += lp - lm;
-        } else {
-          double lp = ray_loss(&Fp, S, pix, target[r], NULL, 0, tex);
-          double lm = ray_loss(&Fm, S, pix, target[r], NULL, 0, tex);
-          acc += lp - lm;
+      for (int32_t i = 0; i < P; ++i) {
+        if (!ok || !(mask[i] >> v & 1)) continue;
+        int32_t pix = pixel_ids ? pixel_ids[i] : i;
+        double Ip = 0.0, Im = 0.0;
+        for (int32_t smp = 0; smp < spp; ++smp) {
+          int tex[2];
+          if (locked) {
+            (void)ray_value(F, S, pix, smp, &tp, 0, tex); /* record branches */
+            Ip += ray_value(&Fp, S, pix, smp, &tp, 1, tex);
+            Im += ray_value(&Fm, S, pix, smp, &tp, 1, tex);
+          } else {
+            Ip += ray_value(&Fp, S, pix, smp, NULL, 0, tex);
+            Im += ray_value(&Fm, S, pix, smp, NULL, 0, tex);
+          }
         }
+        double rp = Ip / spp - target[i], rm = Im / spp - target[i];
+        acc += rp * rp - rm * rm;
       }
       if (ok) tape_free(&tp);
     }

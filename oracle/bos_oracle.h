@@ -59,6 +59,13 @@ typedef struct {
   double step;           /* RK4 step h in the ray parameter t */
   int32_t max_steps;
   int32_t tracer;        /* OR_TRACER_* */
+  /* Eq. (2) pixel integral: spp rays per pixel (1: one ray through the pixel centre),
+     sub-pixel offsets from Philox-4x32-10 keyed by seed with the triangular filter;
+     radiometry != 0 weights each ray by |<n_w, v_w>| / |X_w - camera|. Rays are
+     sample-major: ray r = s * P + i is sample s of pixel i (pixel_ids[i] or i) of P. */
+  int32_t spp;
+  uint32_t seed;
+  int32_t radiometry;
   const double* pattern; /* [pat_h][pat_w], row 0 at the top */
 } or_scene;
 
@@ -91,7 +98,7 @@ int or_integrate_quasi(const or_field* F, const double* x0, const double* v0, do
    undeflected camera ray, step count and status. exit_xv (nullable) gets [x(3), v(3)]
    at the last integrated state. pixel_ids NULL means all width*height pixels. */
 int or_trace(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv);
+             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv, double* vdir);
 /* Wall luminance at each ray's hit and its derivative w.r.t. (u, v). status is updated
    with OR_RAY_OFF_PATTERN. */
 int or_render(const or_scene* S, const int32_t* pixel_ids, int32_t n_rays, const double* uv,
@@ -99,12 +106,29 @@ int or_render(const or_scene* S, const int32_t* pixel_ids, int32_t n_rays, const
 /* L_BOS = sum_j (image_j - target_j)^2 and dL/d(u, v) = 2 r_j dI/d(u, v). */
 int or_loss(const double* image, const double* target, const double* dI_duv, int32_t n,
             double* loss, double* dL_duv);
-/* Exact gradient of sum_j dL_duv_j . (u_j, v_j) w.r.t. every voxel, ADDED into grad. */
+/* Eq. (2) per pixel: image_i = (1/spp) sum_s I_r over the pixel's rays r = s P + i, with
+   I_r = L_wall(u, v) (times |<n_w, vdir>| / |X_w - camera| with radiometry); per ray
+   dI_duv = (1/spp) dI_r/d(u, v) and, with radiometry, dI_ddir = (1/spp) dI_r/d(vdir),
+   vdir the unit direction at the wall (may be NULL without radiometry). */
+int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, const double* vdir, uint8_t* status,
+                     double* image, double* dI_duv, double* dI_ddir);
+/* L_BOS over pixels and per ray dL/d(u, v) = 2 r_i dI_duv (and dL/d vdir likewise). */
+int or_loss_pixels(const double* image, const double* target, int32_t n_pixels, int32_t spp, const double* dI_duv,
+                   const double* dI_ddir, double* loss, double* dL_duv, double* dL_ddir);
+/* Exact gradient of sum_r dL_duv_r . (u_r, v_r) + dL_ddir_r . vdir_r (dL_ddir may be NULL)
+   w.r.t. every voxel, ADDED into grad. */
 int or_adjoint(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* dL_duv, double* grad);
-/* Tangent-linear model: d(u, v)/d(delta) applied to the voxel perturbation vfield. */
+               const double* dL_duv, const double* dL_ddir, double* grad);
+/* Tangent-linear model: d(u, v)/d(delta) (and d vdir/d(delta), nullable) applied to the
+   voxel perturbation vfield. */
 int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* vfield, double* duv_dot);
+               const double* vfield, double* duv_dot, double* ddir_dot);
+/* Philox-4x32-10 (Salmon et al., SC'11) of a 128-bit counter under a 64-bit key. */
+int or_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+/* Sub-pixel offset (pixels, in [-1, 1]^2) of sample s of pixel p: two 24-bit uniforms from
+   Philox(counter (p, s, 0, 0), key (seed, 0)), each mapped through the inverse CDF of
+   the triangular filter. */
+int or_sample_offset(uint32_t seed, int32_t pixel, int32_t sample, double* ox, double* oy);
 /* Central finite differences of L_BOS w.r.t. single voxels. locked != 0 freezes every
    branch of the unperturbed run (interpolation cells, clamp flags, step counts, texel
    cells) so that the difference quotient sees only the smooth dependence. */

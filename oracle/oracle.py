@@ -44,6 +44,7 @@ class _Scene(C.Structure):
         ("proj_pos", D3), ("proj_fwd", D3), ("proj_right", D3), ("proj_up", D3),
         ("proj_fov_x_deg", C.c_double),
         ("step", C.c_double), ("max_steps", C.c_int32), ("tracer", C.c_int32),
+        ("spp", C.c_int32), ("seed", C.c_uint32), ("radiometry", C.c_int32),
         ("pattern", C.POINTER(C.c_double)),
     ]
 
@@ -85,11 +86,15 @@ def load():
             "or_camera_ray": [P, C.c_int32, P, P],
             "or_integrate": [P, P, P, C.c_double, C.c_int32, P, P],
             "or_integrate_quasi": [P, P, P, C.c_double, C.c_int32, P, P],
-            "or_trace": [P, P, P, C.c_int32, P, P, P, P, P],
+            "or_trace": [P, P, P, C.c_int32, P, P, P, P, P, P],
             "or_render": [P, P, C.c_int32, P, P, P, P],
+            "or_render_pixels": [P, C.c_int32, P, P, P, P, P, P],
             "or_loss": [P, P, P, C.c_int32, P, P],
-            "or_adjoint": [P, P, P, C.c_int32, P, P],
-            "or_tangent": [P, P, P, C.c_int32, P, P],
+            "or_loss_pixels": [P, P, C.c_int32, C.c_int32, P, P, P, P, P],
+            "or_adjoint": [P, P, P, C.c_int32, P, P, P],
+            "or_tangent": [P, P, P, C.c_int32, P, P, P],
+            "or_philox4x32": [P, P, P],
+            "or_sample_offset": [C.c_uint32, C.c_int32, C.c_int32, P, P],
             "or_fd_voxels": [P, P, P, C.c_int32, P, P, C.c_int32, C.c_double, C.c_int32, P],
         }.items():
             fn = getattr(lib, name)
@@ -175,6 +180,9 @@ class _SceneHolder:
         s.step = scene.step
         s.max_steps = scene.max_steps
         s.tracer = getattr(scene, "tracer", TRACER_NONLINEAR)
+        s.spp = getattr(scene, "spp", 1)
+        s.seed = getattr(scene, "seed", 0)
+        s.radiometry = getattr(scene, "radiometry", 0)
         self.pattern = None
         if pattern is not None:
             p = np.ascontiguousarray(pattern, dtype=np.float64)
@@ -189,10 +197,12 @@ class _SceneHolder:
 
 
 def _ids(scene, pixel_ids):
+    """(pixel id array or None, number of rays = samples per pixel x pixels)."""
+    spp = getattr(scene, "spp", 1)
     if pixel_ids is None:
-        return None, scene.width * scene.height
+        return None, scene.width * scene.height * spp
     ids = np.ascontiguousarray(pixel_ids, dtype=np.int32)
-    return ids, int(ids.size)
+    return ids, int(ids.size) * spp
 
 
 # --- Sec. 2.A ---------------------------------------------------------------------------
@@ -259,17 +269,19 @@ def integrate(field: Field, x0, v0, h: float, nsteps: int, quasi: bool = False):
 # --- forward, render, loss -----------------------------------------------------------------
 
 def trace(field: Field, scene, pixel_ids=None, want_exit=False):
-    """Returns dict(uv, duv, n_steps, status[, exit_xv]) per ray."""
+    """Returns dict(uv, duv, n_steps, status, vdir[, exit_xv]) per ray (ray r = sample
+    r // P of pixel r % P; vdir the unit direction at the wall)."""
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, None)
     uv = np.empty((n, 2))
     duv = np.empty((n, 2))
     ns = np.empty(n, np.int32)
     st = np.empty(n, np.uint8)
+    vd = np.empty((n, 3))
     ex = np.empty((n, 6)) if want_exit else None
     _check(load().or_trace(field.ref, sh.ref, _ptr(ids), n, _ptr(uv), _ptr(duv), _ptr(ns), _ptr(st),
-                           _ptr(ex)), "trace")
-    out = dict(uv=uv, duv=duv, n_steps=ns, status=st)
+                           _ptr(ex), _ptr(vd)), "trace")
+    out = dict(uv=uv, duv=duv, n_steps=ns, status=st, vdir=vd)
     if want_exit:
         out["exit_xv"] = ex
     return out
@@ -287,6 +299,52 @@ def render(scene, pattern: np.ndarray, uv: np.ndarray, status: np.ndarray):
     return img, dI, st
 
 
+def render_pixels(scene, pattern: np.ndarray, uv: np.ndarray, status: np.ndarray, vdir=None):
+    """Eq. (2) per pixel: (image [P], dI_duv [n_rays, 2], dI_ddir [n_rays, 3], status)."""
+    sh = _SceneHolder(scene, pattern)
+    uv = np.ascontiguousarray(uv, np.float64)
+    st = np.array(status, dtype=np.uint8, copy=True)
+    n = uv.shape[0]
+    spp = getattr(scene, "spp", 1)
+    P = n // spp
+    vd = None if vdir is None else np.ascontiguousarray(vdir, np.float64)
+    img = np.empty(P)
+    dI = np.empty((n, 2))
+    dId = np.empty((n, 3))
+    _check(load().or_render_pixels(sh.ref, P, _ptr(uv), _ptr(vd), _ptr(st), _ptr(img), _ptr(dI), _ptr(dId)),
+           "render_pixels")
+    return img, dI, dId, st
+
+
+def loss_pixels(image, target, spp, dI_duv, dI_ddir=None):
+    """L_BOS over pixels, and per ray dL/d(u, v) and dL/d(vdir)."""
+    image = np.ascontiguousarray(image, np.float64)
+    target = np.ascontiguousarray(target, np.float64)
+    dI_duv = np.ascontiguousarray(dI_duv, np.float64)
+    dId = None if dI_ddir is None else np.ascontiguousarray(dI_ddir, np.float64)
+    P = image.size
+    L = np.zeros(1)
+    g = np.empty((P * spp, 2))
+    gd = np.empty((P * spp, 3)) if dId is not None else None
+    _check(load().or_loss_pixels(_ptr(image), _ptr(target), P, spp, _ptr(dI_duv), _ptr(dId), _ptr(L), _ptr(g),
+                                 _ptr(gd)), "loss_pixels")
+    return float(L[0]), g, gd
+
+
+def philox4x32(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    _check(load().or_philox4x32(_ptr(c), _ptr(k), _ptr(out)), "philox")
+    return out
+
+
+def sample_offset(seed: int, pixel: int, sample: int):
+    ox, oy = C.c_double(), C.c_double()
+    _check(load().or_sample_offset(seed, pixel, sample, C.byref(ox), C.byref(oy)), "sample_offset")
+    return ox.value, oy.value
+
+
 def loss(image, target, dI_duv):
     image = np.ascontiguousarray(image, np.float64)
     target = np.ascontiguousarray(target, np.float64)
@@ -300,29 +358,31 @@ def loss(image, target, dI_duv):
 
 # --- derivatives ---------------------------------------------------------------------------
 
-def adjoint(field: Field, scene, dL_duv, pixel_ids=None, shape=None):
+def adjoint(field: Field, scene, dL_duv, pixel_ids=None, dL_ddir=None):
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, None)
     lam = np.ascontiguousarray(dL_duv, np.float64).reshape(n, 2)
+    lam_d = None if dL_ddir is None else np.ascontiguousarray(dL_ddir, np.float64).reshape(n, 3)
     nx, ny, nz = field.s.n
     g = np.zeros((nz, ny, nx))
-    _check(load().or_adjoint(field.ref, sh.ref, _ptr(ids), n, _ptr(lam), _ptr(g)), "adjoint")
+    _check(load().or_adjoint(field.ref, sh.ref, _ptr(ids), n, _ptr(lam), _ptr(lam_d), _ptr(g)), "adjoint")
     return g
 
 
-def tangent(field: Field, scene, vfield, pixel_ids=None):
+def tangent(field: Field, scene, vfield, pixel_ids=None, with_dir=False):
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, None)
     vf = np.ascontiguousarray(vfield, np.float64)
     out = np.empty((n, 2))
-    _check(load().or_tangent(field.ref, sh.ref, _ptr(ids), n, _ptr(vf), _ptr(out)), "tangent")
-    return out
+    od = np.empty((n, 3)) if with_dir else None
+    _check(load().or_tangent(field.ref, sh.ref, _ptr(ids), n, _ptr(vf), _ptr(out), _ptr(od)), "tangent")
+    return (out, od) if with_dir else out
 
 
 def fd_voxels(field: Field, scene, pattern, target, voxels, h=1e-7, locked=True, pixel_ids=None):
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, pattern)
-    tg = np.ascontiguousarray(target, np.float64).reshape(n)
+    tg = np.ascontiguousarray(target, np.float64).reshape(n // getattr(scene, "spp", 1))
     vx = np.ascontiguousarray(voxels, np.int64)
     out = np.empty(vx.size)
     _check(load().or_fd_voxels(field.ref, sh.ref, _ptr(ids), n, _ptr(tg), _ptr(vx), vx.size, h,
