@@ -194,7 +194,7 @@ class Workload:
                 self.fields.append(f)
                 self.descs.append(sc)
                 self.scenes.append(api.Scene(sc, f, pat))
-            self.targets = [torch.zeros(s.n_rays, device=dev) for s in self.scenes]
+            self.targets = [torch.zeros(s.n_pixels, device=dev) for s in self.scenes]
             self.data_note = "synthetic: 64 seeded plume fields; target image = 0"
             if args.tune:
                 from paper_2509_14442_amd import autotune

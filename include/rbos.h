@@ -10,9 +10,12 @@
  *     Sharma's three-stage Runge-Kutta-Nystrom scheme on the trilinear interpolant of
  *     the cell-centred grid (clamped to the edge values outside the voxel centres);
  *     rays start at the box entry with |v| = eta, move straight outside the box;
- *   - Sec. 2.C, Eq. (2) with one ray through each pixel centre and the luminance term
- *     only: the back-wall hit is rendered as the printed texture or the pinhole
- *     projector's image (bilinear, zero outside);
+ *   - Sec. 2.C, Eq. (2): each pixel is the mean of spp rays cast through sub-pixel
+ *     points drawn from the triangular camera filter (one ray through the centre when
+ *     spp = 1); each ray carries the back wall's radiance at its hit, the printed
+ *     texture or the pinhole projector's image (bilinear, zero outside), optionally
+ *     weighted by |<n_w, v_w>| / |X_w - c| (wall normal n_w, unit direction v_w at the
+ *     wall, camera centre c);
  *   - Sec. 2.D: L_BOS = sum_j (I_flow^j - I^j(eta))^2, and its exact gradient with
  *     respect to eta - 1 at every voxel, back-propagated through the integrator from
  *     ray-state checkpoints (the gradient the paper obtains by automatic
@@ -24,6 +27,10 @@
  *     lo + (i + 1/2)(hi - lo)/n.
  *   - Pixel j = row * width + col, row 0 at the top of the image; the camera has a
  *     horizontal field of view and square pixels.
+ *   - A scene traces n_pixels pixels (pixel_ids[i], or pixel i of the full image) with
+ *     spp rays each: n_rays = n_pixels * spp rays, sample-major, ray r = s * n_pixels + i
+ *     being sample s of pixel i. Per-ray arrays hold n_rays entries, per-pixel arrays
+ *     (image, target) n_pixels.
  *   - Pointers marked [dev] are device memory owned by the caller. The library never
  *     allocates, frees or synchronises; every launch goes on the `stream` argument
  *     (a hipStream_t; NULL is the default stream), so all calls may be captured in a
@@ -46,7 +53,7 @@
 extern "C" {
 #endif
 
-#define RBOS_ABI_VERSION 1
+#define RBOS_ABI_VERSION 2
 
 typedef enum {
   RBOS_OK = 0,
@@ -96,8 +103,9 @@ typedef struct rbos_scene {
   double cam_pos[3], cam_fwd[3], cam_right[3], cam_up[3];
   double cam_fov_x_deg;
   int32_t width, height;
-  const int32_t* pixel_ids;      /* [dev] optional ray list (pixel ids); NULL: every pixel */
-  int32_t n_rays;                /* length of pixel_ids, or width*height when NULL */
+  const int32_t* pixel_ids;      /* [dev] optional pixel list (ids in [0, width*height)); NULL:
+                                    every pixel */
+  int32_t n_pixels;              /* length of pixel_ids, or width*height when NULL */
   /* back wall: a plane through wall_origin with unit normal wall_normal (facing the
      camera); (wall_u, wall_v) orthonormal in-plane axes defining wall coordinates */
   double wall_origin[3], wall_normal[3], wall_u[3], wall_v[3];
@@ -119,9 +127,18 @@ typedef struct rbos_scene {
   int32_t ckpt_stride;
   int32_t tracer;                /* RBOS_TRACER_NONLINEAR / RBOS_TRACER_QUASILINEAR; all scenes
                                     of one call share it */
+  /* Eq. (2) pixel integral: spp rays per pixel (1 .. 1024; n_pixels * spp <= 2^30). With
+     spp > 1, sample s of pixel p goes through the pixel centre plus the offset (ox, oy)
+     (pixels; +y down the image): Philox-4x32-10 of the counter (p, s, 0, 0) under the key
+     (seed, 0) gives words x0, x1, the uniforms u = (x >> 8) 2^-24, and each offset is the
+     inverse CDF of the triangular density 1 - |x| on [-1, 1] at u. radiometry (0 or 1)
+     weights each ray's radiance by |<n_w, v_w>| / |X_w - c|. */
+  int32_t spp;
+  uint32_t seed;
+  int32_t radiometry;
 } rbos_scene;
 
-/* Per-scene forward outputs, indexed by ray r (pixel_ids[r], or pixel r). */
+/* Per-scene forward outputs, indexed by ray r = s * n_pixels + i. */
 typedef struct rbos_trace_out {
   float* wall_uv;    /* [dev] [n_rays][2] wall coordinates (u, v) of the hit, FP32-rounded */
   float* wall_duv;   /* [dev] [n_rays][2] (u, v) minus the undeflected camera ray's hit;
@@ -131,20 +148,27 @@ typedef struct rbos_trace_out {
   float* ckpt;       /* [dev] rbos_ckpt_bytes(scene) bytes of ray-state checkpoints,
                         written when scene.ckpt_stride > 0; opaque layout; must stay
                         unmodified until rbos_trace_adjoint has run */
+  float* wall_dir;   /* [dev] [n_rays][3] unit ray direction at the wall (the camera ray's
+                        for rays that miss the box; NaN for non-finite states); nullable,
+                        but rbos_render needs it when scene.radiometry is set */
 } rbos_trace_out;
 
 /* Per-scene render inputs/outputs. */
 typedef struct rbos_render_io {
-  const float* target;  /* [dev] [n_rays] measured image I_flow; nullable */
-  float* image;         /* [dev] [n_rays] rendered I(eta) */
-  float* dL_duv;        /* [dev] [n_rays][2] dL_BOS/d(u, v); needs target; nullable */
+  const float* target;  /* [dev] [n_pixels] measured image I_flow; nullable */
+  float* image;         /* [dev] [n_pixels] rendered I(eta) */
+  float* dL_duv;        /* [dev] [n_rays][2] dL_BOS/d(u, v) of each ray; needs target; nullable */
   float* loss;          /* [dev] one float: L_BOS of this scene; needs target; nullable */
+  float* dL_ddir;       /* [dev] [n_rays][3] dL_BOS/d(wall_dir) of each ray (the radiometric
+                           weight's dependence on the direction); needs target; required
+                           with dL_duv when scene.radiometry is set, ignored otherwise */
 } rbos_render_io;
 
 /* Per-scene adjoint inputs/outputs. */
 typedef struct rbos_adjoint_io {
   const float* dL_duv;  /* [dev] [n_rays][2] */
   double* grad;         /* [dev] [nz][ny][nx] FP64; the gradient w.r.t. eta - 1 is ADDED */
+  const float* dL_ddir; /* [dev] [n_rays][3] dL/d(wall_dir); nullable (no direction term) */
 } rbos_adjoint_io;
 
 /* Launch shape (nullable: library defaults). */
@@ -201,15 +225,16 @@ size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes);
 int rbos_trace_forward(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
                        const rbos_launch* launch, void* workspace, size_t ws_bytes, void* stream);
 
-/* Render the traced hits (wall luminance, bilinear) and, with a target, the residual,
-   L_BOS per scene (deterministic FP32 reduction) and dL_BOS/d(u, v). Also sets
-   RBOS_RAY_OFF_PATTERN in outs[s].status. */
+/* Render the traced hits (wall luminance, bilinear, times the radiometric weight when
+   set) and average each pixel's rays; with a target, the residual, L_BOS per scene
+   (deterministic FP32 reduction) and per ray dL_BOS/d(u, v) (and dL_BOS/d(wall_dir)).
+   Also sets RBOS_RAY_OFF_PATTERN in outs[s].status. */
 int rbos_render(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
                 const rbos_render_io* io, void* workspace, size_t ws_bytes, void* stream);
 
-/* Back-propagate dL/d(u, v) per ray through the wall step and every Sharma step
-   (replayed from the forward checkpoints) to dL/d(eta - 1) per voxel, accumulated in
-   FP64 into io[s].grad. Needs the same scenes (ckpt_stride > 0), the forward outputs and
+/* Back-propagate dL/d(u, v) (and dL/d(wall_dir)) per ray through the wall step and
+   every Sharma step (replayed from the forward checkpoints) to dL/d(eta - 1) per voxel,
+   accumulated in FP64 into io[s].grad. Needs the same scenes (ckpt_stride > 0), the forward outputs and
    the unmodified field. */
 int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
                        const rbos_adjoint_io* io, const rbos_launch* launch, void* workspace,

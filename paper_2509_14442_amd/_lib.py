@@ -30,7 +30,7 @@ class rbos_scene(C.Structure):
         ("cam_pos", D3), ("cam_fwd", D3), ("cam_right", D3), ("cam_up", D3),
         ("cam_fov_x_deg", C.c_double),
         ("width", C.c_int32), ("height", C.c_int32),
-        ("pixel_ids", C.c_void_p), ("n_rays", C.c_int32),
+        ("pixel_ids", C.c_void_p), ("n_pixels", C.c_int32),
         ("wall_origin", D3), ("wall_normal", D3), ("wall_u", D3), ("wall_v", D3),
         ("wall_mode", C.c_int32),
         ("pattern", C.c_void_p), ("pat_w", C.c_int32), ("pat_h", C.c_int32),
@@ -38,20 +38,22 @@ class rbos_scene(C.Structure):
         ("proj_pos", D3), ("proj_fwd", D3), ("proj_right", D3), ("proj_up", D3),
         ("proj_fov_x_deg", C.c_double),
         ("step", C.c_double), ("max_steps", C.c_int32), ("ckpt_stride", C.c_int32), ("tracer", C.c_int32),
+        ("spp", C.c_int32), ("seed", C.c_uint32), ("radiometry", C.c_int32),
     ]
 
 
 class rbos_trace_out(C.Structure):
     _fields_ = [("wall_uv", C.c_void_p), ("wall_duv", C.c_void_p), ("n_steps", C.c_void_p),
-                ("status", C.c_void_p), ("ckpt", C.c_void_p)]
+                ("status", C.c_void_p), ("ckpt", C.c_void_p), ("wall_dir", C.c_void_p)]
 
 
 class rbos_render_io(C.Structure):
-    _fields_ = [("target", C.c_void_p), ("image", C.c_void_p), ("dL_duv", C.c_void_p), ("loss", C.c_void_p)]
+    _fields_ = [("target", C.c_void_p), ("image", C.c_void_p), ("dL_duv", C.c_void_p), ("loss", C.c_void_p),
+                ("dL_ddir", C.c_void_p)]
 
 
 class rbos_adjoint_io(C.Structure):
-    _fields_ = [("dL_duv", C.c_void_p), ("grad", C.c_void_p)]
+    _fields_ = [("dL_duv", C.c_void_p), ("grad", C.c_void_p), ("dL_ddir", C.c_void_p)]
 
 
 class rbos_launch(C.Structure):

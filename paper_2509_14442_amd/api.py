@@ -132,10 +132,10 @@ class Scene:
         if pixel_ids is not None:
             pixel_ids = pixel_ids.to(device=field.buf.device, dtype=torch.int32).contiguous()
             s.pixel_ids = pixel_ids.data_ptr() if pixel_ids.numel() else field.buf.data_ptr()
-            s.n_rays = pixel_ids.numel()
+            s.n_pixels = pixel_ids.numel()
         else:
             s.pixel_ids = None
-            s.n_rays = desc.width * desc.height
+            s.n_pixels = desc.width * desc.height
         s.wall_origin, s.wall_normal = _vec(desc.wall_origin), _vec(desc.wall_normal)
         s.wall_u, s.wall_v = _vec(desc.wall_u), _vec(desc.wall_v)
         s.wall_mode = desc.wall_mode
@@ -153,12 +153,18 @@ class Scene:
         s.max_steps = desc.max_steps
         s.ckpt_stride = desc.ckpt_stride if ckpt_stride is None else int(ckpt_stride)
         s.tracer = int(getattr(desc, "tracer", L.RBOS_TRACER_NONLINEAR))
+        s.spp = int(getattr(desc, "spp", 1))
+        s.seed = int(getattr(desc, "seed", 0))
+        s.radiometry = int(getattr(desc, "radiometry", 0))
         self.struct = s
         self.desc = desc
         self.field = field
         self.pattern = pattern
         self.pixel_ids = pixel_ids
-        self.n_rays = int(s.n_rays)
+        self.n_pixels = int(s.n_pixels)
+        self.spp = int(s.spp)
+        self.n_rays = self.n_pixels * self.spp  # ray r = sample r // n_pixels of pixel r % n_pixels
+        self.radiometry = bool(s.radiometry)
         self.dims = field.dims
 
     def set_field(self, field: Field):
@@ -180,9 +186,10 @@ class Tracer:
     """Output buffers, workspace and the three ABI calls for a batch of scenes."""
 
     def __init__(self, scenes: List[Scene], launch: Optional[L.rbos_launch] = None, checkpoints: bool = True,
-                 adjoint_launch: Optional[L.rbos_launch] = None):
+                 adjoint_launch: Optional[L.rbos_launch] = None, want_dir: bool = False):
         """`launch` shapes the forward trace and, unless `adjoint_launch` is given, the
-        adjoint too (checkpoints are stored per ray, so the two may differ)."""
+        adjoint too (checkpoints are stored per ray, so the two may differ). Per-ray
+        buffers hold n_pixels * spp rays, sample-major; images hold n_pixels values."""
         self.scenes = scenes
         self.n = len(scenes)
         self.launch = launch
@@ -191,7 +198,7 @@ class Tracer:
         dev = scenes[0].field.buf.device if scenes else torch.device("cuda")
         ws = lib().rbos_workspace_bytes(self._arr, self.n)
         self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
-        self.uv, self.duv, self.n_steps, self.status, self.ckpt = [], [], [], [], []
+        self.uv, self.duv, self.n_steps, self.status, self.ckpt, self.wall_dir = [], [], [], [], [], []
         self._outs = (L.rbos_trace_out * max(self.n, 1))()
         for i, s in enumerate(scenes):
             n = s.n_rays
@@ -199,12 +206,16 @@ class Tracer:
             self.duv.append(torch.empty((n, 2), dtype=torch.float32, device=dev))
             self.n_steps.append(torch.empty(n, dtype=torch.int32, device=dev))
             self.status.append(torch.empty(n, dtype=torch.uint8, device=dev))
+            # the wall direction: needed by the radiometric weight, kept when asked for
+            wd = torch.empty((n, 3), dtype=torch.float32, device=dev) if (s.radiometry or want_dir) else None
+            self.wall_dir.append(wd)
             cb = lib().rbos_ckpt_bytes(C.byref(self._arr[i])) if checkpoints else 0
             self.ckpt.append(torch.empty(max(cb // 4, 1), dtype=torch.float32, device=dev) if cb else None)
             o = self._outs[i]
             o.wall_uv, o.wall_duv = self.uv[i].data_ptr(), self.duv[i].data_ptr()
             o.n_steps, o.status = self.n_steps[i].data_ptr(), self.status[i].data_ptr()
             o.ckpt = self.ckpt[i].data_ptr() if self.ckpt[i] is not None else None
+            o.wall_dir = wd.data_ptr() if wd is not None else None
         if not checkpoints:
             for i in range(self.n):
                 self._arr[i].ckpt_stride = 0
@@ -235,20 +246,25 @@ class Tracer:
                want_grad)
         if getattr(self, "_render_key", None) != key:
             io = (L.rbos_render_io * max(self.n, 1))()
-            self.image, self.dL_duv, self.loss = [], [], []
+            self.image, self.dL_duv, self.dL_ddir, self.loss = [], [], [], []
             self._targets = []
             for i, s in enumerate(self.scenes):
-                img = torch.empty(s.n_rays, dtype=torch.float32, device=dev)
+                img = torch.empty(s.n_pixels, dtype=torch.float32, device=dev)
                 tgt = targets[i] if targets is not None else None
                 if tgt is not None:
                     tgt = tgt.to(device=dev, dtype=torch.float32).contiguous().reshape(-1)
+                    if tgt.numel() != s.n_pixels:
+                        raise ValueError(f"target has {tgt.numel()} values for {s.n_pixels} pixels")
                 g = (torch.empty((s.n_rays, 2), dtype=torch.float32, device=dev)
                      if (tgt is not None and want_grad) else None)
+                gd = (torch.empty((s.n_rays, 3), dtype=torch.float32, device=dev)
+                      if (g is not None and s.radiometry) else None)
                 lo = torch.zeros(1, dtype=torch.float32, device=dev) if tgt is not None else None
                 io[i].target, io[i].image = _ptr(tgt), _ptr(img)
-                io[i].dL_duv, io[i].loss = _ptr(g), _ptr(lo)
+                io[i].dL_duv, io[i].loss, io[i].dL_ddir = _ptr(g), _ptr(lo), _ptr(gd)
                 self.image.append(img)
                 self.dL_duv.append(g)
+                self.dL_ddir.append(gd)
                 self.loss.append(lo)
                 self._targets.append(tgt)
             self._render_io = io
@@ -258,10 +274,18 @@ class Tracer:
         return self
 
     def adjoint(self, grads: Optional[List[torch.Tensor]] = None, dL_duv: Optional[List[torch.Tensor]] = None,
-                zero: bool = True, stream=None) -> List[torch.Tensor]:
-        """dL/d(eta - 1) per scene (float64 [nz][ny][nx]); accumulates into `grads` if given."""
+                zero: bool = True, stream=None,
+                dL_ddir: Optional[List[Optional[torch.Tensor]]] = None) -> List[torch.Tensor]:
+        """dL/d(eta - 1) per scene (float64 [nz][ny][nx]); accumulates into `grads` if given.
+        Without explicit per-ray seeds, uses the last render's dL/d(u, v) (and, with the
+        radiometric weight, dL/d(direction))."""
         dev = self.workspace.device
-        dL = dL_duv if dL_duv is not None else self.dL_duv
+        if dL_duv is None:
+            dL = self.dL_duv
+            if dL_ddir is None:
+                dL_ddir = getattr(self, "dL_ddir", None)
+        else:
+            dL = dL_duv
         if grads is None:
             grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device=dev) for s in self.scenes]
         elif zero:
@@ -273,6 +297,11 @@ class Tracer:
             d = dL[i].to(device=dev, dtype=torch.float32).contiguous()
             keep.append(d)
             io[i].dL_duv, io[i].grad = _ptr(d), _ptr(grads[i])
+            dd = dL_ddir[i] if dL_ddir is not None else None
+            if dd is not None:
+                dd = dd.to(device=dev, dtype=torch.float32).contiguous()
+                keep.append(dd)
+            io[i].dL_ddir = _ptr(dd)
         L.check(lib().rbos_trace_adjoint(self._arr, self.n, self._outs, io, self._adjoint_launch_ptr(),
                                          _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
         self._keep_adj = keep
@@ -282,7 +311,7 @@ class Tracer:
 class BOSLoss(torch.autograd.Function):
     """L_BOS(eta - 1) for one scene, with the hand-written adjoint as its backward.
 
-    forward(delta [nz][ny][nx] float32, tracer, target [n_rays]) -> scalar loss.
+    forward(delta [nz][ny][nx] float32, tracer, target [n_pixels]) -> scalar loss.
     The tracer's scene must use an FP32 field whose buffer this function re-encodes."""
 
     @staticmethod

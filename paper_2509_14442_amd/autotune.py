@@ -100,7 +100,7 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
         hbm_budget = int(free * 0.5)
     if targets is None:
         targets = [None] * len(scenes)
-    tg = [t if t is not None else torch.zeros(s.n_rays, device="cuda") for t, s in zip(targets, scenes)]
+    tg = [t if t is not None else torch.zeros(s.n_pixels, device="cuda") for t, s in zip(targets, scenes)]
     adj = mode != "fwd"
 
     def tracer(fwd_t, adj_t, stride):

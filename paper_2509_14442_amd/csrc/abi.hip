@@ -91,9 +91,14 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
     return fail(RBOS_E_RANGE, "scene %d: cam_fov_x_deg must be in (0, 179)", idx);
   if (S->width < 1 || S->height < 1 || (long long)S->width * S->height > (1LL << 30))
     return fail(RBOS_E_SHAPE, "scene %d: width and height must be >= 1 with width*height <= 2^30", idx);
-  if (!S->pixel_ids && (long long)S->n_rays != (long long)S->width * S->height)
-    return fail(RBOS_E_SHAPE, "scene %d: n_rays must equal width*height when pixel_ids is NULL", idx);
-  if (S->n_rays < 0) return fail(RBOS_E_SHAPE, "scene %d: n_rays < 0", idx);
+  if (!S->pixel_ids && (long long)S->n_pixels != (long long)S->width * S->height)
+    return fail(RBOS_E_SHAPE, "scene %d: n_pixels must equal width*height when pixel_ids is NULL", idx);
+  if (S->n_pixels < 0) return fail(RBOS_E_SHAPE, "scene %d: n_pixels < 0", idx);
+  if (S->spp < 1 || S->spp > 1024) return fail(RBOS_E_RANGE, "scene %d: spp must be in [1, 1024] (got %d)", idx, S->spp);
+  if ((long long)S->n_pixels * S->spp > (1LL << 30))
+    return fail(RBOS_E_SHAPE, "scene %d: n_pixels * spp must be <= 2^30", idx);
+  if (S->radiometry != 0 && S->radiometry != 1)
+    return fail(RBOS_E_RANGE, "scene %d: radiometry must be 0 or 1", idx);
   if (!finite3(S->wall_origin) || !orthonormal(S->wall_normal, S->wall_u, S->wall_v))
     return fail(RBOS_E_RANGE, "scene %d: wall origin must be finite and normal/u/v orthonormal", idx);
   if (S->wall_mode != RBOS_WALL_PRINTED && S->wall_mode != RBOS_WALL_PROJECTOR)
@@ -128,15 +133,20 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
   return RBOS_OK;
 }
 
-long long tiles_of(const rbos_scene* S, const Launch& L, int* tiles_x) {
+// tiles of one sample plane (the scene has spp planes)
+long long tiles_per_plane(const rbos_scene* S, const Launch& L, int* tiles_x) {
   if (S->pixel_ids) {
     *tiles_x = 0;
-    return ((long long)S->n_rays + 63) / 64;
+    return ((long long)S->n_pixels + 63) / 64;
   }
   int tx = (S->width + L.tile_w - 1) / L.tile_w;
   int ty = (S->height + L.tile_h - 1) / L.tile_h;
   *tiles_x = tx;
   return (long long)tx * ty;
+}
+
+long long tiles_of(const rbos_scene* S, const Launch& L, int* tiles_x) {
+  return tiles_per_plane(S, L, tiles_x) * (S->spp > 0 ? S->spp : 1);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -148,11 +158,17 @@ int ckpt_slots(const rbos_scene* S) {
   return (S->max_steps - 1) / S->ckpt_stride;
 }
 
-// entries per checkpoint component: the image in 8 x 8 pixel blocks, or the ray list
+// entries per checkpoint component and sample plane: the image in 8 x 8 pixel blocks
+long long ckpt_plane_entries(const rbos_scene* S) {
+  return (long long)((S->width + 7) / 8) * ((S->height + 7) / 8) * 64;
+}
+
+// entries per checkpoint component: spp image planes, or the ray list (all samples)
 // rounded up to 64
 long long ckpt_entries(const rbos_scene* S) {
-  if (S->pixel_ids) return ((long long)S->n_rays + 63) / 64 * 64;
-  return (long long)((S->width + 7) / 8) * ((S->height + 7) / 8) * 64;
+  const long long spp = S->spp > 0 ? S->spp : 1;
+  if (S->pixel_ids) return ((long long)S->n_pixels * spp + 63) / 64 * 64;
+  return ckpt_plane_entries(S) * spp;
 }
 
 struct Layout {
@@ -171,7 +187,7 @@ Layout layout(const rbos_scene* scenes, int n, const Launch& L) {
   for (int i = 0; i < n; ++i) {
     int tx;
     tiles += tiles_of(&scenes[i], L, &tx);
-    rblocks += ((long long)scenes[i].n_rays + 255) / 256;
+    rblocks += ((long long)scenes[i].n_pixels + 255) / 256;
   }
   y.total_tiles = tiles;
   y.total_render_blocks = (int)rblocks;
@@ -240,8 +256,13 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.width = S->width;
   d.height = S->height;
   d.pixel_ids = S->pixel_ids;
-  d.n_rays = S->n_rays;
+  d.n_pix = S->n_pixels;
+  d.spp = S->spp;
+  d.n_rays = S->n_pixels * S->spp;
+  d.seed = S->seed;
+  d.radiometry = S->radiometry;
   int tx;
+  d.tiles_plane = (int)tiles_per_plane(S, L, &tx);
   long long nt = tiles_of(S, L, &tx);
   d.tile_w = L.tile_w;
   d.tile_h = L.tile_h;
@@ -249,6 +270,7 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.n_tiles = (int)nt;
   d.tile_begin = tile_begin;
   d.ckpt_pad = ckpt_entries(S);
+  d.ckpt_plane = ckpt_plane_entries(S);
   d.ckpt_tx = (S->width + 7) / 8;
   d.wall_mode = S->wall_mode;
   d.pattern = S->pattern;
@@ -266,7 +288,7 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
     d.proj_inv_ty = to_df(1.0 / (tp * S->pat_h / S->pat_w));
   }
   d.render_block_begin = render_block_begin;
-  d.render_blocks = (int)(((long long)S->n_rays + 255) / 256);
+  d.render_blocks = (int)(((long long)S->n_pixels + 255) / 256);
   return d;
 }
 
@@ -286,6 +308,8 @@ int prepare(const rbos_scene* scenes, int32_t n_scenes, const rbos_launch* launc
   for (int i = 0; i < n_scenes; ++i) {
     rc = check_scene(&scenes[i], i, need_render);
     if (rc) return rc;
+    if (ckpt_entries(&scenes[i]) > (1LL << 31) - 1)
+      return fail(RBOS_E_SHAPE, "scene %d: too many checkpoint entries (8 x 8 blocks times spp)", i);
     if (scenes[i].dtype != scenes[0].dtype)
       return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one call must share the storage dtype", i);
     if (scenes[i].tracer != scenes[0].tracer)
@@ -386,7 +410,7 @@ int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, in
 }
 
 size_t rbos_ckpt_bytes(const rbos_scene* S) {
-  if (!S || S->ckpt_stride <= 0 || S->max_steps < 1 || S->n_rays < 0) return 0;
+  if (!S || S->ckpt_stride <= 0 || S->max_steps < 1 || S->n_pixels < 0 || S->spp < 1) return 0;
   // a per-ray header, then checkpoint slots for steps k, 2k, ... below max_steps
   // (6 floats per ray and slot; none for the quasi-linear tracer)
   return (rbos::RAY_HEADER + (size_t)ckpt_slots(S) * 6) * (size_t)ckpt_entries(S) * sizeof(float);
@@ -416,19 +440,18 @@ int rbos_trace_forward(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
   if (n_scenes > 0 && !outs) return fail(RBOS_E_NULL, "outs is NULL");
   for (int i = 0; i < n_scenes; ++i) {
     const rbos_trace_out& o = outs[i];
-    const bool rays = scenes[i].n_rays > 0;
+    const bool rays = scenes[i].n_pixels > 0;
     if (rays && (!o.wall_uv || !o.wall_duv || !o.n_steps || !o.status))
       return fail(RBOS_E_NULL, "scene %d: wall_uv, wall_duv, n_steps and status are required", i);
     if (rays && scenes[i].ckpt_stride > 0 && !o.ckpt)
       return fail(RBOS_E_NULL, "scene %d: ckpt_stride > 0 needs ckpt", i);
-    if (scenes[i].n_rays > 0 && scenes[i].pixel_ids == nullptr && scenes[i].n_rays != scenes[i].width * scenes[i].height)
-      return fail(RBOS_E_SHAPE, "scene %d: n_rays mismatch", i);
     SceneDev& d = P.table[i];
     d.uv = o.wall_uv;
     d.duv = o.wall_duv;
     d.n_steps = o.n_steps;
     d.status = o.status;
     d.ckpt = scenes[i].ckpt_stride > 0 ? o.ckpt : nullptr;
+    d.wall_dir = o.wall_dir;
   }
   if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
   rbos::LaunchPlan plan{};
@@ -448,18 +471,25 @@ int rbos_render(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out
   if (rc) return rc;
   if (n_scenes > 0 && (!outs || !io)) return fail(RBOS_E_NULL, "outs or io is NULL");
   for (int i = 0; i < n_scenes; ++i) {
-    const bool rays = scenes[i].n_rays > 0;
+    const bool rays = scenes[i].n_pixels > 0;
+    const bool radio = scenes[i].radiometry != 0;
     if (rays && (!outs[i].wall_duv || !outs[i].status))
       return fail(RBOS_E_NULL, "scene %d: wall_duv and status are required", i);
+    if (rays && radio && !outs[i].wall_dir)
+      return fail(RBOS_E_NULL, "scene %d: radiometry needs the forward's wall_dir", i);
     if (rays && !io[i].image) return fail(RBOS_E_NULL, "scene %d: image is required", i);
-    if ((io[i].dL_duv || io[i].loss) && !io[i].target)
-      return fail(RBOS_E_NULL, "scene %d: dL_duv and loss need a target", i);
+    if ((io[i].dL_duv || io[i].loss || io[i].dL_ddir) && !io[i].target)
+      return fail(RBOS_E_NULL, "scene %d: dL_duv, dL_ddir and loss need a target", i);
+    if (rays && radio && io[i].dL_duv && !io[i].dL_ddir)
+      return fail(RBOS_E_NULL, "scene %d: with radiometry, dL_duv needs dL_ddir as well", i);
     SceneDev& d = P.table[i];
     d.duv = outs[i].wall_duv;
     d.status = outs[i].status;
+    d.wall_dir = outs[i].wall_dir;
     d.target = io[i].target;
     d.image = io[i].image;
     d.dL_duv = io[i].dL_duv;
+    d.dL_ddir = radio ? io[i].dL_ddir : nullptr;
     d.loss = io[i].loss;
   }
   if (n_scenes == 0) return RBOS_OK;
@@ -484,7 +514,7 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
     if (scenes[i].ckpt_stride <= 0) return fail(RBOS_E_UNSUPPORTED, "scene %d: the adjoint needs ckpt_stride > 0", i);
     if (scenes[i].ckpt_stride != scenes[0].ckpt_stride)
       return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one adjoint call must share ckpt_stride", i);
-    const bool rays = scenes[i].n_rays > 0;
+    const bool rays = scenes[i].n_pixels > 0;
     if (rays && (!outs[i].ckpt || !outs[i].n_steps || !outs[i].status))
       return fail(RBOS_E_NULL, "scene %d: ckpt, n_steps and status are required", i);
     if (rays && !io[i].dL_duv) return fail(RBOS_E_NULL, "scene %d: dL_duv is required", i);
@@ -494,6 +524,7 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
     d.status = outs[i].status;
     d.ckpt = outs[i].ckpt;
     d.adj_dL_duv = io[i].dL_duv;
+    d.adj_dL_ddir = io[i].dL_ddir;
     d.grad = io[i].grad;
   }
   if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
@@ -516,26 +547,27 @@ size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields) {
            OFF(rbos_scene, box_hi), OFF(rbos_scene, dtype), OFF(rbos_scene, enc_scale), OFF(rbos_scene, enc_offset),
            OFF(rbos_scene, field), OFF(rbos_scene, cam_pos), OFF(rbos_scene, cam_fwd), OFF(rbos_scene, cam_right),
            OFF(rbos_scene, cam_up), OFF(rbos_scene, cam_fov_x_deg), OFF(rbos_scene, width), OFF(rbos_scene, height),
-           OFF(rbos_scene, pixel_ids), OFF(rbos_scene, n_rays), OFF(rbos_scene, wall_origin),
+           OFF(rbos_scene, pixel_ids), OFF(rbos_scene, n_pixels), OFF(rbos_scene, wall_origin),
            OFF(rbos_scene, wall_normal), OFF(rbos_scene, wall_u), OFF(rbos_scene, wall_v), OFF(rbos_scene, wall_mode),
            OFF(rbos_scene, pattern), OFF(rbos_scene, pat_w), OFF(rbos_scene, pat_h), OFF(rbos_scene, pat_extent_u),
            OFF(rbos_scene, pat_extent_v), OFF(rbos_scene, proj_pos), OFF(rbos_scene, proj_fwd),
            OFF(rbos_scene, proj_right), OFF(rbos_scene, proj_up), OFF(rbos_scene, proj_fov_x_deg),
-           OFF(rbos_scene, step), OFF(rbos_scene, max_steps), OFF(rbos_scene, ckpt_stride), OFF(rbos_scene, tracer)};
+           OFF(rbos_scene, step), OFF(rbos_scene, max_steps), OFF(rbos_scene, ckpt_stride), OFF(rbos_scene, tracer),
+           OFF(rbos_scene, spp), OFF(rbos_scene, seed), OFF(rbos_scene, radiometry)};
       sz = sizeof(rbos_scene);
       break;
     case 1:
       o = {OFF(rbos_trace_out, wall_uv), OFF(rbos_trace_out, wall_duv), OFF(rbos_trace_out, n_steps),
-           OFF(rbos_trace_out, status), OFF(rbos_trace_out, ckpt)};
+           OFF(rbos_trace_out, status), OFF(rbos_trace_out, ckpt), OFF(rbos_trace_out, wall_dir)};
       sz = sizeof(rbos_trace_out);
       break;
     case 2:
       o = {OFF(rbos_render_io, target), OFF(rbos_render_io, image), OFF(rbos_render_io, dL_duv),
-           OFF(rbos_render_io, loss)};
+           OFF(rbos_render_io, loss), OFF(rbos_render_io, dL_ddir)};
       sz = sizeof(rbos_render_io);
       break;
     case 3:
-      o = {OFF(rbos_adjoint_io, dL_duv), OFF(rbos_adjoint_io, grad)};
+      o = {OFF(rbos_adjoint_io, dL_duv), OFF(rbos_adjoint_io, grad), OFF(rbos_adjoint_io, dL_ddir)};
       sz = sizeof(rbos_adjoint_io);
       break;
     case 4:

@@ -144,8 +144,14 @@ struct SceneDev {
   df cam_cy;           // tan(fov_x / 2) * height / width
   int width, height;
   const int* pixel_ids;
-  int n_rays;
+  int n_pix;           // pixels traced (length of pixel_ids, or width * height)
+  int n_rays;          // n_pix * spp
+  int spp;             // rays per pixel (Eq. 2); ray r = s * n_pix + i
+  unsigned int seed;   // sub-pixel sample key
+  int radiometry;      // weight radiance by |<n_w, v_w>| / |X_w - c|
   int tile_w, tile_h, tiles_x, n_tiles, tile_begin;
+  int tiles_plane;     // tiles per sample plane
+  long long ckpt_plane;  // checkpoint entries per sample plane
   // wall
   df wall_org[3], wall_n[3], wall_u[3], wall_v[3];
   float wall_n_f[3], wall_u_f[3], wall_v_f[3], wall_org_f[3];
@@ -162,14 +168,17 @@ struct SceneDev {
   int* n_steps;
   unsigned char* status;
   float* ckpt;
+  float* wall_dir;
   // render io
   const float* target;
   float* image;
   float* dL_duv;
+  float* dL_ddir;
   float* loss;
   int render_block_begin, render_blocks;
   // adjoint io
   const float* adj_dL_duv;
+  const float* adj_dL_ddir;
   double* grad;
 };
 
@@ -210,29 +219,35 @@ __device__ __forceinline__ int find_scene(const SceneDev* scenes, int n_scenes, 
   return lo;
 }
 
-// Entry of ray r (pixel pix) in every checkpoint component: the image in 8 x 8 pixel
-// blocks, row-major over blocks and within a block, so the 64 rays of an 8 x 8 tile read
-// and write one contiguous 256-byte run; with a pixel-id list, r itself.
-__device__ __forceinline__ int ckpt_entry(const SceneDev& S, int r, int pix) {
+// Entry of ray r (pixel pix, sample s) in every checkpoint component: per sample plane,
+// the image in 8 x 8 pixel blocks, row-major over blocks and within a block, so the 64
+// rays of an 8 x 8 tile read and write one contiguous 256-byte run; with a pixel-id
+// list, r itself.
+__device__ __forceinline__ int ckpt_entry(const SceneDev& S, int r, int pix, int s) {
   if (S.pixel_ids) return r;
   const int row = pix / S.width, col = pix - row * S.width;
-  return (((row >> 3) * S.ckpt_tx + (col >> 3)) << 6) + ((row & 7) << 3) + (col & 7);
+  return (int)(s * S.ckpt_plane) + (((row >> 3) * S.ckpt_tx + (col >> 3)) << 6) + ((row & 7) << 3) + (col & 7);
 }
 
-// ray index r and pixel of lane `lane` in scene tile `tile`; false if none
-__device__ __forceinline__ bool tile_ray(const SceneDev& S, int tile, int lane, int& r, int& pix) {
+// Ray index r, pixel and sample of lane `lane` in scene tile `tile`; false if none. Tiles
+// are grouped by sample plane (every tile holds one sample of 64 neighbouring pixels),
+// so `s` is the same in every lane.
+__device__ __forceinline__ bool tile_ray(const SceneDev& S, int tile, int lane, int& r, int& pix, int& s) {
+  s = tile / S.tiles_plane;
+  const int t = tile - s * S.tiles_plane;
   if (S.pixel_ids) {
-    r = tile * 64 + lane;
-    if (r >= S.n_rays) return false;
-    pix = gld(S.pixel_ids + r);
+    const int i = t * 64 + lane;
+    if (i >= S.n_pix) return false;
+    pix = gld(S.pixel_ids + i);
+    r = s * S.n_pix + i;
     return true;
   }
-  int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
+  int tx = t % S.tiles_x, ty = t / S.tiles_x;
   int col = tx * S.tile_w + lane % S.tile_w;
   int row = ty * S.tile_h + lane / S.tile_w;
   if (col >= S.width || row >= S.height) return false;
-  r = row * S.width + col;
-  pix = r;
+  pix = row * S.width + col;
+  r = s * S.n_pix + pix;
   return true;
 }
 
@@ -247,10 +262,63 @@ struct Ray {
   df uv0[2];     // its wall coordinates
 };
 
-__device__ __forceinline__ void camera_ray(const SceneDev& S, int pix, df dir[3]) {
+// Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11) of the counter (c0, c1, 0, 0)
+// under the key (k0, 0); returns the first two output words. Each round multiplies the
+// even words by the two round constants, mixes the high halves with the odd words and
+// the key, and the key steps by the Weyl increments.
+__device__ __forceinline__ void philox2(unsigned int c0, unsigned int c1, unsigned int k0, unsigned int& x0,
+                                        unsigned int& x1) {
+  unsigned int c2 = 0u, c3 = 0u, k1 = 0u;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const unsigned int lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const unsigned int lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  x0 = c0;
+  x1 = c1;
+}
+
+// Inverse CDF of the triangular density 1 - |x| on [-1, 1] at a 24-bit uniform u. u, 2u
+// and 2 - 2u are exact in binary32; the one rounding of the square root moves the sample
+// by under 1e-7 pixel.
+__device__ __forceinline__ float tent_offset(unsigned int x) {
+  const float u = (float)(x >> 8) * 0x1p-24f;
+  return u < 0.5f ? sqrtf(2.0f * u) - 1.0f : 1.0f - sqrtf(2.0f - 2.0f * u);
+}
+
+// Image-plane coordinates 2 (col + 1/2 + ox) and 2 (row + 1/2 + oy) of sample s of pixel
+// pix, summed exactly in double-float. Kept out of line: it runs once per ray, and inlined
+// into the tracing kernels its temporaries raised their register allocation.
+struct df2 {
+  df x, y;
+};
+__device__ __attribute__((noinline)) df2 sample_point(int col, int row, unsigned int pix, unsigned int s,
+                                                     unsigned int seed) {
+  unsigned int x0, x1;
+  philox2(pix, s, seed, x0, x1);
+  return df2{dd_add_f(df{(float)(2 * col + 1), 0.0f}, 2.0f * tent_offset(x0)),
+             dd_add_f(df{(float)(2 * row + 1), 0.0f}, 2.0f * tent_offset(x1))};
+}
+
+// Camera ray of sample s of pixel pix: through the pixel centre with one sample per pixel,
+// else through the centre plus the sample's offset drawn from the triangular filter.
+__device__ __forceinline__ void camera_ray(const SceneDev& S, int pix, int s, df dir[3]) {
   int col = pix % S.width, row = pix / S.width;
-  df px = dd_sub(dd_mul_f(S.cam_ax, (float)(2 * col + 1)), S.cam_cx);
-  df py = dd_sub(S.cam_cy, dd_mul_f(S.cam_ax, (float)(2 * row + 1)));
+  df px, py;
+  if (S.spp == 1) {
+    px = dd_sub(dd_mul_f(S.cam_ax, (float)(2 * col + 1)), S.cam_cx);
+    py = dd_sub(S.cam_cy, dd_mul_f(S.cam_ax, (float)(2 * row + 1)));
+  } else {
+    const df2 q = sample_point(col, row, (unsigned int)pix, (unsigned int)s, S.seed);
+    px = dd_sub(dd_mul(S.cam_ax, q.x), S.cam_cx);
+    py = dd_sub(S.cam_cy, dd_mul(S.cam_ax, q.y));
+  }
   for (int a = 0; a < 3; ++a)
     dir[a] = dd_add(S.cam_fwd[a], dd_add(dd_mul(px, S.cam_right[a]), dd_mul(py, S.cam_up[a])));
   df len = dd_sqrt(dd_dot3(dir, dir));
@@ -293,19 +361,6 @@ __device__ __forceinline__ bool wall_hit_straight(const SceneDev& S, const df di
   uv[0] = dd_dot3(r, S.wall_u);
   uv[1] = dd_dot3(r, S.wall_v);
   return true;
-}
-
-__device__ __forceinline__ void setup_ray(const SceneDev& S, int pix, Ray& R) {
-  camera_ray(S, pix, R.dir);
-  R.wall0 = wall_hit_straight(S, R.dir, R.uv0);
-  df t_in;
-  R.entered = box_entry(S, R.dir, t_in);
-  if (R.entered) {
-    for (int a = 0; a < 3; ++a) {
-      df x = dd_add(S.cam_pos[a], dd_mul(t_in, R.dir[a]));
-      R.U0[a] = dd_add_f(dd_mul(dd_sub(x, S.lo[a]), S.inv_vox[a]), 0.5f);
-    }
-  }
 }
 
 // ------------------------------------------------------------------------------------

@@ -1,7 +1,8 @@
 // render.hip -- Sec. 2.C / 2.D: wall luminance at each traced hit (printed texture or
-// pinhole projector, bilinear, zero outside), residual against the measured image,
+// pinhole projector, bilinear, zero outside; optionally times the radiometric weight),
+// pixel values as the mean of their rays (Eq. 2), residual against the measured image,
 // L_BOS = sum_j r_j^2 (deterministic: per-block partials, then one fixed-order pass per
-// scene) and dL_BOS/d(u, v) = 2 r_j dI_j/d(u, v).
+// scene) and per ray dL_BOS/d(u, v) = 2 r_j dI_j/d(u, v).
 #include "rbos_device.hpp"
 #include "rbos_launch.hpp"
 
@@ -86,6 +87,59 @@ __device__ __forceinline__ float wall_luminance(const SceneDev& S, df u, df v, f
   return I;
 }
 
+// Radiance of ray r (its sample of Eq. 2) and its derivatives w.r.t. (u, v) and, with the
+// radiometric weight w = |<n_w, d>| / |X_w - c|, w.r.t. the unit direction d at the wall.
+// Sets RBOS_RAY_OFF_PATTERN in the status.
+__device__ __forceinline__ float ray_radiance(const SceneDev& S, int r, int pix, int smp, float dI[2], float dId[3]) {
+  dI[0] = dI[1] = 0.0f;
+  dId[0] = dId[1] = dId[2] = 0.0f;
+  const unsigned char st = gld(S.status + r);
+  if (st & (RAY_NO_WALL_HIT | RAY_NONFINITE)) return 0.0f;
+  df dir[3], uv0[2];
+  camera_ray(S, pix, smp, dir);
+  bool off = false;
+  float I = 0.0f;
+  df u = {0.0f, 0.0f}, v = {0.0f, 0.0f};
+  if (wall_hit_straight(S, dir, uv0)) {
+    u = dd_add_f(uv0[0], gld(S.duv + 2 * (size_t)r));
+    v = dd_add_f(uv0[1], gld(S.duv + 2 * (size_t)r + 1));
+    I = wall_luminance(S, u, v, dI, off);
+  } else {
+    off = true;
+  }
+  if (off) gst(S.status + r, (unsigned char)(st | RAY_OFF_PATTERN));
+  if (S.radiometry && !off) {
+    float R[3], d[3], R2 = 0.0f, c = 0.0f;
+    const float uf = dd_to_f(u), vf = dd_to_f(v);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R[k] = (S.wall_org_f[k] - dd_to_f(S.cam_pos[k])) + uf * S.wall_u_f[k] + vf * S.wall_v_f[k];
+      d[k] = gld(S.wall_dir + 3 * (size_t)r + k);
+      R2 += R[k] * R[k];
+      c += S.wall_n_f[k] * d[k];
+    }
+    const float inv_dist = 1.0f / sqrtf(R2), ac = fabsf(c), w = ac * inv_dist;
+    const float kk = -w * inv_dist * inv_dist;  // dw/dR = -|c| R / |R|^3
+    float Ru = 0.0f, Rv = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Ru += R[k] * S.wall_u_f[k];
+      Rv += R[k] * S.wall_v_f[k];
+    }
+    dI[0] = dI[0] * w + I * (kk * Ru);
+    dI[1] = dI[1] * w + I * (kk * Rv);
+    const float sg = c < 0.0f ? -inv_dist : inv_dist;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dId[k] = I * (sg * S.wall_n_f[k]);
+    I *= w;
+  }
+  return I;
+}
+
+// One thread per pixel: the mean of its spp rays (Eq. 2), the residual against the
+// target, and per ray dL/d(u, v) = 2 r dI_s/d(u, v) / spp (likewise dL/d(direction)).
+// The per-ray derivatives are stored divided by spp on the first pass and scaled by 2 r
+// once the pixel's value is known.
 __global__ __launch_bounds__(256) void k_render(const SceneDev* __restrict__ scenes, int n_scenes,
                                                 int total_blocks, float* __restrict__ partials) {
   __shared__ float red[4];
@@ -101,32 +155,43 @@ __global__ __launch_bounds__(256) void k_render(const SceneDev* __restrict__ sce
     si = lo;
   }
   const SceneDev& S = scenes[si];
-  const int r = (blk - S.render_block_begin) * 256 + threadIdx.x;
+  const int i = (blk - S.render_block_begin) * 256 + threadIdx.x;
   float res2 = 0.0f;
-  if (r < S.n_rays) {
-    const int pix = S.pixel_ids ? gld(S.pixel_ids + r) : r;
-    const unsigned char st = gld(S.status + r);
-    float I = 0.0f, dI[2] = {0.0f, 0.0f};
-    if (!(st & (RAY_NO_WALL_HIT | RAY_NONFINITE))) {
-      df dir[3], uv0[2];
-      camera_ray(S, pix, dir);
-      bool off = false;
-      if (wall_hit_straight(S, dir, uv0)) {
-        df u = dd_add_f(uv0[0], gld(S.duv + 2 * (size_t)r));
-        df v = dd_add_f(uv0[1], gld(S.duv + 2 * (size_t)r + 1));
-        I = wall_luminance(S, u, v, dI, off);
-      } else {
-        off = true;
+  if (i < S.n_pix) {
+    const int pix = S.pixel_ids ? gld(S.pixel_ids + i) : i;
+    const int spp = S.spp;
+    const bool grad = S.target && S.dL_duv;
+    const bool grad_dir = grad && S.radiometry && S.dL_ddir;
+    const float inv_spp = 1.0f / (float)spp;
+    float sum = 0.0f, dI[2], dId[3];
+    for (int smp = 0; smp < spp; ++smp) {
+      const int r = smp * S.n_pix + i;
+      sum += ray_radiance(S, r, pix, smp, dI, dId);
+      if (grad) {
+        gst(S.dL_duv + 2 * (size_t)r, dI[0] * inv_spp);
+        gst(S.dL_duv + 2 * (size_t)r + 1, dI[1] * inv_spp);
       }
-      if (off) gst(S.status + r, (unsigned char)(st | RAY_OFF_PATTERN));
+      if (grad_dir) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gst(S.dL_ddir + 3 * (size_t)r + k, dId[k] * inv_spp);
+      }
     }
-    gst(S.image + r, I);
+    const float I = spp == 1 ? sum : sum * inv_spp;
+    gst(S.image + i, I);
     if (S.target) {
-      float res = I - gld(S.target + r);
+      const float res = I - gld(S.target + i);
       res2 = res * res;
-      if (S.dL_duv) {
-        gst(S.dL_duv + 2 * (size_t)r, 2.0f * res * dI[0]);
-        gst(S.dL_duv + 2 * (size_t)r + 1, 2.0f * res * dI[1]);
+      const float g2 = 2.0f * res;
+      if (grad) {
+        for (int smp = 0; smp < spp; ++smp) {
+          const int r = smp * S.n_pix + i;
+          gst(S.dL_duv + 2 * (size_t)r, g2 * gld(S.dL_duv + 2 * (size_t)r));
+          gst(S.dL_duv + 2 * (size_t)r + 1, g2 * gld(S.dL_duv + 2 * (size_t)r + 1));
+          if (grad_dir) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gst(S.dL_ddir + 3 * (size_t)r + k, g2 * gld(S.dL_ddir + 3 * (size_t)r + k));
+          }
+        }
       }
     }
   }

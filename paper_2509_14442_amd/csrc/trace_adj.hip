@@ -260,30 +260,42 @@ __device__ __forceinline__ void adjoint_ray_setup(const SceneDev& S, int tile, i
   R.active = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) R.rb[a] = R.tb[a] = 0.0f;
-  if (!tile_ray(S, tile, lane, R.r, pix)) return;
+  int smp;
+  if (!tile_ray(S, tile, lane, R.r, pix, smp)) return;
   const int r = R.r;
-  R.q = ckpt_entry(S, r, pix);
+  R.q = ckpt_entry(S, r, pix, smp);
   R.n = gld(S.n_steps + r);
   const unsigned char st = gld(S.status + r);
   const float lu = gld(S.adj_dL_duv + 2 * (size_t)r), lv = gld(S.adj_dL_duv + 2 * (size_t)r + 1);
-  R.active = R.n > 0 && !(st & (RAY_NO_WALL_HIT | RAY_NONFINITE | RAY_MISSED_BOX)) && !(lu == 0.0f && lv == 0.0f);
+  float ld[3] = {0.0f, 0.0f, 0.0f};  // dL/d(unit direction at the wall)
+  if (S.adj_dL_ddir) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ld[a] = gld(S.adj_dL_ddir + 3 * (size_t)r + a);
+  }
+  const bool seed = !(lu == 0.0f && lv == 0.0f) || !(ld[0] == 0.0f && ld[1] == 0.0f && ld[2] == 0.0f);
+  R.active = R.n > 0 && !(st & (RAY_NO_WALL_HIT | RAY_NONFINITE | RAY_MISSED_BOX)) && seed;
   if (!R.active) return;
   float e_end[3], s;
   load_ray_header(S, R.q, R.B, e_end, s);
-  float v[3], lX[3], vn = 0.0f, vl = 0.0f;
+  float v[3], lX[3], vn = 0.0f, vl = 0.0f, v2 = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     v[a] = R.B.V[a] + e_end[a] * S.vox[a];
     lX[a] = lu * S.wall_u_f[a] + lv * S.wall_v_f[a];
     vn += v[a] * S.wall_n_f[a];
     vl += v[a] * lX[a];
+    v2 += v[a] * v[a];
   }
   const float qv = vl / vn;
+  // the direction v / |v| at the wall: its adjoint (ld - d (d . ld)) / |v| joins dL/dv
+  const float inv_v = 1.0f / sqrtf(v2);
+  const float dl = (v[0] * ld[0] + v[1] * ld[1] + v[2] * ld[2]) * inv_v;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float lx = lX[a] - S.wall_n_f[a] * qv;
+    const float lvd = (ld[a] - v[a] * inv_v * dl) * inv_v;
     R.rb[a] = lx * S.vox[a];
-    R.tb[a] = s * R.rb[a];
+    R.tb[a] = fmaf(lvd, S.vox[a], s * R.rb[a]);
   }
 }
 

@@ -10,7 +10,7 @@ namespace rbos {
 // store_ray_header), then the states (d, e) before steps k, 2k, ... (6 components per
 // slot).
 template <int DT, bool QL>
-__device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
+__device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int smp) {
   int n = 0;
   unsigned char status = 0;
   float uvd[2] = {0.0f, 0.0f};
@@ -18,9 +18,10 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   bool entered;
   RayBase B;
   Cell C;
+  float e_end[3] = {0.0f, 0.0f, 0.0f};  // velocity deviation of the last state
   {
     Ray R;
-    camera_ray(S, pix, R.dir);
+    camera_ray(S, pix, smp, R.dir);
     df t_in;
     entered = box_entry(S, R.dir, t_in);
     if (entered) {
@@ -40,7 +41,7 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
     // checkpoint slot s holds the state after (s + 1) K steps; kc counts down to the next
-    const int q = ckpt_entry(S, r, pix);
+    const int q = ckpt_entry(S, r, pix, smp);
     float* ck = S.ckpt ? S.ckpt + (size_t)RAY_HEADER * S.ckpt_pad + (size_t)q : nullptr;
     const size_t slot_stride = 6 * (size_t)S.ckpt_pad;
     int kc = S.ckpt_k;
@@ -75,10 +76,12 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
       }
     }
     if (!exited) status |= RAY_TRUNCATED;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e_end[a] = st.e[a];
     if (!(status & RAY_NONFINITE)) {
       float dX[3], s = 0.0f;
       const bool hit = wall_deflection(S, B, st, dX, &s);
-      if (ck) store_ray_header(S, ckpt_entry(S, r, pix), B, st, s);
+      if (ck) store_ray_header(S, ckpt_entry(S, r, pix, smp), B, st, s);
       if (hit) {
         uvd[0] = dX[0] * S.wall_u_f[0] + dX[1] * S.wall_u_f[1] + dX[2] * S.wall_u_f[2];
         uvd[1] = dX[0] * S.wall_v_f[0] + dX[1] * S.wall_v_f[1] + dX[2] * S.wall_v_f[2];
@@ -92,7 +95,7 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   }
   // the undeflected camera ray's wall hit, recomputed here rather than kept live
   df dir[3], uv0[2];
-  camera_ray(S, pix, dir);
+  camera_ray(S, pix, smp, dir);
   const bool wall0 = wall_hit_straight(S, dir, uv0);
   if (!wall0 && !(status & RAY_NONFINITE)) {
     // the camera ray itself never reaches the wall: treat the hit as missing
@@ -115,6 +118,29 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix) {
   }
   gst(S.n_steps + r, n);
   gst(S.status + r, status);
+  if (S.wall_dir) {
+    // unit direction at the wall: the exit velocity V + e (world units), or the camera
+    // ray's for rays that never enter the box
+    float w[3];
+    if (status & RAY_NONFINITE) {
+      w[0] = w[1] = w[2] = __builtin_nanf("");
+    } else if (entered) {
+      float n2 = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        w[a] = fmaf(e_end[a], S.vox[a], B.V[a]);
+        n2 = fmaf(w[a], w[a], n2);
+      }
+      const float inv = 1.0f / sqrtf(n2);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) w[a] *= inv;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) w[a] = dd_to_f(dir[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gst(S.wall_dir + 3 * (size_t)r + a, w[a]);
+  }
 }
 
 template <int DT, bool QL>
@@ -126,9 +152,9 @@ __global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ 
   const int si = find_scene(scenes, n_scenes, gtile);
   const SceneDev& S = scenes[si];
   const int tile = gtile - S.tile_begin;
-  int r, pix;
-  if (!tile_ray(S, tile, lane, r, pix)) return;
-  trace_one<DT, QL>(S, r, pix);
+  int r, pix, smp;
+  if (!tile_ray(S, tile, lane, r, pix, smp)) return;
+  trace_one<DT, QL>(S, r, pix, smp);
 }
 
 // Persistent form: blocks pull tiles from per-XCD queues (contiguous tile ranges), and
@@ -150,8 +176,8 @@ __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];
       const int tile = t - S.tile_begin;
-      int r, pix;
-      if (tile_ray(S, tile, lane, r, pix)) trace_one<DT, QL>(S, r, pix);
+      int r, pix, smp;
+      if (tile_ray(S, tile, lane, r, pix, smp)) trace_one<DT, QL>(S, r, pix, smp);
     }
   }
 }

@@ -29,7 +29,7 @@ def test_exports_match_header(lib):
     assert declared == set(L.EXPORTS)
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.rbos_version() == 1
+    assert lib.rbos_version() == int(re.search(r"#define RBOS_ABI_VERSION (\d+)", hdr).group(1)) == 2
 
 
 def test_struct_layouts_match(lib):
@@ -60,7 +60,8 @@ def _valid_scene():
     s.cam_right, s.cam_up = L.D3(1, 0, 0), L.D3(0, 0, 1)
     s.cam_fov_x_deg = 40.0
     s.width = s.height = 4
-    s.n_rays = 16
+    s.n_pixels = 16
+    s.spp = 1
     s.wall_origin, s.wall_normal = L.D3(0.5, 1.5, 0.5), L.D3(0, -1, 0)
     s.wall_u, s.wall_v = L.D3(1, 0, 0), L.D3(0, 0, 1)
     s.wall_mode = 0
@@ -87,7 +88,10 @@ def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
     (lambda s: setattr(s, "field", None), -1),
     (lambda s: setattr(s, "cam_fwd", L.D3(0, 1, 0.1)), -3),
     (lambda s: setattr(s, "cam_fov_x_deg", 0.0), -3),
-    (lambda s: setattr(s, "n_rays", 15), -2),
+    (lambda s: setattr(s, "n_pixels", 15), -2),
+    (lambda s: setattr(s, "spp", 0), -3),
+    (lambda s: setattr(s, "spp", 1025), -3),
+    (lambda s: setattr(s, "radiometry", 2), -3),
     (lambda s: setattr(s, "wall_normal", L.D3(0, -2, 0)), -3),
     (lambda s: setattr(s, "step", -1.0), -3),
     (lambda s: setattr(s, "step", 1.0), -3),
@@ -135,6 +139,20 @@ def test_render_and_adjoint_validation(lib):
     io = L.rbos_render_io(None, 0x8000, None, None)
     rc = lib.rbos_render(C.byref(s), 1, C.byref(outs), C.byref(io), C.c_void_p(0x100000), 1 << 20, None)
     assert rc == -1 and b"pattern" in lib.rbos_last_error()
+    # the radiometric weight needs the forward's wall directions, and its gradient a
+    # direction seed per ray
+    s = _valid_scene()
+    s.radiometry = 1
+    io = L.rbos_render_io(0x8800, 0x8000, None, None)
+    rc = lib.rbos_render(C.byref(s), 1, C.byref(outs), C.byref(io), C.c_void_p(0x100000), 1 << 20, None)
+    assert rc == -1 and b"wall_dir" in lib.rbos_last_error()
+    outs_d = L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0x7000, 0x7800)
+    io = L.rbos_render_io(0x8800, 0x8000, 0x9000, None)
+    rc = lib.rbos_render(C.byref(s), 1, C.byref(outs_d), C.byref(io), C.c_void_p(0x100000), 1 << 20, None)
+    assert rc == -1 and b"dL_ddir" in lib.rbos_last_error()
+    io = L.rbos_render_io(None, 0x8000, None, None, 0x9800)
+    rc = lib.rbos_render(C.byref(s), 1, C.byref(outs_d), C.byref(io), C.c_void_p(0x100000), 1 << 20, None)
+    assert rc == -1 and b"target" in lib.rbos_last_error()
     s = _valid_scene()
     s.ckpt_stride = 0
     aio = L.rbos_adjoint_io(0xa000, 0xb000)
@@ -162,9 +180,13 @@ def test_field_validation_and_sizes(lib):
     assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + ((64 - 1) // 16) * 6) * 64 * 4
     s.ckpt_stride = 1  # every step's state
     assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 64 * 4
-    s.width, s.height, s.n_rays = 17, 9, 17 * 9  # 3 x 2 blocks
+    s.width, s.height, s.n_pixels = 17, 9, 17 * 9  # 3 x 2 blocks
     assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 6 * 64 * 4
-    s.pixel_ids, s.n_rays = 0x40, 65  # ray list: 65 -> 128 entries
+    s.spp = 3  # one image plane per sample
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 3 * 6 * 64 * 4
+    s.pixel_ids, s.n_pixels = 0x40, 65  # pixel list: 65 x 3 rays -> 256 entries
+    assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 256 * 4
+    s.spp = 1  # 65 rays -> 128 entries
     assert lib.rbos_ckpt_bytes(C.byref(s)) == (19 + (64 - 1) * 6) * 128 * 4
     s.tracer = L.RBOS_TRACER_QUASILINEAR  # the quasi-linear adjoint needs only the ray header
     assert lib.rbos_ckpt_bytes(C.byref(s)) == 19 * 128 * 4
