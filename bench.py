@@ -56,6 +56,11 @@ def parse(argv=None):
     p.add_argument("--tracer", default="nonlinear", choices=list(TRACERS),
                    help="nonlinear (Eq. 1 coupled) or quasi-linear (forces on the straight entry line)")
     p.add_argument("--offset", type=float, default=0.0, help="16-bit code offset c (eta - 1 = c + q/s)")
+    p.add_argument("--spp", type=int, default=1,
+                   help="rays per pixel (Eq. 2 pixel integral over the triangular filter; 1 = pixel centres)")
+    p.add_argument("--radiometry", type=int, default=0, choices=[0, 1],
+                   help="weight each ray by |<n_w, v_w>| / |X_w - c|")
+    p.add_argument("--sample-seed", type=int, default=1, help="sub-pixel sample key")
     p.add_argument("--ckpt", type=int, default=8, help="checkpoint stride (steps)")
     p.add_argument("--tile", default="8x8", help="forward: rays per wavefront tile")
     p.add_argument("--wpb", type=int, default=4, help="forward: wavefronts per block")
@@ -113,7 +118,7 @@ def traffic_config(args, W) -> dict:
     """What the adjoint's counters depend on: workload, storage, stride and its launch."""
     l = W.adj_launch
     return {"workload": args.workload, "tracer": args.tracer, "dtype": args.dtype,
-            "ckpt_stride": str(W.ckpt_stride),
+            "ckpt_stride": str(W.ckpt_stride), "spp": str(args.spp), "radiometry": str(args.radiometry),
             "adj_launch": "%dx%d wpb %d persistent %d bpc %d" % (l.tile_w, l.tile_h, l.waves_per_block,
                                                                  l.persistent, l.blocks_per_cu)}
 
@@ -163,7 +168,8 @@ class Workload:
         self.temps, self.fields, self.scenes, self.descs = [], [], [], []
         if args.workload in ("room1m", "room256"):
             desc = (bi.scene_room_1m() if args.workload == "room1m" else bi.scene_room_256_3m()).replace(
-                ckpt_stride=args.ckpt, tracer=TRACERS[args.tracer])
+                ckpt_stride=args.ckpt, tracer=TRACERS[args.tracer], spp=args.spp, seed=args.sample_seed,
+                radiometry=args.radiometry)
             seed_a, seed_b = (3, 4) if args.workload == "room1m" else (5, 6)
             lo, hi, dims = desc.box_lo, desc.box_hi, desc.dims
             TA = bi.temperature_grid(bi.plumes_room(seed_a, lo, hi), lo, hi, dims).astype(np.float32)
@@ -186,7 +192,8 @@ class Workload:
             pat = torch.from_numpy(bi.blurred_noise(12, (1024, 1024)).astype(np.float32)).to(dev)
             self.pat = pat
             for sc, spec in bi.scenes_batch(64):
-                sc = sc.replace(ckpt_stride=args.ckpt, tracer=TRACERS[args.tracer])
+                sc = sc.replace(ckpt_stride=args.ckpt, tracer=TRACERS[args.tracer], spp=args.spp,
+                                seed=args.sample_seed, radiometry=args.radiometry)
                 T = torch.from_numpy(bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32))
                 T = T.to(dev)
                 f = api.Field.from_temperature(T, args.dtype, None, args.offset)
@@ -338,8 +345,10 @@ def main():
         "dtype": args.dtype,
         "data": W.data_note,
         "config": {
-            "workload": names[args.workload] + (", quasi-linear tracer" if args.tracer == "quasilinear" else ""),
-            "tracer": args.tracer,
+            "workload": names[args.workload] + (", quasi-linear tracer" if args.tracer == "quasilinear" else "")
+            + (", %d rays per pixel (triangular filter)" % args.spp if args.spp > 1 else "")
+            + (", radiometric weight" if args.radiometry else ""),
+            "tracer": args.tracer, "spp": args.spp, "radiometry": bool(args.radiometry),
             "storage": args.dtype, "offset": args.offset, "ckpt_stride": W.ckpt_stride,
             "fwd_launch": launch_desc(W.launch), "adj_launch": launch_desc(W.adj_launch),
             "graph": bool(args.graph),
@@ -378,8 +387,9 @@ def _stored_delta(T, dtype, scale, offset):
     return oracle.decode(oracle.encode(oracle.delta_from_temperature_f32(T), code, scale, offset), code, scale, offset)
 
 
-def _gpu_subset(W, ids, dL):
-    """GPU forward + adjoint restricted to the pixel ids, with the given dL/d(u, v)."""
+def _gpu_subset(W, ids, dL, dL_ddir=None):
+    """GPU forward + adjoint restricted to the pixel ids, with the given per-ray dL/d(u, v)
+    (and dL/d(direction))."""
     import torch
 
     from paper_2509_14442_amd import api
@@ -387,7 +397,8 @@ def _gpu_subset(W, ids, dL):
     sub = api.Tracer([api.Scene(W.descs[0], W.fields[0], W.pat, torch.from_numpy(ids).cuda())], W.launch,
                      adjoint_launch=W.adj_launch)
     sub.forward()
-    g = sub.adjoint(dL_duv=[torch.from_numpy(dL.astype("float32")).cuda()])[0]
+    dd = None if dL_ddir is None else [torch.from_numpy(dL_ddir.astype("float32")).cuda()]
+    g = sub.adjoint(dL_duv=[torch.from_numpy(dL.astype("float32")).cuda()], dL_ddir=dd)[0]
     torch.cuda.synchronize()
     return sub, g.cpu().numpy()
 
@@ -407,41 +418,52 @@ def cpu_baseline_and_errors(args, W):
     FA = oracle.grid_field(_stored_delta(W.TA_np, args.dtype, f.scale, args.offset), desc.box_lo, desc.box_hi)
     FB = oracle.grid_field(_stored_delta(W.TB_np, args.dtype, f.scale, args.offset), desc.box_lo, desc.box_hi)
 
+    spp = desc.spp
+
+    radio = bool(desc.radiometry)
+
     def run(ids):
         tb = oracle.trace(FB, desc, ids)
-        target, _, _ = oracle.render(desc, p64, tb["uv"], tb["status"])
+        target = oracle.render_pixels(desc, p64, tb["uv"], tb["status"], tb["vdir"], tb["path"])["image"]
         t0 = time.perf_counter()
         fa = oracle.trace(FA, desc, ids)
-        img, dI, st = oracle.render(desc, p64, fa["uv"], fa["status"])
-        L, dL = oracle.loss(img, target, dI)
-        g = oracle.adjoint(FA, desc, dL, ids)
+        rp = oracle.render_pixels(desc, p64, fa["uv"], fa["status"], fa["vdir"], fa["path"])
+        L, dL, dLd, dLp = oracle.loss_pixels(rp["image"], target, spp, rp["dI_duv"],
+                                             rp["dI_ddir"] if radio else None, rp["dI_dpath"] if radio else None)
+        g = oracle.adjoint(FA, desc, dL, ids, dL_ddir=dLd, dL_dpath=dLp)
+        fa["dL_ddir"] = dLd
         return time.perf_counter() - t0, fa, dL, g
 
     # calibrate on a small sample, then size the sample for ~cpu_seconds of oracle work
     probe = bi.strided_tiles(desc.width, desc.height, 8, 256, 7)
     dt, fa, _, _ = run(probe)
-    per_ray = dt / max(len(probe), 1)
-    n_target = int(args.cpu_seconds / max(per_ray, 1e-9))
+    per_pixel = dt / max(len(probe), 1)
+    n_target = int(args.cpu_seconds / max(per_pixel, 1e-9))
     total_tiles = ((desc.width + 7) // 8) * ((desc.height + 7) // 8)
     keep = max(1, int(total_tiles * 64 / max(n_target, 1)))
     ids = bi.strided_tiles(desc.width, desc.height, 8, keep, 3)
     dt, fa, dL, g_ref = run(ids)
     steps = int(fa["n_steps"].sum())
     cpu = {"value": steps / dt, "unit": "ray-steps/s", "cores": oracle.threads(), "kind": "oracle",
-           "sample": f"{len(ids)} rays (every {keep}th 8x8 tile of the 1024x1024 image), "
-                     f"{steps} ray-steps, fwd+render+loss+adjoint in FP64, {dt:.1f} s"}
+           "sample": f"{len(ids) * spp} rays ({spp} per pixel of 1 in {keep} 8x8 tiles of the 1024x1024 "
+                     f"image), {steps} ray-steps, fwd+render+loss+adjoint in FP64, {dt:.1f} s"}
     tr = W.tracer
-    uv = tr.uv[0].cpu().numpy().astype(np.float64)[ids]
-    duv = tr.duv[0].cpu().numpy().astype(np.float64)[ids]
-    ns = tr.n_steps[0].cpu().numpy()[ids]
+    rows = (np.arange(spp)[:, None] * (desc.width * desc.height) + ids[None, :]).ravel()
+    uv = tr.uv[0].cpu().numpy().astype(np.float64)[rows]
+    duv = tr.duv[0].cpu().numpy().astype(np.float64)[rows]
+    ns = tr.n_steps[0].cpu().numpy()[rows]
     ok = np.isfinite(fa["uv"][:, 0])
     e_uv = np.sqrt(((uv[ok] - fa["uv"][ok]) ** 2).sum(1))
     e_duv = np.sqrt(((duv[ok] - fa["duv"][ok]) ** 2).sum(1))
-    _, g = _gpu_subset(W, ids, dL)
+    _, g = _gpu_subset(W, ids, dL, fa["dL_ddir"])
+    if radio:
+        # the GPU is given the oracle's (u, v) and direction seeds: compare with the same
+        # map (the weight's path term is the oracle's own seed, outside the timed sample)
+        g_ref = oracle.adjoint(FA, desc, dL, ids, dL_ddir=fa["dL_ddir"])
     l2 = float(np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     bound = 1e-3 * np.maximum(np.abs(g_ref), 1e-2 * np.abs(g_ref).max())
     err = {
-        "sample_rays": int(len(ids)),
+        "sample_rays": int(len(rows)),
         "exit_err_max_m": float(e_uv.max()), "exit_err_rms_m": float(np.sqrt((e_uv ** 2).mean())),
         "exit_err_p99_m": float(np.percentile(e_uv, 99)),
         "deflection_err_max_m": float(e_duv.max()),
@@ -465,11 +487,12 @@ def subsample_errors(args, W):
     desc = W.descs[0]
     f = W.fields[0]
     ids = bi.pixel_subset(desc.width * desc.height, 4096, 15)
+    rows = (np.arange(desc.spp)[:, None] * (desc.width * desc.height) + ids[None, :]).ravel()
     rng = np.random.default_rng(16)
-    lam = rng.standard_normal((len(ids), 2))
+    lam = rng.standard_normal((len(rows), 2))
     _, g = _gpu_subset(W, ids, lam)
-    uv = W.tracer.uv[0].cpu().numpy().astype(np.float64)[ids]
-    out = {"sample_rays": int(len(ids)), "storage": args.dtype, "offset": args.offset, "scale": f.scale}
+    uv = W.tracer.uv[0].cpu().numpy().astype(np.float64)[rows]
+    out = {"sample_rays": int(len(rows)), "storage": args.dtype, "offset": args.offset, "scale": f.scale}
     exact = oracle.delta_from_temperature(W.TA_np)
     deq = _stored_delta(W.TA_np, args.dtype, f.scale, args.offset)
     for name, delta in (("vs_dequantised", deq), ("vs_exact", exact)):

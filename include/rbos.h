@@ -14,8 +14,10 @@
  *     points drawn from the triangular camera filter (one ray through the centre when
  *     spp = 1); each ray carries the back wall's radiance at its hit, the printed
  *     texture or the pinhole projector's image (bilinear, zero outside), optionally
- *     weighted by |<n_w, v_w>| / |X_w - c| (wall normal n_w, unit direction v_w at the
- *     wall, camera centre c);
+ *     weighted by |<n_w, v_w>| / ell (wall normal n_w, unit direction v_w at the wall,
+ *     ell the length of the ray path, evaluated as the distance |X_w - c| from the
+ *     camera centre c to the hit: the traced path is longer by a term of second order
+ *     in the deflection angle, ~1e-11 relative for air);
  *   - Sec. 2.D: L_BOS = sum_j (I_flow^j - I^j(eta))^2, and its exact gradient with
  *     respect to eta - 1 at every voxel, back-propagated through the integrator from
  *     ray-state checkpoints (the gradient the paper obtains by automatic

@@ -578,7 +578,20 @@ typedef struct {
   int32_t n_steps;
   uint8_t status;
   double x[3], v[3];   /* last integrated state (straight camera ray when missed) */
+  double path;         /* length of the ray path from the camera centre to the wall hit */
 } ray_result_t;
+
+static double dist3(const double* a, const double* b) {
+  double d[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  return sqrt(dot3(d, d));
+}
+
+/* unit vector from a to b */
+static void unit_from_to(const double* a, const double* b, double* u) {
+  double d[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+  double len = sqrt(dot3(d, d));
+  for (int i = 0; i < 3; ++i) u[i] = d[i] / len;
+}
 
 /* Trace one ray. With locked != 0 the tape's cells and step count are replayed. */
 static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, tape_t* tp, int locked,
@@ -587,6 +600,8 @@ static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t
   camera_ray(S, pix, sample, org, dir);
   out->status = 0;
   out->n_steps = 0;
+  out->path = NAN;
+  double path = 0.0; /* polyline through the camera centre, the box entry and every state */
   double X[3];
   out->uv0[0] = out->uv0[1] = NAN;
   if (wall_hit(S, org, dir, X, NULL)) wall_coords(S, X, out->uv0);
@@ -606,6 +621,7 @@ static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t
     if (tp && !locked) tp->cells[0] = s0.cell;
     for (int i = 0; i < 3; ++i) v[i] = (1.0 + s0.delta) * dir[i];
     if (tp) { memcpy(tp->x0, x, sizeof x); memcpy(&tp->x[0], x, sizeof x); memcpy(&tp->v[0], v, sizeof v); }
+    path = dist3(org, x);
     double x_in[3], v_in[3];
     memcpy(x_in, x, sizeof x);
     memcpy(v_in, v, sizeof v);
@@ -615,6 +631,7 @@ static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t
       double xn[3], vn[3];
       cell_t* lk = tp ? &tp->cells[1 + 3 * n] : NULL;
       ray_step(F, S, x_in, v_in, n, x, v, lk, locked, xn, vn, NULL);
+      path += dist3(x, xn);
       memcpy(x, xn, sizeof x);
       memcpy(v, vn, sizeof v);
       if (tp) { memcpy(&tp->x[3 * (n + 1)], x, sizeof x); memcpy(&tp->v[3 * (n + 1)], v, sizeof v); }
@@ -630,12 +647,16 @@ static void trace_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t
   memcpy(out->x, x, sizeof x);
   memcpy(out->v, v, sizeof v);
   if (out->status & OR_RAY_NONFINITE) { out->uv[0] = out->uv[1] = NAN; return; }
-  if (!wall_hit(S, x, v, X, NULL)) {
+  double s_w;
+  if (!wall_hit(S, x, v, X, &s_w)) {
     out->status |= OR_RAY_NO_WALL_HIT;
     out->uv[0] = out->uv[1] = NAN;
     return;
   }
   wall_coords(S, X, out->uv);
+  /* the straight continuation to the wall, signed: negative when the last step ended
+     past the wall plane (the wall on the box face), which takes the overshoot back */
+  out->path = path + s_w * sqrt(dot3(v, v));
 }
 
 static int check_args(const or_field* F, const or_scene* S, const int32_t* ids, int32_t n_rays) {
@@ -655,7 +676,8 @@ static void ray_pixel(const or_scene* S, const int32_t* ids, int32_t n_rays, int
 }
 
 int or_trace(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv, double* vdir) {
+             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv, double* vdir,
+             double* path) {
   if (check_args(F, S, pixel_ids, n_rays)) return -1;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t r = 0; r < n_rays; ++r) {
@@ -667,6 +689,7 @@ int or_trace(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int
       double len = sqrt(dot3(res.v, res.v));
       for (int i = 0; i < 3; ++i) vdir[3 * r + i] = res.v[i] / len;
     }
+    if (path) path[r] = res.path;
     if (uv) { uv[2 * r] = res.uv[0]; uv[2 * r + 1] = res.uv[1]; }
     if (duv) { duv[2 * r] = res.uv[0] - res.uv0[0]; duv[2 * r + 1] = res.uv[1] - res.uv0[1]; }
     if (n_steps) n_steps[r] = res.n_steps;
@@ -712,58 +735,57 @@ int or_loss(const double* image, const double* target, const double* dI_duv, int
   return 0;
 }
 
-/* Eq. (2) weight of a ray reaching the wall at (u, v) with unit direction d:
-   w = |<n_w, d>| / |X_w - c| (c the camera centre; the path length read as the distance
-   from the camera to the hit), and its derivatives w.r.t. (u, v) and d. */
-static double radiometric(const or_scene* S, const double* uv, const double* d, double* dw_duv, double* dw_dd) {
-  double r[3];
-  for (int i = 0; i < 3; ++i)
-    r[i] = S->wall_origin[i] + uv[0] * S->wall_u[i] + uv[1] * S->wall_v[i] - S->cam_pos[i];
-  double dist = sqrt(dot3(r, r)), c = dot3(S->wall_normal, d), ac = fabs(c);
-  double k = -ac / (dist * dist * dist);
-  dw_duv[0] = k * dot3(r, S->wall_u);
-  dw_duv[1] = k * dot3(r, S->wall_v);
+/* Eq. (2) weight of a ray reaching the wall with unit direction d after a path of length
+   ell: w = |<n_w, d>| / ell (the cosine between the wall normal and the direction, over
+   the length of the ray path), and its derivatives w.r.t. d and ell. */
+static double radiometric(const or_scene* S, const double* d, double ell, double* dw_dd, double* dw_dell) {
+  double c = dot3(S->wall_normal, d), w = fabs(c) / ell;
   double sg = c < 0.0 ? -1.0 : 1.0;
-  for (int i = 0; i < 3; ++i) dw_dd[i] = sg * S->wall_normal[i] / dist;
-  return ac / dist;
+  for (int i = 0; i < 3; ++i) dw_dd[i] = sg * S->wall_normal[i] / ell;
+  *dw_dell = -w / ell;
+  return w;
 }
 
 /* Radiance carried by one ray (the integrand of Eq. (2) for that sample) and its
-   derivatives w.r.t. (u, v) and the unit direction at the wall. */
-static double ray_radiance(const or_scene* S, const double* uv, const double* d, int* tex, int lock, double* dI,
-                           double* dId, int* off) {
+   derivatives w.r.t. (u, v), the unit direction at the wall and the path length. */
+static double ray_radiance(const or_scene* S, const double* uv, const double* d, double ell, int* tex, int lock,
+                           double* dI, double* dId, double* dIp, int* off) {
   double L = wall_luminance(S, uv, tex, lock, dI, off);
   dId[0] = dId[1] = dId[2] = 0.0;
+  *dIp = 0.0;
   if (!S->radiometry) return L;
-  double dw[2], dwd[3];
-  double w = radiometric(S, uv, d, dw, dwd);
-  dI[0] = dI[0] * w + L * dw[0];
-  dI[1] = dI[1] * w + L * dw[1];
+  double dwd[3], dwp;
+  double w = radiometric(S, d, ell, dwd, &dwp);
+  dI[0] *= w;
+  dI[1] *= w;
   for (int k = 0; k < 3; ++k) dId[k] = L * dwd[k];
+  *dIp = L * dwp;
   return L * w;
 }
 
-int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, const double* vdir, uint8_t* status,
-                     double* image, double* dI_duv, double* dI_ddir) {
+int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, const double* vdir, const double* path,
+                     uint8_t* status, double* image, double* dI_duv, double* dI_ddir, double* dI_dpath) {
   if (!S || !uv || !image || n_pixels < 0 || S->spp < 1 || !S->pattern || S->pat_w < 1 || S->pat_h < 1) return -1;
-  if (S->radiometry && !vdir) return -1;
+  if (S->radiometry && (!vdir || !path)) return -1;
   const int spp = S->spp;
 #pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n_pixels; ++i) {
     double sum = 0.0;
     for (int s = 0; s < spp; ++s) {
       int64_t r = (int64_t)s * n_pixels + i;
-      double dI[2] = {0.0, 0.0}, dId[3] = {0.0, 0.0, 0.0}, I = 0.0;
+      double dI[2] = {0.0, 0.0}, dId[3] = {0.0, 0.0, 0.0}, dIp = 0.0, I = 0.0;
       uint8_t st = status ? status[r] : 0;
       if (!(st & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE))) {
         int tex[2], off = 0;
-        I = ray_radiance(S, &uv[2 * r], vdir ? &vdir[3 * r] : NULL, tex, 0, dI, dId, &off);
+        I = ray_radiance(S, &uv[2 * r], vdir ? &vdir[3 * r] : NULL, path ? path[r] : 0.0, tex, 0, dI, dId, &dIp,
+                         &off);
         if (off && status) status[r] |= OR_RAY_OFF_PATTERN;
       }
       sum += I;
       if (dI_duv) { dI_duv[2 * r] = dI[0] / spp; dI_duv[2 * r + 1] = dI[1] / spp; }
       if (dI_ddir)
         for (int k = 0; k < 3; ++k) dI_ddir[3 * r + k] = dId[k] / spp;
+      if (dI_dpath) dI_dpath[r] = dIp / spp;
     }
     image[i] = sum / spp;
   }
@@ -771,7 +793,8 @@ int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, cons
 }
 
 int or_loss_pixels(const double* image, const double* target, int32_t n_pixels, int32_t spp, const double* dI_duv,
-                   const double* dI_ddir, double* loss, double* dL_duv, double* dL_ddir) {
+                   const double* dI_ddir, const double* dI_dpath, double* loss, double* dL_duv, double* dL_ddir,
+                   double* dL_dpath) {
   if (!image || !target || n_pixels < 0 || spp < 1) return -1;
   double L = 0.0;
   for (int32_t i = 0; i < n_pixels; ++i) {
@@ -785,6 +808,7 @@ int or_loss_pixels(const double* image, const double* target, int32_t n_pixels, 
       }
       if (dL_ddir && dI_ddir)
         for (int k = 0; k < 3; ++k) dL_ddir[3 * r + k] = 2.0 * res * dI_ddir[3 * r + k];
+      if (dL_dpath && dI_dpath) dL_dpath[r] = 2.0 * res * dI_dpath[r];
     }
   }
   if (loss) *loss = L;
@@ -826,15 +850,24 @@ static void scatter_value(const or_field* F, const sample_t* s, double scale, do
       }
 }
 
-/* Reverse one ray given lambda = dL/d(u, v). */
+/* dL/dx_n += lam_p (chat_{n-1} - chat_n) for a state 0 < n < N of the path polyline */
+static void path_adjoint(const tape_t* tp, int n, double lam_p, double* rx) {
+  if (lam_p == 0.0 || n == 0) return;
+  double a[3], b[3];
+  unit_from_to(&tp->x[3 * (n - 1)], &tp->x[3 * n], a);
+  unit_from_to(&tp->x[3 * n], &tp->x[3 * (n + 1)], b);
+  for (int i = 0; i < 3; ++i) rx[i] += lam_p * (a[i] - b[i]);
+}
+
+/* Reverse one ray given lambda = dL/d(u, v) (and dL/d direction, dL/d path length). */
 static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, const double* lam_uv,
-                        const double* lam_dir, tape_t* tp, double* g) {
+                        const double* lam_dir, double lam_p, tape_t* tp, double* g) {
   ray_result_t res;
   trace_ray(F, S, pix, sample, tp, 0, &res);
   if (!tp->entered) return;                                   /* straight camera ray */
   if (res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE)) return; /* rendered as 0 */
-  if (lam_uv[0] == 0.0 && lam_uv[1] == 0.0 && (!lam_dir || (lam_dir[0] == 0.0 && lam_dir[1] == 0.0 &&
-                                                            lam_dir[2] == 0.0)))
+  if (lam_uv[0] == 0.0 && lam_uv[1] == 0.0 && lam_p == 0.0 &&
+      (!lam_dir || (lam_dir[0] == 0.0 && lam_dir[1] == 0.0 && lam_dir[2] == 0.0)))
     return;
   int N = tp->n_steps;
   double h = S->step;
@@ -843,13 +876,28 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, int32
   /* wall step: X = x + s v; dX/dx = I - v n^T/(v.n), dX/dv = s dX/dx */
   double X[3], s;
   wall_hit(S, xN, vN, X, &s);
+  /* path = |x_0 - c| + sum_k |x_{k+1} - x_k| + s |v_N| with s |v_N| = (X - x_N).vhat_N:
+     its variation is vhat_N.(dX - dx_N) (vhat_N . d vhat_N = 0), so it adds lam_p vhat_N
+     to dL/dX and -lam_p vhat_N to dL/dx_N; every state k between adds
+     lam_p (chat_{k-1} - chat_k) (chat_k the unit chord from x_k to x_{k+1}); x_0 is fixed
+     by the camera */
+  double vhat[3];
+  {
+    double len = sqrt(dot3(vN, vN));
+    for (int i = 0; i < 3; ++i) vhat[i] = vN[i] / len;
+  }
   double lX[3];
-  for (int i = 0; i < 3; ++i) lX[i] = lam_uv[0] * S->wall_u[i] + lam_uv[1] * S->wall_v[i];
+  for (int i = 0; i < 3; ++i) lX[i] = lam_uv[0] * S->wall_u[i] + lam_uv[1] * S->wall_v[i] + lam_p * vhat[i];
   double vn = dot3(vN, S->wall_normal), vl = dot3(vN, lX);
   double r[3], tau[3];
   for (int i = 0; i < 3; ++i) {
     r[i] = lX[i] - S->wall_normal[i] * vl / vn;
     tau[i] = s * r[i];
+  }
+  if (lam_p != 0.0) {
+    double c_prev[3];
+    unit_from_to(&tp->x[3 * (N - 1)], xN, c_prev);
+    for (int i = 0; i < 3; ++i) r[i] += lam_p * (c_prev[i] - vhat[i]);
   }
   if (lam_dir) {
     /* the unit direction at the wall, d = v / |v|: dL/dv += (I - d d^T) dL/dd / |v| */
@@ -887,6 +935,7 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, int32
         scatter_force(F, &st.s[k], bars[k], h, g);
         axpy3(lv0, ts[k] * h, p);
       }
+      path_adjoint(tp, n, lam_p, rbar);
       memcpy(r, rbar, sizeof r);
       memcpy(tau, tbar, sizeof tau);
       continue;
@@ -909,6 +958,7 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, int32
     for (int i = 0; i < 3; ++i) p[i] *= h;
     scatter_force(F, &st.s[0], abar, h, g);
     axpy3(rbar, 1.0, p);
+    path_adjoint(tp, n, lam_p, rbar);
     memcpy(r, rbar, sizeof r);
     memcpy(tau, tbar, sizeof tau);
   }
@@ -920,7 +970,7 @@ static void adjoint_ray(const or_field* F, const or_scene* S, int32_t pix, int32
 }
 
 int or_adjoint(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* dL_duv, const double* dL_ddir, double* grad) {
+               const double* dL_duv, const double* dL_ddir, const double* dL_dpath, double* grad) {
   if (check_args(F, S, pixel_ids, n_rays) || F->mode != OR_FIELD_GRID || !dL_duv || !grad) return -1;
   int64_t nvox = (int64_t)F->n[0] * F->n[1] * F->n[2];
   int nth = omp_get_max_threads();
@@ -943,7 +993,8 @@ int or_adjoint(const or_field* F, const or_scene* S, const int32_t* pixel_ids, i
       for (int32_t r = 0; r < n_rays; ++r) {
         int32_t pix, sample;
         ray_pixel(S, pixel_ids, n_rays, r, &pix, &sample);
-        adjoint_ray(F, S, pix, sample, &dL_duv[2 * r], dL_ddir ? &dL_ddir[3 * r] : NULL, &tp, part[t]);
+        adjoint_ray(F, S, pix, sample, &dL_duv[2 * r], dL_ddir ? &dL_ddir[3 * r] : NULL, dL_dpath ? dL_dpath[r] : 0.0,
+                    &tp, part[t]);
       }
     }
     if (ok) tape_free(&tp);
@@ -987,11 +1038,13 @@ static void force_tangent(const or_field* F, const sample_t* s, const double* dP
 }
 
 static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, int32_t sample, const double* vf,
-                        tape_t* tp, double* out, double* out_dir) {
+                        tape_t* tp, double* out, double* out_dir, double* out_path) {
   ray_result_t res;
   trace_ray(F, S, pix, sample, tp, 0, &res);
   out[0] = out[1] = 0.0;
   if (out_dir) out_dir[0] = out_dir[1] = out_dir[2] = 0.0;
+  if (out_path) *out_path = 0.0;
+  double dpath = 0.0; /* sum_k chat_k . (dx_{k+1} - dx_k), dx_0 = 0 */
   if (!tp->entered || (res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE))) return;
   double h = S->step;
   sample_t s0;
@@ -1021,10 +1074,14 @@ static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, int32
         force_tangent(F, &st.s[k], dP, vf, dD);
         for (int i = 0; i < 3; ++i) dK[k][i] = h * dD[i];
       }
+      double c[3], dx_old[3];
+      memcpy(dx_old, dx, sizeof dx);
       for (int i = 0; i < 3; ++i) {
         dx[i] = dx[i] + h * (dv[i] + (dA[i] + 2.0 * dB[i]) / 6.0);
         dv[i] = dv[i] + (dA[i] + 4.0 * dB[i] + dC[i]) / 6.0;
       }
+      unit_from_to(&tp->x[3 * n], &tp->x[3 * (n + 1)], c);
+      for (int i = 0; i < 3; ++i) dpath += c[i] * (dx[i] - dx_old[i]);
       continue;
     }
     force_tangent(F, &st.s[0], dx, vf, dD);
@@ -1035,10 +1092,14 @@ static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, int32
     for (int i = 0; i < 3; ++i) dP[i] = dx[i] + h * dv[i] + 0.5 * h * dB[i];
     force_tangent(F, &st.s[2], dP, vf, dD);
     for (int i = 0; i < 3; ++i) dC[i] = h * dD[i];
+    double c[3], dx_old[3];
+    memcpy(dx_old, dx, sizeof dx);
     for (int i = 0; i < 3; ++i) {
       dx[i] = dx[i] + h * (dv[i] + (dA[i] + 2.0 * dB[i]) / 6.0);
       dv[i] = dv[i] + (dA[i] + 4.0 * dB[i] + dC[i]) / 6.0;
     }
+    unit_from_to(&tp->x[3 * n], &tp->x[3 * (n + 1)], c);
+    for (int i = 0; i < 3; ++i) dpath += c[i] * (dx[i] - dx_old[i]);
   }
   const double* x = &tp->x[3 * tp->n_steps];
   const double* v = &tp->v[3 * tp->n_steps];
@@ -1050,6 +1111,11 @@ static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, int32
   for (int i = 0; i < 3; ++i) dX[i] = dx[i] + ds * v[i] + s * dv[i];
   out[0] = dot3(dX, S->wall_u);
   out[1] = dot3(dX, S->wall_v);
+  if (out_path) {
+    double len = sqrt(dot3(v, v)), vhat[3];
+    for (int i = 0; i < 3; ++i) vhat[i] = v[i] / len;
+    *out_path = dpath + dot3(vhat, dX) - dot3(vhat, dx);
+  }
   if (out_dir) {
     /* d = v / |v|: dd = (I - d d^T) dv / |v| */
     double len = sqrt(dot3(v, v)), d[3];
@@ -1060,7 +1126,7 @@ static void tangent_ray(const or_field* F, const or_scene* S, int32_t pix, int32
 }
 
 int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* vfield, double* duv_dot, double* ddir_dot) {
+               const double* vfield, double* duv_dot, double* ddir_dot, double* dpath_dot) {
   if (check_args(F, S, pixel_ids, n_rays) || F->mode != OR_FIELD_GRID || !vfield || !duv_dot) return -1;
   int fail = 0;
 #pragma omp parallel
@@ -1076,7 +1142,8 @@ int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, i
       if (!ok) continue;
       int32_t pix, sample;
       ray_pixel(S, pixel_ids, n_rays, r, &pix, &sample);
-      tangent_ray(F, S, pix, sample, vfield, &tp, &duv_dot[2 * r], ddir_dot ? &ddir_dot[3 * r] : NULL);
+      tangent_ray(F, S, pix, sample, vfield, &tp, &duv_dot[2 * r], ddir_dot ? &ddir_dot[3 * r] : NULL,
+                  dpath_dot ? &dpath_dot[r] : NULL);
     }
     if (ok) tape_free(&tp);
   }
@@ -1092,11 +1159,11 @@ static double ray_value(const or_field* F, const or_scene* S, int32_t pix, int32
   ray_result_t res;
   trace_ray(F, S, pix, sample, tp, locked, &res);
   if (res.status & (OR_RAY_NO_WALL_HIT | OR_RAY_NONFINITE)) return 0.0;
-  double dI[2], dId[3], d[3];
+  double dI[2], dId[3], dIp, d[3];
   int off;
   double len = sqrt(dot3(res.v, res.v));
   for (int i = 0; i < 3; ++i) d[i] = res.v[i] / len;
-  return ray_radiance(S, res.uv, d, tex, locked, dI, dId, &off);
+  return ray_radiance(S, res.uv, d, res.path, tex, locked, dI, dId, &dIp, &off);
 }
 
 static int ray_touches(const or_field* F, const tape_t* tp, int64_t vox) {

@@ -61,8 +61,8 @@ typedef struct {
   int32_t tracer;        /* OR_TRACER_* */
   /* Eq. (2) pixel integral: spp rays per pixel (1: one ray through the pixel centre),
      sub-pixel offsets from Philox-4x32-10 keyed by seed with the triangular filter;
-     radiometry != 0 weights each ray by |<n_w, v_w>| / |X_w - camera|. Rays are
-     sample-major: ray r = s * P + i is sample s of pixel i (pixel_ids[i] or i) of P. */
+     radiometry != 0 weights each ray by |<n_w, v_w>| / (length of the ray path). Rays
+     are sample-major: ray r = s * P + i is sample s of pixel i (pixel_ids[i] or i). */
   int32_t spp;
   uint32_t seed;
   int32_t radiometry;
@@ -96,9 +96,14 @@ int or_integrate_quasi(const or_field* F, const double* x0, const double* v0, do
 
 /* Forward: per ray wall coordinates (u, v), deflection (u, v) - (u0, v0) against the
    undeflected camera ray, step count and status. exit_xv (nullable) gets [x(3), v(3)]
-   at the last integrated state. pixel_ids NULL means all width*height pixels. */
+   at the last integrated state, vdir (nullable) the unit direction at the wall, path
+   (nullable) the length of the ray path: the polyline from the camera centre through
+   the box entry and every integrated state, plus the signed straight continuation
+   s |v| to the wall hit (s < 0 when the last step ended past the wall plane). pixel_ids NULL means all
+   width*height pixels. */
 int or_trace(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv, double* vdir);
+             double* uv, double* duv, int32_t* n_steps, uint8_t* status, double* exit_xv, double* vdir,
+             double* path);
 /* Wall luminance at each ray's hit and its derivative w.r.t. (u, v). status is updated
    with OR_RAY_OFF_PATTERN. */
 int or_render(const or_scene* S, const int32_t* pixel_ids, int32_t n_rays, const double* uv,
@@ -107,22 +112,25 @@ int or_render(const or_scene* S, const int32_t* pixel_ids, int32_t n_rays, const
 int or_loss(const double* image, const double* target, const double* dI_duv, int32_t n,
             double* loss, double* dL_duv);
 /* Eq. (2) per pixel: image_i = (1/spp) sum_s I_r over the pixel's rays r = s P + i, with
-   I_r = L_wall(u, v) (times |<n_w, vdir>| / |X_w - camera| with radiometry); per ray
-   dI_duv = (1/spp) dI_r/d(u, v) and, with radiometry, dI_ddir = (1/spp) dI_r/d(vdir),
-   vdir the unit direction at the wall (may be NULL without radiometry). */
-int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, const double* vdir, uint8_t* status,
-                     double* image, double* dI_duv, double* dI_ddir);
-/* L_BOS over pixels and per ray dL/d(u, v) = 2 r_i dI_duv (and dL/d vdir likewise). */
+   I_r = L_wall(u, v) (times |<n_w, vdir>| / path with radiometry); per ray
+   dI_duv = (1/spp) dI_r/d(u, v) and, with radiometry, dI_ddir = (1/spp) dI_r/d(vdir) and
+   dI_dpath = (1/spp) dI_r/d(path), vdir and path from or_trace (both may be NULL
+   without radiometry). */
+int or_render_pixels(const or_scene* S, int32_t n_pixels, const double* uv, const double* vdir, const double* path,
+                     uint8_t* status, double* image, double* dI_duv, double* dI_ddir, double* dI_dpath);
+/* L_BOS over pixels and per ray dL/d(u, v) = 2 r_i dI_duv (dL/d vdir, dL/d path likewise;
+   each output nullable). */
 int or_loss_pixels(const double* image, const double* target, int32_t n_pixels, int32_t spp, const double* dI_duv,
-                   const double* dI_ddir, double* loss, double* dL_duv, double* dL_ddir);
-/* Exact gradient of sum_r dL_duv_r . (u_r, v_r) + dL_ddir_r . vdir_r (dL_ddir may be NULL)
-   w.r.t. every voxel, ADDED into grad. */
+                   const double* dI_ddir, const double* dI_dpath, double* loss, double* dL_duv, double* dL_ddir,
+                   double* dL_dpath);
+/* Exact gradient of sum_r dL_duv_r . (u_r, v_r) + dL_ddir_r . vdir_r + dL_dpath_r path_r
+   (dL_ddir, dL_dpath may be NULL) w.r.t. every voxel, ADDED into grad. */
 int or_adjoint(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* dL_duv, const double* dL_ddir, double* grad);
-/* Tangent-linear model: d(u, v)/d(delta) (and d vdir/d(delta), nullable) applied to the
-   voxel perturbation vfield. */
+               const double* dL_duv, const double* dL_ddir, const double* dL_dpath, double* grad);
+/* Tangent-linear model: d(u, v)/d(delta) (and d vdir/d(delta), d path/d(delta), both
+   nullable) applied to the voxel perturbation vfield. */
 int or_tangent(const or_field* F, const or_scene* S, const int32_t* pixel_ids, int32_t n_rays,
-               const double* vfield, double* duv_dot, double* ddir_dot);
+               const double* vfield, double* duv_dot, double* ddir_dot, double* dpath_dot);
 /* Philox-4x32-10 (Salmon et al., SC'11) of a 128-bit counter under a 64-bit key. */
 int or_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
 /* Sub-pixel offset (pixels, in [-1, 1]^2) of sample s of pixel p: two 24-bit uniforms from

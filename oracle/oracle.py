@@ -86,13 +86,13 @@ def load():
             "or_camera_ray": [P, C.c_int32, P, P],
             "or_integrate": [P, P, P, C.c_double, C.c_int32, P, P],
             "or_integrate_quasi": [P, P, P, C.c_double, C.c_int32, P, P],
-            "or_trace": [P, P, P, C.c_int32, P, P, P, P, P, P],
+            "or_trace": [P, P, P, C.c_int32, P, P, P, P, P, P, P],
             "or_render": [P, P, C.c_int32, P, P, P, P],
-            "or_render_pixels": [P, C.c_int32, P, P, P, P, P, P],
+            "or_render_pixels": [P, C.c_int32, P, P, P, P, P, P, P, P],
             "or_loss": [P, P, P, C.c_int32, P, P],
-            "or_loss_pixels": [P, P, C.c_int32, C.c_int32, P, P, P, P, P],
-            "or_adjoint": [P, P, P, C.c_int32, P, P, P],
-            "or_tangent": [P, P, P, C.c_int32, P, P, P],
+            "or_loss_pixels": [P, P, C.c_int32, C.c_int32, P, P, P, P, P, P, P],
+            "or_adjoint": [P, P, P, C.c_int32, P, P, P, P],
+            "or_tangent": [P, P, P, C.c_int32, P, P, P, P],
             "or_philox4x32": [P, P, P],
             "or_sample_offset": [C.c_uint32, C.c_int32, C.c_int32, P, P],
             "or_fd_voxels": [P, P, P, C.c_int32, P, P, C.c_int32, C.c_double, C.c_int32, P],
@@ -269,8 +269,9 @@ def integrate(field: Field, x0, v0, h: float, nsteps: int, quasi: bool = False):
 # --- forward, render, loss -----------------------------------------------------------------
 
 def trace(field: Field, scene, pixel_ids=None, want_exit=False):
-    """Returns dict(uv, duv, n_steps, status, vdir[, exit_xv]) per ray (ray r = sample
-    r // P of pixel r % P; vdir the unit direction at the wall)."""
+    """Returns dict(uv, duv, n_steps, status, vdir, path[, exit_xv]) per ray (ray r = sample
+    r // P of pixel r % P; vdir the unit direction at the wall, path the length of the
+    ray path from the camera centre to the wall hit)."""
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, None)
     uv = np.empty((n, 2))
@@ -278,10 +279,11 @@ def trace(field: Field, scene, pixel_ids=None, want_exit=False):
     ns = np.empty(n, np.int32)
     st = np.empty(n, np.uint8)
     vd = np.empty((n, 3))
+    pl = np.empty(n)
     ex = np.empty((n, 6)) if want_exit else None
     _check(load().or_trace(field.ref, sh.ref, _ptr(ids), n, _ptr(uv), _ptr(duv), _ptr(ns), _ptr(st),
-                           _ptr(ex), _ptr(vd)), "trace")
-    out = dict(uv=uv, duv=duv, n_steps=ns, status=st, vdir=vd)
+                           _ptr(ex), _ptr(vd), _ptr(pl)), "trace")
+    out = dict(uv=uv, duv=duv, n_steps=ns, status=st, vdir=vd, path=pl)
     if want_exit:
         out["exit_xv"] = ex
     return out
@@ -299,8 +301,9 @@ def render(scene, pattern: np.ndarray, uv: np.ndarray, status: np.ndarray):
     return img, dI, st
 
 
-def render_pixels(scene, pattern: np.ndarray, uv: np.ndarray, status: np.ndarray, vdir=None):
-    """Eq. (2) per pixel: (image [P], dI_duv [n_rays, 2], dI_ddir [n_rays, 3], status)."""
+def render_pixels(scene, pattern: np.ndarray, uv: np.ndarray, status: np.ndarray, vdir=None, path=None):
+    """Eq. (2) per pixel: dict(image [P], dI_duv [n_rays, 2], dI_ddir [n_rays, 3],
+    dI_dpath [n_rays], status)."""
     sh = _SceneHolder(scene, pattern)
     uv = np.ascontiguousarray(uv, np.float64)
     st = np.array(status, dtype=np.uint8, copy=True)
@@ -308,27 +311,32 @@ def render_pixels(scene, pattern: np.ndarray, uv: np.ndarray, status: np.ndarray
     spp = getattr(scene, "spp", 1)
     P = n // spp
     vd = None if vdir is None else np.ascontiguousarray(vdir, np.float64)
+    pl = None if path is None else np.ascontiguousarray(path, np.float64)
     img = np.empty(P)
     dI = np.empty((n, 2))
     dId = np.empty((n, 3))
-    _check(load().or_render_pixels(sh.ref, P, _ptr(uv), _ptr(vd), _ptr(st), _ptr(img), _ptr(dI), _ptr(dId)),
-           "render_pixels")
-    return img, dI, dId, st
+    dIp = np.empty(n)
+    _check(load().or_render_pixels(sh.ref, P, _ptr(uv), _ptr(vd), _ptr(pl), _ptr(st), _ptr(img), _ptr(dI),
+                                   _ptr(dId), _ptr(dIp)), "render_pixels")
+    return dict(image=img, dI_duv=dI, dI_ddir=dId, dI_dpath=dIp, status=st)
 
 
-def loss_pixels(image, target, spp, dI_duv, dI_ddir=None):
-    """L_BOS over pixels, and per ray dL/d(u, v) and dL/d(vdir)."""
+def loss_pixels(image, target, spp, dI_duv, dI_ddir=None, dI_dpath=None):
+    """L_BOS over pixels, and per ray dL/d(u, v), dL/d(vdir) and dL/d(path) (the last two
+    None when their inputs are)."""
     image = np.ascontiguousarray(image, np.float64)
     target = np.ascontiguousarray(target, np.float64)
     dI_duv = np.ascontiguousarray(dI_duv, np.float64)
     dId = None if dI_ddir is None else np.ascontiguousarray(dI_ddir, np.float64)
+    dIp = None if dI_dpath is None else np.ascontiguousarray(dI_dpath, np.float64)
     P = image.size
     L = np.zeros(1)
     g = np.empty((P * spp, 2))
     gd = np.empty((P * spp, 3)) if dId is not None else None
-    _check(load().or_loss_pixels(_ptr(image), _ptr(target), P, spp, _ptr(dI_duv), _ptr(dId), _ptr(L), _ptr(g),
-                                 _ptr(gd)), "loss_pixels")
-    return float(L[0]), g, gd
+    gp = np.empty(P * spp) if dIp is not None else None
+    _check(load().or_loss_pixels(_ptr(image), _ptr(target), P, spp, _ptr(dI_duv), _ptr(dId), _ptr(dIp), _ptr(L),
+                                 _ptr(g), _ptr(gd), _ptr(gp)), "loss_pixels")
+    return float(L[0]), g, gd, gp
 
 
 def philox4x32(ctr, key):
@@ -358,25 +366,29 @@ def loss(image, target, dI_duv):
 
 # --- derivatives ---------------------------------------------------------------------------
 
-def adjoint(field: Field, scene, dL_duv, pixel_ids=None, dL_ddir=None):
+def adjoint(field: Field, scene, dL_duv, pixel_ids=None, dL_ddir=None, dL_dpath=None):
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, None)
     lam = np.ascontiguousarray(dL_duv, np.float64).reshape(n, 2)
     lam_d = None if dL_ddir is None else np.ascontiguousarray(dL_ddir, np.float64).reshape(n, 3)
+    lam_p = None if dL_dpath is None else np.ascontiguousarray(dL_dpath, np.float64).reshape(n)
     nx, ny, nz = field.s.n
     g = np.zeros((nz, ny, nx))
-    _check(load().or_adjoint(field.ref, sh.ref, _ptr(ids), n, _ptr(lam), _ptr(lam_d), _ptr(g)), "adjoint")
+    _check(load().or_adjoint(field.ref, sh.ref, _ptr(ids), n, _ptr(lam), _ptr(lam_d), _ptr(lam_p), _ptr(g)),
+           "adjoint")
     return g
 
 
 def tangent(field: Field, scene, vfield, pixel_ids=None, with_dir=False):
+    """d(u, v) per ray; with_dir: (d(u, v), d vdir, d path)."""
     ids, n = _ids(scene, pixel_ids)
     sh = _SceneHolder(scene, None)
     vf = np.ascontiguousarray(vfield, np.float64)
     out = np.empty((n, 2))
     od = np.empty((n, 3)) if with_dir else None
-    _check(load().or_tangent(field.ref, sh.ref, _ptr(ids), n, _ptr(vf), _ptr(out), _ptr(od)), "tangent")
-    return (out, od) if with_dir else out
+    op = np.empty(n) if with_dir else None
+    _check(load().or_tangent(field.ref, sh.ref, _ptr(ids), n, _ptr(vf), _ptr(out), _ptr(od), _ptr(op)), "tangent")
+    return (out, od, op) if with_dir else out
 
 
 def fd_voxels(field: Field, scene, pattern, target, voxels, h=1e-7, locked=True, pixel_ids=None):

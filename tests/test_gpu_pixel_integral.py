@@ -1,8 +1,10 @@
 """GPU parity of the pixel integral (Eq. 2) against the oracle: spp rays per pixel through
 sub-pixel points drawn from the triangular filter (Philox-4x32-10 per pixel and sample),
 pixel values as the mean of their rays, the optional radiometric weight
-|<n_w, v_w>| / |X_w - c|, and the gradient including the weight's dependence on the
-direction at the wall.
+|<n_w, v_w>| / ell, and the gradient including the weight's dependence on the direction
+at the wall. The oracle's ell is the length of the traced path; the GPU takes the
+camera-to-hit distance, shorter by < 1e-10 relative on these fields (an oracle pin), so
+its values and gradients are compared with the oracle's exact definition.
 
 Tolerances as for one ray per pixel: exit points <= 1e-6 m (every sample), wall
 directions <= 1e-6 (FP32 normalisation of the exit velocity), images <= 1e-5, gradients
@@ -41,9 +43,9 @@ def _tracer(w, ids=None, launch=None, adj_launch=None, dtype="f32"):
 def _oracle(w, ids=None):
     F = oracle.grid_field(stored_delta(w.T32), w.scene.box_lo, w.scene.box_hi)
     out = oracle.trace(F, w.scene, ids)
-    img, dI, dId, st = oracle.render_pixels(w.scene, w.pattern32.astype(np.float64), out["uv"], out["status"],
-                                            out["vdir"])
-    out.update(image=img, dI=dI, dId=dId, status_r=st)
+    rp = oracle.render_pixels(w.scene, w.pattern32.astype(np.float64), out["uv"], out["status"], out["vdir"],
+                              out["path"])
+    out.update(image=rp["image"], dI=rp["dI_duv"], dId=rp["dI_ddir"], dIp=rp["dI_dpath"], status_r=rp["status"])
     return F, out
 
 
@@ -102,12 +104,14 @@ def test_sampled_radiometric_gradient_matches_oracle(tracer, ckpt):
     w = _with(unit_box_workload(40, 40), spp=4, seed=21, radiometry=1, tracer=tracer, ckpt_stride=ckpt)
     target = _target(w, 2)
     F, ref = _oracle(w)
-    L, dL, dLd = oracle.loss_pixels(ref["image"], target, 4, ref["dI"], ref["dId"])
-    g_ref = oracle.adjoint(F, w.scene, dL, dL_ddir=dLd)
+    L, dL, dLd, dLp = oracle.loss_pixels(ref["image"], target, 4, ref["dI"], ref["dId"], ref["dIp"])
+    g_full = oracle.adjoint(F, w.scene, dL, dL_ddir=dLd, dL_dpath=dLp)  # the loss's gradient
+    g_ref = oracle.adjoint(F, w.scene, dL, dL_ddir=dLd)  # the map the GPU's seeds feed
     tr = _tracer(w)
     tr.forward().render([torch.from_numpy(target.astype(np.float32)).to(DEV)])
     assert float(tr.loss[0]) == pytest.approx(L, rel=1e-4)
-    # the GPU's own per-ray seeds against the oracle's
+    # the GPU's own per-ray seeds against the oracle's (the GPU's (u, v) seeds also carry
+    # the weight's distance term, which the oracle seeds through the path: < 1e-3 here)
     scale_uv, scale_d = np.abs(dL).max(), np.abs(dLd).max()
     assert np.abs(_np(tr.dL_duv[0]) - dL).max() <= 1e-3 * scale_uv
     assert np.abs(_np(tr.dL_ddir[0]) - dLd).max() <= 1e-3 * scale_d
@@ -116,8 +120,11 @@ def test_sampled_radiometric_gradient_matches_oracle(tracer, ckpt):
                        dL_ddir=[torch.from_numpy(dLd.astype(np.float32)).to(DEV)])[0])
     l2, frac = grad_errors(g, g_ref)
     assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
-    l2o, _ = grad_errors(g_own, g_ref)
-    assert l2o < 1e-2, l2o
+    # end to end, the GPU's loss gradient: its seeds 2 r dI carry the FP32 rounding of the
+    # residual r = I - I*, here ~1e-4 against images ~0.16 (ulp 1.5e-8): ~1e-4 relative
+    # per ray (measured rel-L2 3.6e-4), so the per-voxel bound does not apply
+    l2o, _ = grad_errors(g_own, g_full)
+    assert l2o < 1e-3, l2o
     # the direction term alone: seeds on the direction only
     g_dir = _np(tr.adjoint(dL_duv=[torch.zeros((tr.scenes[0].n_rays, 2), device=DEV)],
                            dL_ddir=[torch.from_numpy(dLd.astype(np.float32)).to(DEV)])[0])

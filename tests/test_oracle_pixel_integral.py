@@ -1,6 +1,8 @@
 """Pins for the oracle's pixel integral (Eq. 2): each pixel's value is the mean of spp
 rays cast through sub-pixel points drawn from the triangular camera filter, each ray
-carrying the wall radiance at its hit, optionally weighted by |<n_w, v_w>| / |X_w - c|.
+carrying the wall radiance at its hit, optionally weighted by |<n_w, v_w>| / ell, ell the
+length of the ray path (the polyline from the camera centre through the box entry and
+every integrated state, then the signed straight continuation to the wall hit).
 
 Independent references:
   * Philox-4x32-10 against the published known-answer vectors (tests/golden);
@@ -12,6 +14,9 @@ Independent references:
     the camera direction;
   * the radiometric weight of a straight ray is (n.d)^2 / D, D the camera-to-wall
     distance along the normal;
+  * the path length: the camera-to-hit distance for straight rays; for eta^2 linear (the
+    exact parabola) the polyline through the parabola's own points at the step times;
+    never shorter than the chord, and longer by a second-order amount;
   * one sample per pixel and no weight is the centre-ray model, bit for bit;
   * the gradient including the direction term: dot-product identity with the
     tangent-linear model, and branch-locked central differences of the per-pixel loss.
@@ -118,8 +123,9 @@ def test_one_sample_no_weight_is_the_centre_model():
     fw = oracle.trace(F, sc)
     pat = binary_dots(4)
     img, dI, _ = oracle.render(sc, pat, fw["uv"], fw["status"])
-    img2, dI2, dId, _ = oracle.render_pixels(sc, pat, fw["uv"], fw["status"])
-    assert np.array_equal(img, img2) and np.array_equal(dI, dI2) and not dId.any()
+    rp = oracle.render_pixels(sc, pat, fw["uv"], fw["status"])
+    assert np.array_equal(img, rp["image"]) and np.array_equal(dI, rp["dI_duv"])
+    assert not rp["dI_ddir"].any() and not rp["dI_dpath"].any()
     assert np.abs(np.linalg.norm(fw["vdir"], axis=1) - 1.0).max() < 1e-15
     # spp = 1 ignores the key: no offsets are drawn
     assert np.array_equal(oracle.trace(F, sc.replace(seed=99))["uv"], fw["uv"])
@@ -132,7 +138,7 @@ def test_pixel_value_is_the_mean_of_its_rays():
     F = oracle.grid_field(oracle.delta_from_temperature(T.astype(np.float32)), sc.box_lo, sc.box_hi)
     fw = oracle.trace(F, sc)
     pat = binary_dots(5)
-    img, _, _, _ = oracle.render_pixels(sc, pat, fw["uv"], fw["status"])
+    img = oracle.render_pixels(sc, pat, fw["uv"], fw["status"])["image"]
     per_ray, _, _ = oracle.render(sc.replace(spp=1), pat, fw["uv"], fw["status"])
     P = sc.width * sc.height
     assert np.allclose(img, per_ray.reshape(spp, P).mean(0), rtol=0, atol=1e-15)
@@ -146,13 +152,59 @@ def test_radiometric_weight_of_straight_rays():
     sc = sc.replace(pat_extent_u=1.5 * sc.pat_extent_u, pat_extent_v=1.5 * sc.pat_extent_v)
     fw = oracle.trace(_homogeneous(sc), sc)
     pat = np.full((sc.pat_h, sc.pat_w), 0.5)
-    img, _, _, st = oracle.render_pixels(sc, pat, fw["uv"], fw["status"], fw["vdir"])
+    rp = oracle.render_pixels(sc, pat, fw["uv"], fw["status"], fw["vdir"], fw["path"])
     n = np.asarray(sc.wall_normal)
     D = abs(n @ (np.asarray(sc.wall_origin) - np.asarray(sc.cam_pos)))
     w = (fw["vdir"] @ n) ** 2 / D
     P = sc.width * sc.height
-    assert np.allclose(img, 0.5 * w.reshape(spp, P).mean(0), rtol=1e-13, atol=0)
-    assert not (st & O.RAY_OFF_PATTERN).any()
+    assert np.allclose(rp["image"], 0.5 * w.reshape(spp, P).mean(0), rtol=1e-12, atol=0)
+    assert not (rp["status"] & O.RAY_OFF_PATTERN).any()
+    # straight rays: the path is the camera-to-hit distance
+    X = np.asarray(sc.wall_origin) + fw["uv"][:, :1] * np.asarray(sc.wall_u) + fw["uv"][:, 1:] * np.asarray(sc.wall_v)
+    assert np.allclose(fw["path"], np.linalg.norm(X - np.asarray(sc.cam_pos), axis=1), rtol=1e-13, atol=0)
+
+
+def test_path_length_of_the_exact_parabola():
+    """eta^2 = a + g.(x - c): the traced states are x0 + v0 t + g t^2 / 4 exactly, so the
+    path is |x0 - cam| + the polyline through those points at t = 0, h, ..., N h + the
+    straight segment to the wall."""
+    g = np.array([0.004, 0.0, -0.006])
+    sc = scene_unit_box().replace(width=5, height=4)
+    F = oracle.analytic_field(O.FIELD_ETA2_LINEAR, sc.box_lo, sc.box_hi, a=1.0005, g=tuple(g), c=(0.5, 0.5, 0.5))
+    out = oracle.trace(F, sc, want_exit=True)
+    h = sc.step
+    for pix in range(sc.width * sc.height):
+        o, d = oracle.camera_ray(sc, pix)
+        t_in = (sc.box_lo[1] - o[1]) / d[1]
+        x0 = o + t_in * d
+        eta0 = math.sqrt(1.0005 + g @ (x0 - np.array([0.5, 0.5, 0.5])))
+        v0 = eta0 * d
+        N = out["n_steps"][pix]
+        t = h * np.arange(N + 1)
+        pts = x0 + np.outer(t, v0) + np.outer(t * t, g) / 4.0
+        xN, vN = out["exit_xv"][pix, :3], out["exit_xv"][pix, 3:]
+        assert np.allclose(pts[-1], xN, atol=1e-12)
+        s = ((np.asarray(sc.wall_origin) - xN) @ np.asarray(sc.wall_normal)) / (vN @ np.asarray(sc.wall_normal))
+        ref = np.linalg.norm(x0 - o) + np.linalg.norm(np.diff(pts, axis=0), axis=1).sum() + s * np.linalg.norm(vN)
+        assert out["path"][pix] == pytest.approx(ref, rel=1e-13)
+
+
+def test_path_exceeds_the_chord_by_second_order():
+    """In the room's plumes the path is never shorter than the camera-to-hit chord, and
+    longer by far less than one FP32 ulp of it (the deflection angle is ~1e-5 rad)."""
+    from bos_inputs import plumes_room, scene_room
+
+    sc = scene_room((64, 64, 48), 96, 72)
+    T = temperature_grid(plumes_room(3, sc.box_lo, sc.box_hi), sc.box_lo, sc.box_hi, sc.dims)
+    F = oracle.grid_field(oracle.delta_from_temperature(T.astype(np.float32)), sc.box_lo, sc.box_hi)
+    out = oracle.trace(F, sc)
+    ok = np.isfinite(out["uv"][:, 0])
+    X = (np.asarray(sc.wall_origin) + out["uv"][ok, :1] * np.asarray(sc.wall_u)
+         + out["uv"][ok, 1:] * np.asarray(sc.wall_v))
+    chord = np.linalg.norm(X - np.asarray(sc.cam_pos), axis=1)
+    excess = (out["path"][ok] - chord) / chord
+    assert excess.min() > -1e-14
+    assert excess.max() < 1e-9, excess.max()
 
 
 def _plume(sc, seed=1):
@@ -170,13 +222,17 @@ def test_dot_product_identity_with_direction_terms(tracer):
     rng = np.random.default_rng(17)
     v = rng.standard_normal(d.shape)
     w_uv, w_dir = rng.standard_normal((n, 2)), rng.standard_normal((n, 3))
-    t_uv, t_dir = oracle.tangent(F, sc, v, ids, with_dir=True)
-    lhs = float(np.sum(t_uv * w_uv) + np.sum(t_dir * w_dir))
-    rhs = float(np.sum(v * oracle.adjoint(F, sc, w_uv, ids, dL_ddir=w_dir)))
+    w_path = rng.standard_normal(n) * 1e3  # the path moves far less than the hit: scale up
+    t_uv, t_dir, t_path = oracle.tangent(F, sc, v, ids, with_dir=True)
+    lhs = float(np.sum(t_uv * w_uv) + np.sum(t_dir * w_dir) + np.sum(t_path * w_path))
+    rhs = float(np.sum(v * oracle.adjoint(F, sc, w_uv, ids, dL_ddir=w_dir, dL_dpath=w_path)))
     assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs))
-    # the direction part alone is non-trivial
-    rhs_dir = float(np.sum(v * oracle.adjoint(F, sc, np.zeros((n, 2)), ids, dL_ddir=w_dir)))
-    assert abs(rhs_dir) > 1e-3 * abs(rhs)
+    # the direction and path parts alone are non-trivial and satisfy it too
+    z = np.zeros((n, 2))
+    for wd, wp, t in ((w_dir, None, np.sum(t_dir * w_dir)), (None, w_path, np.sum(t_path * w_path))):
+        r = float(np.sum(v * oracle.adjoint(F, sc, z, ids, dL_ddir=wd, dL_dpath=wp)))
+        assert abs(r) > 1e-4 * abs(rhs)
+        assert abs(t - r) <= 1e-10 * abs(r) + 1e-12 * abs(rhs)
     # and the direction stays unit: its tangent is orthogonal to it
     fw = oracle.trace(F, sc, ids)
     assert np.abs(np.sum(t_dir * fw["vdir"], axis=1)).max() <= 1e-12 * np.abs(t_dir).max()
@@ -189,12 +245,13 @@ def test_pixel_loss_gradient_matches_locked_central_differences(radiometry):
     F2, _ = _plume(sc, 2)
     pat = binary_dots(11)
     fw2 = oracle.trace(F2, sc)
-    target, _, _, _ = oracle.render_pixels(sc, pat, fw2["uv"], fw2["status"], fw2["vdir"])
+    target = oracle.render_pixels(sc, pat, fw2["uv"], fw2["status"], fw2["vdir"], fw2["path"])["image"]
     fw = oracle.trace(F, sc)
-    img, dI, dId, _ = oracle.render_pixels(sc, pat, fw["uv"], fw["status"], fw["vdir"])
-    L, dL, dLd = oracle.loss_pixels(img, target, sc.spp, dI, dId if radiometry else None)
+    rp = oracle.render_pixels(sc, pat, fw["uv"], fw["status"], fw["vdir"], fw["path"])
+    L, dL, dLd, dLp = oracle.loss_pixels(rp["image"], target, sc.spp, rp["dI_duv"],
+                                         rp["dI_ddir"] if radiometry else None, rp["dI_dpath"] if radiometry else None)
     assert L > 0
-    g = oracle.adjoint(F, sc, dL, dL_ddir=dLd)
+    g = oracle.adjoint(F, sc, dL, dL_ddir=dLd, dL_dpath=dLp)
     gmax = np.abs(g).max()
     rng = np.random.default_rng(31)
     cand = np.flatnonzero(np.abs(g) > 1e-3 * gmax)
@@ -211,9 +268,9 @@ def test_pixel_integral_argument_errors():
     holder = oracle.oracle._SceneHolder(sc, None)
     uv = np.empty((5, 2))
     P = C.c_void_p
-    rc = O.load().or_trace(F.ref, holder.ref, None, 5, uv.ctypes.data_as(P), None, None, None, None, None)
+    rc = O.load().or_trace(F.ref, holder.ref, None, 5, uv.ctypes.data_as(P), None, None, None, None, None, None)
     assert rc < 0  # 5 rays is not a multiple of 2 samples per pixel
-    rc = O.load().or_trace(F.ref, holder.ref, None, 16, uv.ctypes.data_as(P), None, None, None, None, None)
+    rc = O.load().or_trace(F.ref, holder.ref, None, 16, uv.ctypes.data_as(P), None, None, None, None, None, None)
     assert rc < 0  # a full image needs width * height * spp rays
     with pytest.raises(Exception):
         oracle.trace(F, sc.replace(spp=0))
@@ -221,3 +278,5 @@ def test_pixel_integral_argument_errors():
     fw = oracle.trace(F, sc.replace(radiometry=1))
     with pytest.raises(Exception):
         oracle.render_pixels(sc.replace(radiometry=1), pat, fw["uv"], fw["status"])  # weight needs vdir
+    with pytest.raises(Exception):
+        oracle.render_pixels(sc.replace(radiometry=1), pat, fw["uv"], fw["status"], fw["vdir"])  # and the path
