@@ -242,10 +242,54 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
                        const rbos_adjoint_io* io, const rbos_launch* launch, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* --- Sec. 2.D: the network field ---------------------------------------------------- */
+
+/* The temperature, pressure and velocity are one MLP of the position (Sec. 2.D):
+   (T_nd, p, u_x, u_y, u_z) = MLP(xhat), xhat = 2 (x - box_lo) / (box_hi - box_lo) - 1,
+   with `depth` hidden layers of `width` tanh units and a linear output layer, and
+   T = T0 + (T_in - T0) T_nd. The parameters are packed per layer (3 -> width,
+   width -> width repeated depth - 1 times, width -> 5): the weights [in][out] row-major,
+   then the biases [out]. FP32 throughout; the hidden layers run on the matrix cores. */
+typedef struct rbos_mlp {
+  int32_t width;             /* hidden units per layer: 64 */
+  int32_t depth;             /* hidden layers: 1 .. 8 */
+  const float* params;       /* [dev] rbos_mlp_param_count(width, depth) floats */
+  double box_lo[3], box_hi[3];  /* normalisation box of the inputs (finite, lo < hi) */
+} rbos_mlp;
+
+/* Number of packed parameters (0 if width or depth is unsupported). */
+size_t rbos_mlp_param_count(int32_t width, int32_t depth);
+
+/* Workspace bytes for one point set of n_points: the activations kept by
+   rbos_mlp_forward for a following rbos_mlp_backward, and reduction buffers. */
+size_t rbos_mlp_workspace_bytes(int32_t width, int32_t depth, int64_t n_points);
+
+/* Evaluate the MLP at n_points points: points [dev] [n][3] in metres, or NULL for the
+   voxel centres of the grid grid_dims (host int32[3] = nx, ny, nz over the MLP box,
+   x fastest; n_points must be nx*ny*nz). Writes out [dev] [n][5] and/or
+   T [dev] [n] = T0 + (T_in - T0) out_0 (each nullable) and keeps the activations in the
+   workspace (256-byte aligned, >= rbos_mlp_workspace_bytes). */
+int rbos_mlp_forward(const rbos_mlp* mlp, const float* points, int64_t n_points, const int32_t* grid_dims,
+                     float* out, float* T, double T0, double T_in, void* workspace, size_t ws_bytes, void* stream);
+
+/* Parameter gradient of a loss given per point as dL_dout [dev] [n][5]: ADDS
+   sum_i dL_dout_i . d out_i / d params into dparams [dev] (param_count floats). Needs the
+   workspace of an rbos_mlp_forward on the same points and parameters, unmodified since;
+   the block sums are reduced in a fixed order (deterministic). */
+int rbos_mlp_backward(const rbos_mlp* mlp, const float* points, int64_t n_points, const int32_t* grid_dims,
+                      const float* dL_dout, float* dparams, void* workspace, size_t ws_bytes, void* stream);
+
+/* Chain of the BOS loss to the network (Sec. 2.A, 2.D): from dL/d(eta - 1) per voxel
+   (grad_delta [dev] FP64, the adjoint's output) and the voxel temperatures T [dev] [n]
+   (kelvin, > 0), writes dL_dout [dev] [n][5] with channel 0 =
+   grad_delta * (-rho0G T0 / T^2) * (T_in - T0) and channels 1..4 = 0. */
+int rbos_mlp_bos_seed(int64_t n, const float* T, const double* grad_delta, double rho0G, double T0, double T_in,
+                      float* dL_dout, void* stream);
+
 /* --- binding support --------------------------------------------------------------- */
 
 /* Layout of the public structs for binding checks: which = 0 rbos_scene,
-   1 rbos_trace_out, 2 rbos_render_io, 3 rbos_adjoint_io, 4 rbos_launch. Writes up to
+   1 rbos_trace_out, 2 rbos_render_io, 3 rbos_adjoint_io, 4 rbos_launch, 5 rbos_mlp. Writes up to
    max_fields member offsets (declaration order) and returns sizeof, or 0 if unknown. */
 size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields);
 

@@ -61,12 +61,18 @@ class rbos_launch(C.Structure):
                 ("persistent", C.c_int32), ("blocks_per_cu", C.c_int32)]
 
 
-STRUCTS = [rbos_scene, rbos_trace_out, rbos_render_io, rbos_adjoint_io, rbos_launch]
+class rbos_mlp(C.Structure):
+    _fields_ = [("width", C.c_int32), ("depth", C.c_int32), ("params", C.c_void_p), ("box_lo", D3),
+                ("box_hi", D3)]
+
+
+STRUCTS = [rbos_scene, rbos_trace_out, rbos_render_io, rbos_adjoint_io, rbos_launch, rbos_mlp]
 
 EXPORTS = [
     "rbos_version", "rbos_last_error", "rbos_field_bytes", "rbos_field_from_temperature",
     "rbos_field_encode", "rbos_ckpt_bytes", "rbos_workspace_bytes", "rbos_trace_forward",
-    "rbos_render", "rbos_trace_adjoint", "rbos_struct_layout",
+    "rbos_render", "rbos_trace_adjoint", "rbos_struct_layout", "rbos_mlp_param_count",
+    "rbos_mlp_workspace_bytes", "rbos_mlp_forward", "rbos_mlp_backward", "rbos_mlp_bos_seed",
 ]
 
 _lib = None
@@ -104,6 +110,12 @@ def load(path: str = LIB_PATH):
         "rbos_trace_adjoint": ([C.POINTER(rbos_scene), I32, C.POINTER(rbos_trace_out),
                                 C.POINTER(rbos_adjoint_io), C.POINTER(rbos_launch), P, SZ, P], C.c_int),
         "rbos_struct_layout": ([I32, C.POINTER(C.c_size_t), I32], SZ),
+        "rbos_mlp_param_count": ([I32, I32], SZ),
+        "rbos_mlp_workspace_bytes": ([I32, I32, C.c_int64], SZ),
+        "rbos_mlp_forward": ([C.POINTER(rbos_mlp), P, C.c_int64, P, P, P, C.c_double, C.c_double, P, SZ, P],
+                             C.c_int),
+        "rbos_mlp_backward": ([C.POINTER(rbos_mlp), P, C.c_int64, P, P, P, P, SZ, P], C.c_int),
+        "rbos_mlp_bos_seed": ([C.c_int64, P, P, C.c_double, C.c_double, C.c_double, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

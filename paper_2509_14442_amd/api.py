@@ -308,6 +308,83 @@ class Tracer:
         return grads
 
 
+class MLP:
+    """The network field of Sec. 2.D on the GPU: (T_nd, p, u) = MLP(xhat; params), tanh
+    hidden layers, packed FP32 parameters (see include/rbos.h). Each point set (a points
+    tensor or a voxel grid) keeps its own workspace, which holds the activations of its
+    last forward for the backward."""
+
+    def __init__(self, params: torch.Tensor, width: int, depth: int, box_lo, box_hi):
+        n = lib().rbos_mlp_param_count(width, depth)
+        if n == 0:
+            raise ValueError(f"unsupported MLP width {width} / depth {depth}")
+        if params.numel() != n or params.dtype != torch.float32 or not params.is_cuda:
+            raise ValueError(f"params must be a float32 GPU tensor of {n} values")
+        self.params = params.contiguous()
+        self.width, self.depth = width, depth
+        m = L.rbos_mlp()
+        m.width, m.depth = width, depth
+        m.params = self.params.data_ptr()
+        m.box_lo, m.box_hi = _vec(box_lo), _vec(box_hi)
+        self.struct = m
+        self._ws = {}
+
+    @staticmethod
+    def param_count(width: int, depth: int) -> int:
+        return int(lib().rbos_mlp_param_count(width, depth))
+
+    def _set(self, points, grid):
+        if points is not None:
+            points = points.contiguous()
+            if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+                raise ValueError("points must be float32 [n][3]")
+            n, key, g = points.shape[0], ("p", points.data_ptr(), points.shape[0]), None
+        else:
+            nx, ny, nz = (int(v) for v in grid)
+            n, key, g = nx * ny * nz, ("g", nx, ny, nz), (C.c_int32 * 3)(nx, ny, nz)
+        if key not in self._ws:
+            nb = lib().rbos_mlp_workspace_bytes(self.width, self.depth, n)
+            self._ws[key] = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.params.device)
+        return points, n, g, self._ws[key]
+
+    def forward(self, points: Optional[torch.Tensor] = None, grid=None, want_out: bool = True,
+                T0: Optional[float] = None, T_in: Optional[float] = None, stream=None):
+        """Outputs [n][5] (if want_out) and, with T0 and T_in, T [n] = T0 + (T_in - T0) out_0."""
+        points, n, g, ws = self._set(points, grid)
+        dev = self.params.device
+        out = torch.empty((n, 5), dtype=torch.float32, device=dev) if want_out else None
+        T = torch.empty(n, dtype=torch.float32, device=dev) if T0 is not None else None
+        L.check(lib().rbos_mlp_forward(C.byref(self.struct), _ptr(points), n, g, _ptr(out), _ptr(T),
+                                       float(T0 or 0.0), float(T_in or 0.0), _ptr(ws), ws.numel(), _stream(stream)))
+        self._keep = points
+        return out, T
+
+    def backward(self, dL_dout: torch.Tensor, points: Optional[torch.Tensor] = None, grid=None,
+                 dparams: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """dparams += sum_i dL_dout_i . d out_i / d params (after forward on the same points)."""
+        points, n, g, ws = self._set(points, grid)
+        if dparams is None:
+            dparams = torch.zeros_like(self.params)
+        d = dL_dout.to(dtype=torch.float32).contiguous()
+        if tuple(d.shape) != (n, 5):
+            raise ValueError(f"dL_dout must be [{n}][5]")
+        L.check(lib().rbos_mlp_backward(C.byref(self.struct), _ptr(points), n, g, _ptr(d), _ptr(dparams), _ptr(ws),
+                                        ws.numel(), _stream(stream)))
+        self._keep_d = d
+        return dparams
+
+    @staticmethod
+    def bos_seed(T: torch.Tensor, grad_delta: torch.Tensor, T0: float, T_in: float, rho0G: float = RHO0G,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """dL/dout at the voxel centres from dL/d(eta - 1) (float64) and T (kelvin)."""
+        n = T.numel()
+        if out is None:
+            out = torch.empty((n, 5), dtype=torch.float32, device=T.device)
+        L.check(lib().rbos_mlp_bos_seed(n, _ptr(T.contiguous()), _ptr(grad_delta.contiguous()), rho0G, T0, T_in,
+                                        _ptr(out), _stream(stream)))
+        return out
+
+
 class BOSLoss(torch.autograd.Function):
     """L_BOS(eta - 1) for one scene, with the hand-written adjoint as its backward.
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librbos.so")
-SOURCES = ["abi.hip", "field_pack.hip", "trace_fwd.hip", "render.hip", "trace_adj.hip"]
+SOURCES = ["abi.hip", "field_pack.hip", "trace_fwd.hip", "render.hip", "trace_adj.hip", "mlp.hip"]
 ARCH = os.environ.get("RBOS_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -13,6 +13,7 @@
 #include "../../include/rbos.h"
 #include "rbos_device.hpp"
 #include "rbos_launch.hpp"
+#include "mlp_launch.hpp"
 
 namespace {
 
@@ -537,6 +538,114 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
   return RBOS_OK;
 }
 
+size_t rbos_mlp_param_count(int32_t width, int32_t depth) {
+  if (width != rbos::MLP_WIDTH || depth < 1 || depth > rbos::MLP_MAX_DEPTH) return 0;
+  const size_t w = (size_t)width;
+  return 3 * w + w + (size_t)(depth - 1) * (w * w + w) + w * rbos::MLP_OUT + rbos::MLP_OUT;
+}
+
+size_t rbos_mlp_workspace_bytes(int32_t width, int32_t depth, int64_t n_points) {
+  if (rbos_mlp_param_count(width, depth) == 0 || n_points < 0) return 0;
+  return rbos::mlp_work_bytes(depth, n_points);
+}
+
+}  // extern "C"
+
+namespace {
+
+int mlp_prepare(const rbos_mlp* m, const float* points, int64_t n, const int32_t* grid, void* ws, size_t ws_bytes,
+                rbos::MlpDev& M, rbos::MlpWork& W) {
+  if (!m) return fail(RBOS_E_NULL, "mlp is NULL");
+  if (rbos_mlp_param_count(m->width, m->depth) == 0)
+    return fail(RBOS_E_UNSUPPORTED, "mlp: width must be %d and depth in [1, %d] (got %d, %d)", rbos::MLP_WIDTH,
+                rbos::MLP_MAX_DEPTH, m->width, m->depth);
+  if (!m->params) return fail(RBOS_E_NULL, "mlp: params is NULL");
+  if (!finite3(m->box_lo) || !finite3(m->box_hi) || !(m->box_lo[0] < m->box_hi[0]) ||
+      !(m->box_lo[1] < m->box_hi[1]) || !(m->box_lo[2] < m->box_hi[2]))
+    return fail(RBOS_E_RANGE, "mlp: box must be finite with lo < hi");
+  if (n < 0 || n > (1LL << 31)) return fail(RBOS_E_SHAPE, "mlp: n_points must be in [0, 2^31]");
+  std::memset(&M, 0, sizeof M);
+  if (!points) {
+    if (!grid) return fail(RBOS_E_NULL, "mlp: points and grid_dims are both NULL");
+    if (grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || (long long)grid[0] * grid[1] * grid[2] != n)
+      return fail(RBOS_E_SHAPE, "mlp: grid_dims must be positive with nx*ny*nz == n_points");
+    M.nx = grid[0];
+    M.ny = grid[1];
+    M.nz = grid[2];
+  }
+  if (n > 0) {
+    if (!ws) return fail(RBOS_E_WORKSPACE, "mlp: workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(RBOS_E_WORKSPACE, "mlp: workspace must be 256-byte aligned");
+    const size_t need = rbos::mlp_work_bytes(m->depth, n);
+    if (ws_bytes < need) return fail(RBOS_E_WORKSPACE, "mlp: workspace too small: %zu < %zu bytes", ws_bytes, need);
+  }
+  M.depth = m->depth;
+  M.params = m->params;
+  int off = 0;
+  for (int l = 0; l <= m->depth; ++l) {
+    const int fi = l == 0 ? 3 : rbos::MLP_WIDTH, fo = l == m->depth ? rbos::MLP_OUT : rbos::MLP_WIDTH;
+    M.off_w[l] = off;
+    off += fi * fo;
+    M.off_b[l] = off;
+    off += fo;
+  }
+  M.n = n;
+  M.points = points;
+  for (int a = 0; a < 3; ++a) {
+    const double sc = 2.0 / (m->box_hi[a] - m->box_lo[a]);
+    M.xs[a] = (float)sc;
+    M.xo[a] = (float)(-m->box_lo[a] * sc - 1.0);
+  }
+  if (n > 0) rbos::mlp_work_carve(ws, m->depth, n, W);
+  return RBOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rbos_mlp_forward(const rbos_mlp* mlp, const float* points, int64_t n_points, const int32_t* grid_dims,
+                     float* out, float* T, double T0, double T_in, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  rbos::MlpDev M;
+  rbos::MlpWork W;
+  int rc = mlp_prepare(mlp, points, n_points, grid_dims, workspace, ws_bytes, M, W);
+  if (rc) return rc;
+  if (T && !(std::isfinite(T0) && std::isfinite(T_in))) return fail(RBOS_E_RANGE, "mlp: T0 and T_in must be finite");
+  if (n_points == 0) return RBOS_OK;
+  hipError_t e = rbos::launch_mlp_forward(M, W, out, T, (float)T0, (float)(T_in - T0), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "mlp forward launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+int rbos_mlp_backward(const rbos_mlp* mlp, const float* points, int64_t n_points, const int32_t* grid_dims,
+                      const float* dL_dout, float* dparams, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  rbos::MlpDev M;
+  rbos::MlpWork W;
+  int rc = mlp_prepare(mlp, points, n_points, grid_dims, workspace, ws_bytes, M, W);
+  if (rc) return rc;
+  if (!dparams) return fail(RBOS_E_NULL, "mlp: dparams is NULL");
+  if (n_points > 0 && !dL_dout) return fail(RBOS_E_NULL, "mlp: dL_dout is NULL");
+  if (n_points == 0) return RBOS_OK;
+  hipError_t e = rbos::launch_mlp_backward(M, W, dL_dout, dparams, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "mlp backward launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+int rbos_mlp_bos_seed(int64_t n, const float* T, const double* grad_delta, double rho0G, double T0, double T_in,
+                      float* dL_dout, void* stream) {
+  g_err.clear();
+  if (n < 0) return fail(RBOS_E_SHAPE, "n < 0");
+  if (n > 0 && (!T || !grad_delta || !dL_dout)) return fail(RBOS_E_NULL, "T, grad_delta and dL_dout are required");
+  if (!(rho0G > 0.0) || !std::isfinite(rho0G) || !(T0 > 0.0) || !std::isfinite(T0) || !std::isfinite(T_in))
+    return fail(RBOS_E_RANGE, "rho0G and T0 must be positive and finite, T_in finite");
+  hipError_t e = rbos::launch_mlp_bos_seed(n, T, grad_delta, rho0G, T0, T_in - T0, dL_dout,
+                                           static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "seed launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
 size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields) {
 #define OFF(T, f) offsetof(T, f)
   std::vector<size_t> o;
@@ -574,6 +683,11 @@ size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields) {
       o = {OFF(rbos_launch, tile_w), OFF(rbos_launch, tile_h), OFF(rbos_launch, waves_per_block),
            OFF(rbos_launch, persistent), OFF(rbos_launch, blocks_per_cu)};
       sz = sizeof(rbos_launch);
+      break;
+    case 5:
+      o = {OFF(rbos_mlp, width), OFF(rbos_mlp, depth), OFF(rbos_mlp, params), OFF(rbos_mlp, box_lo),
+           OFF(rbos_mlp, box_hi)};
+      sz = sizeof(rbos_mlp);
       break;
     default:
       return 0;

@@ -196,3 +196,36 @@ def test_field_validation_and_sizes(lib):
     assert lib.rbos_workspace_bytes(C.byref(s), 1) >= 256
     # empty batch is a no-op
     assert lib.rbos_trace_forward(C.byref(s), 0, None, None, None, 0, None) == 0
+
+
+def test_mlp_entry_point_validation(lib):
+    assert lib.rbos_mlp_param_count(64, 4) == 3 * 64 + 64 + 3 * (64 * 64 + 64) + 64 * 5 + 5
+    assert lib.rbos_mlp_param_count(32, 4) == 0 and lib.rbos_mlp_param_count(64, 0) == 0
+    assert lib.rbos_mlp_param_count(64, 9) == 0
+    n = 1000
+    nb = lib.rbos_mlp_workspace_bytes(64, 4, n)
+    assert nb >= 4 * n * 64 * 4 + 2 * n * 64 * 4
+    m = L.rbos_mlp(64, 4, 0x1000, L.D3(0, 0, 0), L.D3(4, 4, 3))
+    ws = C.c_void_p(0x100000)
+
+    def fwd(mm, pts=0x2000, n=n, grid=None, ws=ws, nbytes=nb):
+        rc = lib.rbos_mlp_forward(C.byref(mm) if mm is not None else None, C.c_void_p(pts) if pts else None, n,
+                                  grid, C.c_void_p(0x3000), None, 0.0, 0.0, ws, nbytes, None)
+        return rc, lib.rbos_last_error().decode()
+
+    assert fwd(None)[0] == -1
+    assert fwd(L.rbos_mlp(32, 4, 0x1000, L.D3(0, 0, 0), L.D3(4, 4, 3)))[0] == -7
+    assert fwd(L.rbos_mlp(64, 4, None, L.D3(0, 0, 0), L.D3(4, 4, 3)))[0] == -1
+    assert fwd(L.rbos_mlp(64, 4, 0x1000, L.D3(0, 0, 0), L.D3(4, 0, 3)))[0] == -3
+    assert fwd(m, pts=0)[0] == -1  # neither points nor a grid
+    assert fwd(m, pts=0, grid=(C.c_int32 * 3)(10, 10, 11))[0] == -2  # 1100 != 1000 points
+    assert fwd(m, ws=None)[0] == -5
+    assert fwd(m, nbytes=nb - 1)[0] == -5
+    assert fwd(m, ws=C.c_void_p(0x100010))[0] == -5
+    assert fwd(m, n=0, ws=None, nbytes=0)[0] == 0  # empty: nothing enqueued
+    rc = lib.rbos_mlp_backward(C.byref(m), C.c_void_p(0x2000), n, None, C.c_void_p(0x3000), None, ws, nb, None)
+    assert rc == -1 and b"dparams" in lib.rbos_last_error()
+    assert lib.rbos_mlp_bos_seed(10, C.c_void_p(0x10), C.c_void_p(0x20), -1.0, 293.0, 303.0, C.c_void_p(0x30),
+                                 None) == -3
+    assert lib.rbos_mlp_bos_seed(10, None, C.c_void_p(0x20), 2.7e-4, 293.0, 303.0, C.c_void_p(0x30), None) == -1
+    assert lib.rbos_mlp_bos_seed(0, None, None, 2.7e-4, 293.0, 303.0, None, None) == 0

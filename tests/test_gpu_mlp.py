@@ -1,0 +1,127 @@
+"""GPU parity of the network field (Sec. 2.D) against the oracle: the MLP forward at
+arbitrary points and at the voxel centres (FP32 on the matrix cores vs FP64), its
+parameter gradient for given per-point output seeds, and the BOS loss's parameter
+gradient end to end (MLP -> T on the voxel grid -> eta -> trace -> render -> adjoint ->
+chain to T_nd -> MLP backward).
+
+Tolerances: outputs are O(1) sums of 64 FP32 products per layer through tanh, so
+|out - oracle| <= 2e-5 (measured ~1e-6); T = T0 + 10 K out_0 within 3e-4 K; parameter
+gradients rel-L2 < 1e-5 for given seeds (FP32 accumulation over <= 2^17 points), and
+< 1e-3 end to end, where the seeds themselves come from the FP32 tracer.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as omlp
+from _common import grad_errors, stored_delta
+from bos_inputs import binary_dots, scene_unit_box
+from paper_2509_14442_amd import api
+from test_gpu_forward import DEV, _np
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+T0, T_IN = 293.0, 303.0
+
+
+def _mlp(depth, seed=1, scale=1.0):
+    th = omlp.init_params(64, depth, seed, out_scale=scale)
+    th[np.arange(th.size) % 5 == 2] += 0.02  # non-zero biases
+    m = api.MLP(torch.from_numpy(th.astype(np.float32)).to(DEV), 64, depth, LO, HI)
+    return m, th.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("depth,n", [(1, 1), (3, 1000), (4, 4099), (6, 333)])
+def test_forward_at_points(depth, n):
+    m, th = _mlp(depth)
+    x = np.random.default_rng(depth).uniform(LO, HI, (n, 3)).astype(np.float32)
+    out, T = m.forward(torch.from_numpy(x).to(DEV), T0=T0, T_in=T_IN)
+    ref = omlp.forward(th, 64, depth, x.astype(np.float64), LO, HI)
+    err = np.abs(_np(out) - ref).max()
+    print(f"depth {depth}, {n} points: max |out - oracle| {err:.2e}")
+    assert err <= 2e-5
+    assert np.abs(_np(T) - omlp.temperature(ref[:, 0], T0, T_IN)).max() <= 3e-4
+
+
+def test_forward_on_the_voxel_grid():
+    m, th = _mlp(4, 2)
+    dims = (24, 20, 17)
+    out, T = m.forward(grid=dims, T0=T0, T_in=T_IN)
+    ref = omlp.forward(th, 64, 4, omlp.voxel_centres(LO, HI, dims), LO, HI)
+    assert np.abs(_np(out) - ref).max() <= 2e-5
+    assert np.abs(_np(T) - omlp.temperature(ref[:, 0], T0, T_IN)).max() <= 3e-4
+
+
+@pytest.mark.parametrize("depth,n", [(1, 70), (4, 5000), (5, 131072)])
+def test_parameter_gradient_for_given_seeds(depth, n):
+    m, th = _mlp(depth, 3)
+    rng = np.random.default_rng(10 + depth)
+    x = rng.uniform(LO, HI, (n, 3)).astype(np.float32)
+    lam = rng.standard_normal((n, 5)).astype(np.float32)
+    xt = torch.from_numpy(x).to(DEV)
+    m.forward(xt, want_out=False)
+    g = _np(m.backward(torch.from_numpy(lam).to(DEV), xt)).astype(np.float64)
+    ref = omlp.vjp_params(th, 64, depth, x.astype(np.float64), LO, HI, lam.astype(np.float64))
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    print(f"depth {depth}, {n} points: dparams rel-L2 {rel:.2e}")
+    assert rel < 1e-5
+    assert np.abs(g - ref).max() <= 1e-4 * np.abs(ref).max()
+    # accumulation: a second backward adds the same gradient again
+    d2 = m.backward(torch.from_numpy(lam).to(DEV), xt, dparams=torch.from_numpy(g.astype(np.float32)).to(DEV))
+    assert np.allclose(_np(d2), 2 * g, rtol=1e-6, atol=1e-6 * np.abs(g).max())
+
+
+def test_backward_is_deterministic():
+    m, _ = _mlp(4, 4)
+    x = torch.from_numpy(np.random.default_rng(5).uniform(LO, HI, (70000, 3)).astype(np.float32)).to(DEV)
+    lam = torch.from_numpy(np.random.default_rng(6).standard_normal((70000, 5)).astype(np.float32)).to(DEV)
+    m.forward(x, want_out=False)
+    g1 = m.backward(lam, x)
+    g2 = m.backward(lam, x)
+    assert torch.equal(g1, g2)
+
+
+def test_bos_loss_parameter_gradient_end_to_end():
+    """Unit-box scene on a 32^3 grid whose temperatures come from the MLP; target image
+    from a second network."""
+    sc = scene_unit_box().replace(width=48, height=48)
+    dims = sc.dims
+    m, th = _mlp(3, 7, scale=0.3)
+    _, th2 = _mlp(3, 8, scale=0.3)
+    pat = binary_dots(11)
+    # target: the oracle's render of the second network's field
+    xc = omlp.voxel_centres(LO, HI, dims)
+    T2 = omlp.temperature(omlp.forward(th2, 64, 3, xc, LO, HI)[:, 0], T0, T_IN).reshape(dims[::-1])
+    F2 = oracle.grid_field(stored_delta(T2.astype(np.float32)), LO, HI)
+    fw2 = oracle.trace(F2, sc)
+    target = oracle.render(sc, pat, fw2["uv"], fw2["status"])[0]
+
+    # GPU: MLP -> T grid -> field -> trace -> render -> adjoint -> seed -> backward
+    _, T = m.forward(grid=dims, want_out=False, T0=T0, T_in=T_IN)
+    field = api.Field.from_temperature(T.reshape(dims[::-1]), "f32")
+    scene = api.Scene(sc, field, torch.from_numpy(pat.astype(np.float32)).to(DEV))
+    tr = api.Tracer([scene])
+    tr.forward().render([torch.from_numpy(target.astype(np.float32)).to(DEV)])
+    g_delta = tr.adjoint()[0].reshape(-1)
+    seed = api.MLP.bos_seed(T, g_delta, T0, T_IN)
+    g = _np(m.backward(seed, grid=dims)).astype(np.float64)
+
+    # oracle: the same chain in FP64 from the GPU's stored temperatures
+    T32 = _np(T).reshape(dims[::-1])
+    F = oracle.grid_field(stored_delta(T32), LO, HI)
+    fw = oracle.trace(F, sc)
+    img, dI, _ = oracle.render(sc, pat, fw["uv"], fw["status"])
+    L, dL = oracle.loss(img, target, dI)
+    assert float(tr.loss[0]) == pytest.approx(L, rel=1e-4)
+    gd_ref = oracle.adjoint(F, sc, dL)
+    s_ref = np.zeros((xc.shape[0], 5))
+    s_ref[:, 0] = omlp.bos_temperature_seed(gd_ref.ravel(), T32.ravel().astype(np.float64), 2.7e-4, T0, T_IN)
+    assert np.abs(_np(seed)[:, 0] - s_ref[:, 0]).max() <= 1e-3 * np.abs(s_ref[:, 0]).max()
+    assert not _np(seed)[:, 1:].any()
+    ref = omlp.vjp_params(th, 64, 3, xc, LO, HI, s_ref)
+    l2, _ = grad_errors(g, ref)
+    print(f"end-to-end dparams rel-L2 {l2:.2e}")
+    assert l2 < 1e-3
