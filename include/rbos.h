@@ -286,10 +286,44 @@ int rbos_mlp_backward(const rbos_mlp* mlp, const float* points, int64_t n_points
 int rbos_mlp_bos_seed(int64_t n, const float* T, const double* grad_delta, double rho0G, double T0, double T_in,
                       float* dL_dout, void* stream);
 
+/* Boundary loss (Sec. 2.D): L_Gamma = sum_i sum_k ((out_ik - target_ik) / norm_k)^2 over
+   n points, each field divided by its normaliser (norms: host double[5] > 0, one per
+   output; the paper divides each field by its maximum value). Writes the seed
+   dL_dout [dev] [n][5] = 2 (out - target) / norm^2 for rbos_mlp_backward and, if loss
+   [dev] (one float) is given, L_Gamma, summed in a fixed order in the workspace
+   (>= rbos_mlp_fit_workspace_bytes(n), 256-byte aligned). */
+size_t rbos_mlp_fit_workspace_bytes(int64_t n_points);
+int rbos_mlp_fit_seed(int64_t n, const float* out, const float* target, const double* norms, float* dL_dout,
+                      float* loss, void* workspace, size_t ws_bytes, void* stream);
+
+/* Physics-informed loss (Sec. 2.D): at n collocation points x (metres),
+   L_PDE = sum_i g1 r_mass^2 + g2 |r_mom|^2 + g3 r_heat^2 with the Boussinesq residuals in
+   nondimensional coordinates x_nd = x / L and gravity along -z:
+     r_mass = div u,  r_mom = (u . grad) u + grad p - lap(u) / Re + Ri T_nd e_g,
+     r_heat = (u . grad) T_nd - lap(T_nd) / Pe.
+   The derivatives come from forward-mode jets of the MLP (value, first and second
+   derivative along each axis, 7 channels per point, the hidden layers on the matrix
+   cores); the parameter gradient from their reverse. */
+typedef struct rbos_pde {
+  double Re, Pe, Ri;   /* Reynolds, Peclet and Richardson numbers (Re, Pe > 0) */
+  double L;            /* characteristic length in metres (> 0) */
+  double gamma[3];     /* weights of the mass, momentum and heat residuals */
+} rbos_pde;
+
+/* Workspace bytes of rbos_mlp_pde_loss for n_points collocation points. */
+size_t rbos_mlp_pde_workspace_bytes(int32_t width, int32_t depth, int64_t n_points);
+
+/* Residuals, loss and parameter gradient at the collocation points [dev] [n][3]. Writes
+   residuals [dev] [n][5] (r_mass, r_mom x 3, r_heat) and loss [dev] (one float, summed in
+   a fixed order) when given, and ADDS dL_PDE/d params into dparams [dev] when given. */
+int rbos_mlp_pde_loss(const rbos_mlp* mlp, const rbos_pde* pde, const float* points, int64_t n_points, float* loss,
+                      float* dparams, float* residuals, void* workspace, size_t ws_bytes, void* stream);
+
 /* --- binding support --------------------------------------------------------------- */
 
 /* Layout of the public structs for binding checks: which = 0 rbos_scene,
-   1 rbos_trace_out, 2 rbos_render_io, 3 rbos_adjoint_io, 4 rbos_launch, 5 rbos_mlp. Writes up to
+   1 rbos_trace_out, 2 rbos_render_io, 3 rbos_adjoint_io, 4 rbos_launch, 5 rbos_mlp,
+   6 rbos_pde. Writes up to
    max_fields member offsets (declaration order) and returns sizeof, or 0 if unknown. */
 size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields);
 

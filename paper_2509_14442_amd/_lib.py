@@ -66,13 +66,18 @@ class rbos_mlp(C.Structure):
                 ("box_hi", D3)]
 
 
-STRUCTS = [rbos_scene, rbos_trace_out, rbos_render_io, rbos_adjoint_io, rbos_launch, rbos_mlp]
+class rbos_pde(C.Structure):
+    _fields_ = [("Re", C.c_double), ("Pe", C.c_double), ("Ri", C.c_double), ("L", C.c_double), ("gamma", D3)]
+
+
+STRUCTS = [rbos_scene, rbos_trace_out, rbos_render_io, rbos_adjoint_io, rbos_launch, rbos_mlp, rbos_pde]
 
 EXPORTS = [
     "rbos_version", "rbos_last_error", "rbos_field_bytes", "rbos_field_from_temperature",
     "rbos_field_encode", "rbos_ckpt_bytes", "rbos_workspace_bytes", "rbos_trace_forward",
     "rbos_render", "rbos_trace_adjoint", "rbos_struct_layout", "rbos_mlp_param_count",
     "rbos_mlp_workspace_bytes", "rbos_mlp_forward", "rbos_mlp_backward", "rbos_mlp_bos_seed",
+    "rbos_mlp_fit_workspace_bytes", "rbos_mlp_fit_seed", "rbos_mlp_pde_workspace_bytes", "rbos_mlp_pde_loss",
 ]
 
 _lib = None
@@ -116,6 +121,10 @@ def load(path: str = LIB_PATH):
                              C.c_int),
         "rbos_mlp_backward": ([C.POINTER(rbos_mlp), P, C.c_int64, P, P, P, P, SZ, P], C.c_int),
         "rbos_mlp_bos_seed": ([C.c_int64, P, P, C.c_double, C.c_double, C.c_double, P, P], C.c_int),
+        "rbos_mlp_fit_workspace_bytes": ([C.c_int64], SZ),
+        "rbos_mlp_fit_seed": ([C.c_int64, P, P, C.POINTER(C.c_double), P, P, P, SZ, P], C.c_int),
+        "rbos_mlp_pde_workspace_bytes": ([I32, I32, C.c_int64], SZ),
+        "rbos_mlp_pde_loss": ([C.POINTER(rbos_mlp), C.POINTER(rbos_pde), P, C.c_int64, P, P, P, P, SZ, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

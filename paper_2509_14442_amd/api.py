@@ -373,6 +373,30 @@ class MLP:
         self._keep_d = d
         return dparams
 
+    def pde_loss(self, points: torch.Tensor, Re: float, Pe: float, Ri: float, L_ref: float, gamma=(1.0, 1.0, 1.0),
+                 dparams: Optional[torch.Tensor] = None, want_grad: bool = True, want_residuals: bool = False,
+                 stream=None):
+        """Boussinesq residual loss at collocation points [n][3]: (loss [1], dparams (added
+        into if given), residuals [n][5] or None)."""
+        points = points.contiguous()
+        n = points.shape[0]
+        dev = self.params.device
+        key = ("pde", n)
+        if key not in self._ws:
+            nb = lib().rbos_mlp_pde_workspace_bytes(self.width, self.depth, n)
+            self._ws[key] = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        ws = self._ws[key]
+        loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        if want_grad and dparams is None:
+            dparams = torch.zeros_like(self.params)
+        res = torch.empty((n, 5), dtype=torch.float32, device=dev) if want_residuals else None
+        pde = L.rbos_pde(Re, Pe, Ri, L_ref, L.D3(*gamma))
+        L.check(lib().rbos_mlp_pde_loss(C.byref(self.struct), C.byref(pde), _ptr(points), n, _ptr(loss),
+                                        _ptr(dparams) if want_grad else None, _ptr(res), _ptr(ws), ws.numel(),
+                                        _stream(stream)))
+        self._keep = points
+        return loss, (dparams if want_grad else None), res
+
     @staticmethod
     def bos_seed(T: torch.Tensor, grad_delta: torch.Tensor, T0: float, T_in: float, rho0G: float = RHO0G,
                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -383,6 +407,20 @@ class MLP:
         L.check(lib().rbos_mlp_bos_seed(n, _ptr(T.contiguous()), _ptr(grad_delta.contiguous()), rho0G, T0, T_in,
                                         _ptr(out), _stream(stream)))
         return out
+
+
+def fit_seed(out: torch.Tensor, target: torch.Tensor, norms, want_loss: bool = True, stream=None):
+    """Boundary loss sum ((out - target) / norm)^2 over [n][5] outputs: (seed dL/dout, loss)."""
+    n = out.shape[0]
+    o, t = out.contiguous(), target.to(dtype=torch.float32).contiguous()
+    dL = torch.empty_like(o)
+    loss = torch.zeros(1, dtype=torch.float32, device=o.device) if want_loss else None
+    nb = lib().rbos_mlp_fit_workspace_bytes(n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=o.device)
+    nrm = (C.c_double * 5)(*(float(v) for v in norms))
+    L.check(lib().rbos_mlp_fit_seed(n, _ptr(o), _ptr(t), nrm, _ptr(dL), _ptr(loss), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return dL, loss
 
 
 class BOSLoss(torch.autograd.Function):

@@ -553,8 +553,10 @@ size_t rbos_mlp_workspace_bytes(int32_t width, int32_t depth, int64_t n_points) 
 
 namespace {
 
+enum { MLP_WS_PLAIN = 0, MLP_WS_JET = 1 };
+
 int mlp_prepare(const rbos_mlp* m, const float* points, int64_t n, const int32_t* grid, void* ws, size_t ws_bytes,
-                rbos::MlpDev& M, rbos::MlpWork& W) {
+                int ws_kind, rbos::MlpDev& M, rbos::MlpWork& W) {
   if (!m) return fail(RBOS_E_NULL, "mlp is NULL");
   if (rbos_mlp_param_count(m->width, m->depth) == 0)
     return fail(RBOS_E_UNSUPPORTED, "mlp: width must be %d and depth in [1, %d] (got %d, %d)", rbos::MLP_WIDTH,
@@ -565,7 +567,7 @@ int mlp_prepare(const rbos_mlp* m, const float* points, int64_t n, const int32_t
     return fail(RBOS_E_RANGE, "mlp: box must be finite with lo < hi");
   if (n < 0 || n > (1LL << 31)) return fail(RBOS_E_SHAPE, "mlp: n_points must be in [0, 2^31]");
   std::memset(&M, 0, sizeof M);
-  if (!points) {
+  if (!points && n > 0) {
     if (!grid) return fail(RBOS_E_NULL, "mlp: points and grid_dims are both NULL");
     if (grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || (long long)grid[0] * grid[1] * grid[2] != n)
       return fail(RBOS_E_SHAPE, "mlp: grid_dims must be positive with nx*ny*nz == n_points");
@@ -576,7 +578,7 @@ int mlp_prepare(const rbos_mlp* m, const float* points, int64_t n, const int32_t
   if (n > 0) {
     if (!ws) return fail(RBOS_E_WORKSPACE, "mlp: workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(RBOS_E_WORKSPACE, "mlp: workspace must be 256-byte aligned");
-    const size_t need = rbos::mlp_work_bytes(m->depth, n);
+    const size_t need = ws_kind == MLP_WS_JET ? rbos::mlp_jet_work_bytes(m->depth, n) : rbos::mlp_work_bytes(m->depth, n);
     if (ws_bytes < need) return fail(RBOS_E_WORKSPACE, "mlp: workspace too small: %zu < %zu bytes", ws_bytes, need);
   }
   M.depth = m->depth;
@@ -596,7 +598,7 @@ int mlp_prepare(const rbos_mlp* m, const float* points, int64_t n, const int32_t
     M.xs[a] = (float)sc;
     M.xo[a] = (float)(-m->box_lo[a] * sc - 1.0);
   }
-  if (n > 0) rbos::mlp_work_carve(ws, m->depth, n, W);
+  if (n > 0 && ws_kind == MLP_WS_PLAIN) rbos::mlp_work_carve(ws, m->depth, n, W);
   return RBOS_OK;
 }
 
@@ -609,7 +611,7 @@ int rbos_mlp_forward(const rbos_mlp* mlp, const float* points, int64_t n_points,
   g_err.clear();
   rbos::MlpDev M;
   rbos::MlpWork W;
-  int rc = mlp_prepare(mlp, points, n_points, grid_dims, workspace, ws_bytes, M, W);
+  int rc = mlp_prepare(mlp, points, n_points, grid_dims, workspace, ws_bytes, MLP_WS_PLAIN, M, W);
   if (rc) return rc;
   if (T && !(std::isfinite(T0) && std::isfinite(T_in))) return fail(RBOS_E_RANGE, "mlp: T0 and T_in must be finite");
   if (n_points == 0) return RBOS_OK;
@@ -623,7 +625,7 @@ int rbos_mlp_backward(const rbos_mlp* mlp, const float* points, int64_t n_points
   g_err.clear();
   rbos::MlpDev M;
   rbos::MlpWork W;
-  int rc = mlp_prepare(mlp, points, n_points, grid_dims, workspace, ws_bytes, M, W);
+  int rc = mlp_prepare(mlp, points, n_points, grid_dims, workspace, ws_bytes, MLP_WS_PLAIN, M, W);
   if (rc) return rc;
   if (!dparams) return fail(RBOS_E_NULL, "mlp: dparams is NULL");
   if (n_points > 0 && !dL_dout) return fail(RBOS_E_NULL, "mlp: dL_dout is NULL");
@@ -643,6 +645,61 @@ int rbos_mlp_bos_seed(int64_t n, const float* T, const double* grad_delta, doubl
   hipError_t e = rbos::launch_mlp_bos_seed(n, T, grad_delta, rho0G, T0, T_in - T0, dL_dout,
                                            static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(RBOS_E_HIP, "seed launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+size_t rbos_mlp_fit_workspace_bytes(int64_t n_points) {
+  if (n_points < 0) return 0;
+  return ((size_t)((n_points + 255) / 256) * sizeof(float) + 255) / 256 * 256 + 256;
+}
+
+int rbos_mlp_fit_seed(int64_t n, const float* out, const float* target, const double* norms, float* dL_dout,
+                      float* loss, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (n < 0 || n > (1LL << 31)) return fail(RBOS_E_SHAPE, "n must be in [0, 2^31]");
+  if (!norms) return fail(RBOS_E_NULL, "norms is NULL");
+  for (int k = 0; k < rbos::MLP_OUT; ++k)
+    if (!(norms[k] > 0.0) || !std::isfinite(norms[k])) return fail(RBOS_E_RANGE, "norms must be positive and finite");
+  if (n > 0 && (!out || !target || !dL_dout)) return fail(RBOS_E_NULL, "out, target and dL_dout are required");
+  if (loss) {
+    if (!workspace) return fail(RBOS_E_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RBOS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < rbos_mlp_fit_workspace_bytes(n)) return fail(RBOS_E_WORKSPACE, "workspace too small");
+  }
+  hipError_t e = rbos::launch_mlp_fit_seed(n, out, target, norms, dL_dout, loss, static_cast<float*>(workspace),
+                                           static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "fit seed launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
+size_t rbos_mlp_pde_workspace_bytes(int32_t width, int32_t depth, int64_t n_points) {
+  if (rbos_mlp_param_count(width, depth) == 0 || n_points < 0) return 0;
+  return rbos::mlp_jet_work_bytes(depth, n_points);
+}
+
+int rbos_mlp_pde_loss(const rbos_mlp* mlp, const rbos_pde* pde, const float* points, int64_t n_points, float* loss,
+                      float* dparams, float* residuals, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!pde) return fail(RBOS_E_NULL, "pde is NULL");
+  if (n_points > 0 && !points) return fail(RBOS_E_NULL, "points is NULL");
+  if (n_points > (1LL << 28)) return fail(RBOS_E_SHAPE, "n_points must be <= 2^28");
+  rbos::MlpDev M;
+  rbos::MlpWork W;
+  int rc = mlp_prepare(mlp, points, n_points, nullptr, workspace, ws_bytes, MLP_WS_JET, M, W);
+  if (rc) return rc;
+  if (!(pde->Re > 0.0) || !(pde->Pe > 0.0) || !(pde->L > 0.0) || !std::isfinite(pde->Re) || !std::isfinite(pde->Pe) ||
+      !std::isfinite(pde->Ri) || !std::isfinite(pde->L))
+    return fail(RBOS_E_RANGE, "pde: Re, Pe, L must be positive and finite, Ri finite");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pde->gamma[k]) || pde->gamma[k] < 0.0) return fail(RBOS_E_RANGE, "pde: gamma must be >= 0");
+  rbos::PdeConst P;
+  for (int a = 0; a < 3; ++a) P.s[a] = (float)(2.0 * pde->L / (mlp->box_hi[a] - mlp->box_lo[a]));
+  P.inv_re = (float)(1.0 / pde->Re);
+  P.inv_pe = (float)(1.0 / pde->Pe);
+  P.ri = (float)pde->Ri;
+  for (int k = 0; k < 3; ++k) P.g[k] = (float)pde->gamma[k];
+  hipError_t e = rbos::launch_mlp_pde(M, workspace, P, loss, dparams, residuals, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "pde launch failed: %s", hipGetErrorString(e));
   return RBOS_OK;
 }
 
@@ -688,6 +745,10 @@ size_t rbos_struct_layout(int32_t which, size_t* offsets, int32_t max_fields) {
       o = {OFF(rbos_mlp, width), OFF(rbos_mlp, depth), OFF(rbos_mlp, params), OFF(rbos_mlp, box_lo),
            OFF(rbos_mlp, box_hi)};
       sz = sizeof(rbos_mlp);
+      break;
+    case 6:
+      o = {OFF(rbos_pde, Re), OFF(rbos_pde, Pe), OFF(rbos_pde, Ri), OFF(rbos_pde, L), OFF(rbos_pde, gamma)};
+      sz = sizeof(rbos_pde);
       break;
     default:
       return 0;

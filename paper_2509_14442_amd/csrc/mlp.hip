@@ -60,8 +60,10 @@ __global__ __launch_bounds__(256) void k_mlp_first(MlpDev M, float* __restrict__
 }
 
 // One 32-row tile of C = A B (A [n][64], B [64][64] row-major, C [n][64]) per wavefront,
-// then the epilogue: TANH: C = tanh(C + bias); DTANH: C *= 1 - a^2 (a [n][64]).
-template <bool DTANH>
+// then the epilogue: EPI_TANH: C = tanh(C + bias); EPI_DTANH: C *= 1 - a^2 (a [n][64]);
+// EPI_NONE: C as is.
+enum { EPI_TANH = 0, EPI_DTANH = 1, EPI_NONE = 2 };
+template <int EPI>
 __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __restrict__ A, const float* __restrict__ B,
                                                    const float* __restrict__ bias, const float* __restrict__ act,
                                                    float* __restrict__ C) {
@@ -93,17 +95,19 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
   for (int t = 0; t < 2; ++t) {
     const f32x16& acc = t == 0 ? acc0 : acc1;
     const int col = 32 * t + c;
-    const float bc = DTANH ? 0.0f : bias[col];
+    const float bc = EPI == EPI_TANH ? bias[col] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const long long rr = row0 + acc_row(r, h);
       if (rr < n) {
         float v;
-        if constexpr (DTANH) {
+        if constexpr (EPI == EPI_DTANH) {
           const float y = act[rr * MLP_WIDTH + col];
           v = acc[r] * (1.0f - y * y);
-        } else {
+        } else if constexpr (EPI == EPI_TANH) {
           v = tanhf(acc[r] + bc);
+        } else {
+          v = acc[r];
         }
         C[rr * MLP_WIDTH + col] = v;
       }
@@ -151,19 +155,20 @@ __global__ __launch_bounds__(256) void k_mlp_transpose(MlpDev M, float* __restri
   wt[(l - 1) * MLP_WIDTH * MLP_WIDTH + j * MLP_WIDTH + k] = M.params[M.off_w[l] + k * MLP_WIDTH + j];
 }
 
-// Partial parameter gradient of one layer over this block's points:
-// P[m][j] = sum_i A[i][m] B[i][j] (m < 64, j < 64) and P[4096 + j] = sum_i B[i][j].
-// A: the layer's input (XHAT: the normalised positions, 3 columns; else a [n][64]);
-// B: the gradient at its output, ldb columns of which nb are used. One wavefront per
-// block, the points along K in 64-point chunks.
+// Partial parameter gradient of one layer over this block's rows:
+// P[m][j] = sum_i A[i][m] B[i][j] (m < 64, j < 64) and P[4096 + j] = sum_{i < bias_rows} B[i][j].
+// A: the layer's input (XHAT: the first layer's, rows i < M.n the normalised position of
+// point i, rows i = (1 + a) M.n + p the unit vector e_a (the input's derivative along a
+// in a jet); else a [nrows][64]); B: the gradient at its output, ldb columns of which nb
+// are used. One wavefront per block, the rows along K in 64-row chunks.
 template <bool XHAT>
 __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restrict__ A, const float* __restrict__ B,
                                                   int ldb, int nb, float* __restrict__ partial,
-                                                  long long rows_per_block) {
+                                                  long long rows_per_block, long long nrows, long long bias_rows) {
   constexpr int MT = XHAT ? 1 : 2;
   const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
   const long long r0 = (long long)blockIdx.x * rows_per_block;
-  const long long r1 = r0 + rows_per_block < M.n ? r0 + rows_per_block : M.n;
+  const long long r1 = r0 + rows_per_block < nrows ? r0 + rows_per_block : nrows;
   f32x16 acc[MT][2];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = f32x16{};
@@ -176,7 +181,13 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restr
       float a[MT], b[2];
       if constexpr (XHAT) {
         float x[3] = {0.0f, 0.0f, 0.0f};
-        if (ok) xhat(M, row, x);
+        if (ok) {
+          if (row < M.n) {
+            xhat(M, row, x);
+          } else {
+            x[(int)(row / M.n) - 1] = 1.0f;
+          }
+        }
         a[0] = c < 3 ? x[c] : 0.0f;
       } else {
 #pragma unroll
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restr
       for (int nt = 0; nt < 2; ++nt) {
         const int col = 32 * nt + c;
         b[nt] = (ok && col < nb) ? B[row * ldb + col] : 0.0f;
-        bsum[nt] += b[nt];
+        if (row < bias_rows) bsum[nt] += b[nt];
       }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -231,6 +242,277 @@ __global__ __launch_bounds__(256) void k_mlp_bos_seed(long long n, const float* 
   dL[p * MLP_OUT] = (float)(grad[p] * (k / (t * t)));
 #pragma unroll
   for (int o = 1; o < MLP_OUT; ++o) dL[p * MLP_OUT + o] = 0.0f;
+}
+
+// ------------------------------------------------------------------------------------
+// Jets for the PDE residuals: per point 7 channels of every layer's activations, the
+// value (c = 0), its derivative along xhat_d (c = 1 + d) and its second derivative along
+// xhat_d (c = 4 + d), stored channel-major ([7][n][64]). A linear layer maps every
+// channel by the same weights (the bias enters the value only); tanh maps
+// (z, z_d, z_dd) to (y, t z_d, t z_dd - 2 y t z_d^2) with y = tanh z, t = 1 - y^2.
+// ------------------------------------------------------------------------------------
+constexpr int JET = 7;
+
+// first layer: the input's jet is (xhat, e_d, 0)
+__global__ __launch_bounds__(256) void k_jet_first(MlpDev M, float* __restrict__ aj, float* __restrict__ zj) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long p = idx >> 6;
+  const int j = (int)(idx & 63);
+  const long long n = M.n;
+  if (p >= n) return;
+  float x[3];
+  xhat(M, p, x);
+  const float* W = M.params + M.off_w[0];
+  float z = M.params[M.off_b[0] + j];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) z = fmaf(x[a], W[a * MLP_WIDTH + j], z);
+  const float y = tanhf(z), t = 1.0f - y * y;
+  const long long e = p * MLP_WIDTH + j, ch = n * MLP_WIDTH;
+  aj[e] = y;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float zd = W[d * MLP_WIDTH + j];
+    aj[(1 + d) * ch + e] = t * zd;
+    aj[(4 + d) * ch + e] = -2.0f * y * t * zd * zd;
+    zj[d * ch + e] = zd;
+    zj[(3 + d) * ch + e] = 0.0f;
+  }
+}
+
+// a hidden layer on the jets: one wavefront per 32 points and direction d = blockIdx.y
+// (channels 0, 1 + d, 4 + d); the value channel is written by the d = 0 wavefronts
+__global__ __launch_bounds__(256) void k_jet_dense(long long n, const float* __restrict__ aj,
+                                                   const float* __restrict__ W, const float* __restrict__ bias,
+                                                   float* __restrict__ aj_next, float* __restrict__ zj_next) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long row0 = ((long long)blockIdx.x * 4 + wave) * 32;
+  if (row0 >= n) return;
+  const int d = blockIdx.y;
+  const int c = lane & 31, h = lane >> 5;
+  const long long row = row0 + c, ch = n * MLP_WIDTH;
+  const int chans[3] = {0, 1 + d, 4 + d};
+  f32x16 acc[3][2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    acc[q][0] = acc[q][1] = f32x16{};
+    float a[32];
+    if (row < n) {
+      const f32x4* pa = reinterpret_cast<const f32x4*>(aj + chans[q] * ch + row * MLP_WIDTH + 32 * h);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const f32x4 v = pa[k];
+        a[4 * k] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 32; ++s) a[s] = 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      const float* pb = W + (32 * h + s) * MLP_WIDTH;
+      acc[q][0] = mfma32(a[s], pb[c], acc[q][0]);
+      acc[q][1] = mfma32(a[s], pb[32 + c], acc[q][1]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = 32 * t + c;
+    const float bc = bias[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const long long rr = row0 + acc_row(r, h);
+      if (rr < n) {
+        const float y = tanhf(acc[0][t][r] + bc), tp = 1.0f - y * y;
+        const float zd = acc[1][t][r], zdd = acc[2][t][r];
+        const long long e = rr * MLP_WIDTH + col;
+        if (d == 0) aj_next[e] = y;
+        aj_next[(1 + d) * ch + e] = tp * zd;
+        aj_next[(4 + d) * ch + e] = tp * zdd - 2.0f * y * tp * zd * zd;
+        zj_next[d * ch + e] = zd;
+        zj_next[(3 + d) * ch + e] = zdd;
+      }
+    }
+  }
+}
+
+// output layer on the jets: oj [7][n][5]
+__global__ __launch_bounds__(256) void k_jet_out(MlpDev M, const float* __restrict__ aj, float* __restrict__ oj) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = M.n;
+  const long long q = idx >> 3;  // channel-major (c, p)
+  const int o = (int)(idx & 7);
+  if (q >= JET * n || o >= MLP_OUT) return;
+  const int cch = (int)(q / n);
+  const float* W = M.params + M.off_w[M.depth];
+  const float* a = aj + q * MLP_WIDTH;
+  float z = cch == 0 ? M.params[M.off_b[M.depth] + o] : 0.0f;
+  for (int k = 0; k < MLP_WIDTH; ++k) z = fmaf(a[k], W[k * MLP_OUT + o], z);
+  oj[q * MLP_OUT + o] = z;
+}
+
+// Boussinesq residuals (Sec. 2.D) in nondimensional coordinates from the output jets, the
+// per-point loss g1 r_mass^2 + g2 |r_mom|^2 + g3 r_heat^2 (block partials) and its seed
+// on every output channel. Outputs: T_nd, p, u_x, u_y, u_z; gravity along -z.
+__global__ __launch_bounds__(256) void k_pde_seed(long long n, const float* __restrict__ oj, PdeConst P,
+                                                  float* __restrict__ dj, float* __restrict__ res,
+                                                  float* __restrict__ partials) {
+  __shared__ float red[4];
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  float lp = 0.0f;
+  if (p < n) {
+    float v[MLP_OUT], D1[3][MLP_OUT], D2[3][MLP_OUT];
+#pragma unroll
+    for (int k = 0; k < MLP_OUT; ++k) {
+      v[k] = oj[p * MLP_OUT + k];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        D1[d][k] = P.s[d] * oj[((1 + d) * n + p) * MLP_OUT + k];
+        D2[d][k] = P.s[d] * P.s[d] * oj[((4 + d) * n + p) * MLP_OUT + k];
+      }
+    }
+    const float T = v[0];
+    const float u[3] = {v[2], v[3], v[4]};
+    float rmass = 0.0f, rmom[3], rheat = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rmass += D1[d][2 + d];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float conv = 0.0f, lap = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        conv = fmaf(u[d], D1[d][2 + k], conv);
+        lap += D2[d][2 + k];
+      }
+      rmom[k] = conv + D1[k][1] - lap * P.inv_re + (k == 2 ? -P.ri * T : 0.0f);
+    }
+    {
+      float conv = 0.0f, lap = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        conv = fmaf(u[d], D1[d][0], conv);
+        lap += D2[d][0];
+      }
+      rheat = conv - lap * P.inv_pe;
+    }
+    lp = P.g[0] * rmass * rmass + P.g[1] * (rmom[0] * rmom[0] + rmom[1] * rmom[1] + rmom[2] * rmom[2]) +
+         P.g[2] * rheat * rheat;
+    if (res) {
+      res[p * 5] = rmass;
+      res[p * 5 + 1] = rmom[0];
+      res[p * 5 + 2] = rmom[1];
+      res[p * 5 + 3] = rmom[2];
+      res[p * 5 + 4] = rheat;
+    }
+    if (dj) {
+      const float Rm = 2.0f * P.g[0] * rmass, Rh = 2.0f * P.g[2] * rheat;
+      const float Rv[3] = {2.0f * P.g[1] * rmom[0], 2.0f * P.g[1] * rmom[1], 2.0f * P.g[1] * rmom[2]};
+      // value channel
+      dj[p * MLP_OUT] = -P.ri * Rv[2];
+      dj[p * MLP_OUT + 1] = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float g = Rh * D1[d][0];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g = fmaf(Rv[k], D1[d][2 + k], g);
+        dj[p * MLP_OUT + 2 + d] = g;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float* g1 = dj + ((1 + d) * n + p) * MLP_OUT;
+        float* g2 = dj + ((4 + d) * n + p) * MLP_OUT;
+        const float sd = P.s[d], sd2 = sd * sd;
+        g1[0] = Rh * u[d] * sd;
+        g1[1] = Rv[d] * sd;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g1[2 + k] = (Rv[k] * u[d] + (k == d ? Rm : 0.0f)) * sd;
+        g2[0] = -Rh * sd2 * P.inv_pe;
+        g2[1] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g2[2 + k] = -Rv[k] * sd2 * P.inv_re;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) lp += __shfl_xor(lp, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lp;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Reverse of tanh on the jets: from G = dL/d(a channels) [7][n][64] (OUT: from the output
+// seeds dj [7][n][5] through W_D^T), the layer's y = a_0 and its pre-activation
+// derivatives zj [6][n][64], writes dz = dL/d(z channels) [7][n][64].
+template <bool OUT>
+__global__ __launch_bounds__(256) void k_jet_act_back(MlpDev M, const float* __restrict__ G,
+                                                      const float* __restrict__ aj, const float* __restrict__ zj,
+                                                      float* __restrict__ dz) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long n = M.n;
+  const long long p = idx >> 6;
+  const int j = (int)(idx & 63);
+  if (p >= n) return;
+  const long long e = p * MLP_WIDTH + j, ch = n * MLP_WIDTH;
+  float g[JET];
+  if constexpr (OUT) {
+    const float* W = M.params + M.off_w[M.depth];
+#pragma unroll
+    for (int c = 0; c < JET; ++c) {
+      float s = 0.0f;
+#pragma unroll
+      for (int o = 0; o < MLP_OUT; ++o) s = fmaf(G[(c * n + p) * MLP_OUT + o], W[j * MLP_OUT + o], s);
+      g[c] = s;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < JET; ++c) g[c] = G[c * ch + e];
+  }
+  const float y = aj[e], tp = 1.0f - y * y;
+  float d0 = g[0] * tp;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float zd = zj[d * ch + e], zdd = zj[(3 + d) * ch + e];
+    const float gd = g[1 + d], gdd = g[4 + d];
+    dz[(4 + d) * ch + e] = gdd * tp;
+    dz[(1 + d) * ch + e] = gd * tp - 4.0f * gdd * y * tp * zd;
+    d0 += -2.0f * y * tp * (gd * zd + gdd * zdd) - 2.0f * tp * (1.0f - 3.0f * y * y) * gdd * zd * zd;
+  }
+  dz[e] = d0;
+}
+
+// Boundary-type loss: per point sum_k ((out_k - target_k) / norm_k)^2 and its seed
+// dL/dout_k = 2 (out_k - target_k) / norm_k^2; per-block partial sums of the loss.
+__global__ __launch_bounds__(256) void k_mlp_fit_seed(long long n, const float* __restrict__ out,
+                                                      const float* __restrict__ target, FitNorms inv,
+                                                      float* __restrict__ dL, float* __restrict__ partials) {
+  __shared__ float red[4];
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  float l = 0.0f;
+  if (p < n) {
+#pragma unroll
+    for (int k = 0; k < MLP_OUT; ++k) {
+      const float r = (out[p * MLP_OUT + k] - target[p * MLP_OUT + k]) * inv.v[k];
+      l = fmaf(r, r, l);
+      dL[p * MLP_OUT + k] = 2.0f * r * inv.v[k];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0 && partials) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// fixed-order sum of the block partials into one value
+__global__ __launch_bounds__(256) void k_sum_partials(const float* __restrict__ partials, int nblk,
+                                                      float* __restrict__ result) {
+  __shared__ float red[4];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < nblk; i += 256) s += partials[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *result = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -278,7 +560,7 @@ hipError_t launch_mlp_forward(const MlpDev& M, const MlpWork& w, float* out, flo
   for (int l = 1; l < M.depth; ++l) {
     const float* ain = w.act + (size_t)(l - 1) * n * MLP_WIDTH;
     float* aout = w.act + (size_t)l * n * MLP_WIDTH;
-    hipLaunchKernelGGL((k_mlp_dense<false>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, ain,
+    hipLaunchKernelGGL((k_mlp_dense<EPI_TANH>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, ain,
                        M.params + M.off_w[l], M.params + M.off_b[l], nullptr, aout);
   }
   if (out || T) {
@@ -300,25 +582,126 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
                        stream, M, w.wt);
   // output layer: dW_D = a_D^T dL, db_D = sum dL; delta_D = (dL W_D^T)(1 - a_D^2)
   hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(64), 0, stream, M, act(D), dL_dout, MLP_OUT, MLP_OUT,
-                     part(D), w.rows_per_block);
+                     part(D), w.rows_per_block, n, n);
   hipLaunchKernelGGL(k_mlp_delta_out, dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, dL_dout, act(D),
                      w.delta[0]);
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
     // dW_l = a_l^T delta_{l+1}; delta_l = (delta_{l+1} W_l^T)(1 - a_l^2)
     hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(64), 0, stream, M, act(l), w.delta[cur], MLP_WIDTH,
-                       MLP_WIDTH, part(l), w.rows_per_block);
-    hipLaunchKernelGGL((k_mlp_dense<true>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, w.delta[cur],
+                       MLP_WIDTH, part(l), w.rows_per_block, n, n);
+    hipLaunchKernelGGL((k_mlp_dense<EPI_DTANH>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, w.delta[cur],
                        w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, act(l), w.delta[cur ^ 1]);
     cur ^= 1;
   }
   hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(64), 0, stream, M, nullptr, w.delta[cur], MLP_WIDTH,
-                     MLP_WIDTH, part(0), w.rows_per_block);
+                     MLP_WIDTH, part(0), w.rows_per_block, n, n);
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? 3 : MLP_WIDTH, fo = l == D ? MLP_OUT : MLP_WIDTH;
     hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_for(fi * fo + fo)), dim3(256), 0, stream, part(l), w.nblk, fi, fo,
                        dparams + M.off_w[l], dparams + M.off_b[l]);
   }
+  return hipGetLastError();
+}
+
+size_t mlp_jet_work_bytes(int depth, long long n) {
+  const long long rows = JET * n;
+  long long nblk = (rows + 63) / 64;
+  if (nblk > 1024) nblk = 1024;
+  if (nblk < 1) nblk = 1;
+  size_t b = 0;
+  b += al256(sizeof(float) * (size_t)depth * JET * (size_t)n * MLP_WIDTH);        // a jets
+  b += al256(sizeof(float) * (size_t)depth * (JET - 1) * (size_t)n * MLP_WIDTH);  // z jets
+  b += 2 * al256(sizeof(float) * JET * (size_t)n * MLP_OUT);                      // output jets, seeds
+  b += 3 * al256(sizeof(float) * JET * (size_t)n * MLP_WIDTH);                    // dz x 2, G
+  b += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
+  b += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
+  b += al256(sizeof(float) * (size_t)((n + 255) / 256 + 1));
+  return b;
+}
+
+hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* loss, float* dparams, float* residuals,
+                          hipStream_t stream) {
+  const long long n = M.n;
+  const int D = M.depth;
+  if (n == 0) {
+    if (loss) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, (const float*)nullptr, 0, loss);
+    return hipGetLastError();
+  }
+  const long long rows = JET * n;
+  long long nblk = (rows + 63) / 64;
+  if (nblk > 1024) nblk = 1024;
+  if (nblk < 1) nblk = 1;
+  const long long rpb = ((rows + nblk - 1) / nblk + 63) / 64 * 64;
+  unsigned char* q = static_cast<unsigned char*>(ws);
+  auto take = [&](size_t bytes) {
+    float* f = reinterpret_cast<float*>(q);
+    q += al256(bytes);
+    return f;
+  };
+  const size_t chw = sizeof(float) * (size_t)n * MLP_WIDTH;
+  float* aj = take(chw * JET * D);
+  float* zj = take(chw * (JET - 1) * D);
+  float* oj = take(sizeof(float) * JET * (size_t)n * MLP_OUT);
+  float* dj = take(sizeof(float) * JET * (size_t)n * MLP_OUT);
+  float* dz[2] = {take(chw * JET), take(chw * JET)};
+  float* G = take(chw * JET);
+  float* wt = take(sizeof(float) * (size_t)(D > 1 ? D - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
+  float* partial = take(sizeof(float) * (size_t)(D + 1) * (size_t)nblk * MLP_PART);
+  float* lpart = take(sizeof(float) * (size_t)((n + 255) / 256 + 1));
+  auto A = [&](int l) { return aj + (size_t)(l - 1) * JET * n * MLP_WIDTH; };       // a_l jets, l = 1 .. D
+  auto Z = [&](int l) { return zj + (size_t)(l - 1) * (JET - 1) * n * MLP_WIDTH; };  // z_l jets
+  auto part = [&](int l) { return partial + (size_t)l * nblk * MLP_PART; };
+  const unsigned tiles = (unsigned)((n + 127) / 128);
+  // forward
+  hipLaunchKernelGGL(k_jet_first, dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, A(1), Z(1));
+  for (int l = 1; l < D; ++l)
+    hipLaunchKernelGGL(k_jet_dense, dim3(tiles, 3), dim3(256), 0, stream, n, A(l), M.params + M.off_w[l],
+                       M.params + M.off_b[l], A(l + 1), Z(l + 1));
+  hipLaunchKernelGGL(k_jet_out, dim3(blocks_for(rows * 8)), dim3(256), 0, stream, M, A(D), oj);
+  hipLaunchKernelGGL(k_pde_seed, dim3(blocks_for(n)), dim3(256), 0, stream, n, oj, P, dparams ? dj : nullptr,
+                     residuals, lpart);
+  if (loss) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, lpart, blocks_for(n), loss);
+  if (!dparams) return hipGetLastError();
+  // reverse
+  if (D > 1)
+    hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)(D - 1) * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0,
+                       stream, M, wt);
+  hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(64), 0, stream, M, A(D), dj, MLP_OUT, MLP_OUT,
+                     part(D), rpb, rows, n);
+  hipLaunchKernelGGL((k_jet_act_back<true>), dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, dj, A(D),
+                     Z(D), dz[0]);
+  int cur = 0;
+  for (int l = D - 1; l >= 1; --l) {
+    // dW_l = sum_c a_l^c^T dz_{l+1}^c (bias: value channel); G = dz_{l+1} W_l^T; dz_l
+    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(64), 0, stream, M, A(l), dz[cur], MLP_WIDTH,
+                       MLP_WIDTH, part(l), rpb, rows, n);
+    hipLaunchKernelGGL((k_mlp_dense<EPI_NONE>), dim3((unsigned)((rows + 127) / 128)), dim3(256), 0, stream, rows,
+                       dz[cur], wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, nullptr, G);
+    hipLaunchKernelGGL((k_jet_act_back<false>), dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, G, A(l),
+                       Z(l), dz[cur ^ 1]);
+    cur ^= 1;
+  }
+  // first layer: the input jet (xhat, e_d, 0): rows 0 .. 4n of dz_1
+  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3((unsigned)nblk), dim3(64), 0, stream, M, nullptr, dz[cur], MLP_WIDTH,
+                     MLP_WIDTH, part(0), rpb, 4 * n, n);
+  for (int l = 0; l <= D; ++l) {
+    const int fi = l == 0 ? 3 : MLP_WIDTH, fo = l == D ? MLP_OUT : MLP_WIDTH;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_for(fi * fo + fo)), dim3(256), 0, stream, part(l), (int)nblk, fi, fo,
+                       dparams + M.off_w[l], dparams + M.off_b[l]);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_fit_seed(long long n, const float* out, const float* target, const double* norms, float* dL_dout,
+                               float* loss, float* partials, hipStream_t stream) {
+  FitNorms inv;
+  for (int k = 0; k < MLP_OUT; ++k) inv.v[k] = (float)(1.0 / norms[k]);
+  const int nblk = blocks_for(n);
+  if (n > 0)
+    hipLaunchKernelGGL(k_mlp_fit_seed, dim3(nblk), dim3(256), 0, stream, n, out, target, inv, dL_dout,
+                       loss ? partials : nullptr);
+  if (loss) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, partials, n > 0 ? nblk : 0, loss);
   return hipGetLastError();
 }
 

@@ -50,4 +50,25 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
 hipError_t launch_mlp_bos_seed(long long n, const float* T, const double* grad_delta, double rho0G, double T0,
                                double dT, float* dL_dout, hipStream_t stream);
 
+// boundary-type loss sum_points sum_k ((out_k - target_k) / norm_k)^2: seed dL/dout and
+// (nullable) the loss, reduced in a fixed order through `partials` (one float per 256
+// points)
+struct FitNorms {
+  float v[MLP_OUT];  // 1 / norm_k
+};
+hipError_t launch_mlp_fit_seed(long long n, const float* out, const float* target, const double* norms, float* dL_dout,
+                               float* loss, float* partials, hipStream_t stream);
+
+// PDE loss (Sec. 2.D) on the jets of the MLP: s_d = d xhat_d / d x_nd = 2 L / (hi - lo)
+struct PdeConst {
+  float s[3];
+  float inv_re, inv_pe, ri;
+  float g[3];  // weights of the mass, momentum and heat residuals
+};
+size_t mlp_jet_work_bytes(int depth, long long n);
+// forward jets, residuals [n][5] (nullable), loss (nullable) and, with dparams, the
+// parameter gradient added into dparams
+hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* loss, float* dparams, float* residuals,
+                          hipStream_t stream);
+
 }  // namespace rbos

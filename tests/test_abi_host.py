@@ -229,3 +229,29 @@ def test_mlp_entry_point_validation(lib):
                                  None) == -3
     assert lib.rbos_mlp_bos_seed(10, None, C.c_void_p(0x20), 2.7e-4, 293.0, 303.0, C.c_void_p(0x30), None) == -1
     assert lib.rbos_mlp_bos_seed(0, None, None, 2.7e-4, 293.0, 303.0, None, None) == 0
+
+
+def test_pde_and_fit_validation(lib):
+    m = L.rbos_mlp(64, 3, 0x1000, L.D3(0, 0, 0), L.D3(1, 1, 1))
+    pde = L.rbos_pde(50.0, 35.0, 0.8, 0.5, L.D3(1, 1, 1))
+    nb = lib.rbos_mlp_pde_workspace_bytes(64, 3, 100)
+    assert nb > 7 * 100 * 64 * 4 * 3
+    ws = C.c_void_p(0x100000)
+
+    def call(mm=m, pp=pde, pts=0x2000, n=100, w=ws, nbytes=nb):
+        return lib.rbos_mlp_pde_loss(C.byref(mm), C.byref(pp) if pp is not None else None,
+                                     C.c_void_p(pts) if pts else None, n, C.c_void_p(0x3000), None, None, w, nbytes,
+                                     None)
+
+    assert call(pp=None) == -1
+    assert call(pts=0) == -1
+    assert call(pp=L.rbos_pde(0.0, 35.0, 0.8, 0.5, L.D3(1, 1, 1))) == -3
+    assert call(pp=L.rbos_pde(50.0, 35.0, 0.8, 0.5, L.D3(1, -1, 1))) == -3
+    assert call(nbytes=nb - 1) == -5
+    assert call(mm=L.rbos_mlp(64, 9, 0x1000, L.D3(0, 0, 0), L.D3(1, 1, 1))) == -7
+    nrm = (C.c_double * 5)(1, 1, 1, 1, 0)
+    assert lib.rbos_mlp_fit_seed(10, C.c_void_p(0x10), C.c_void_p(0x20), nrm, C.c_void_p(0x30), None, None, 0,
+                                 None) == -3
+    nrm = (C.c_double * 5)(1, 1, 1, 1, 1)
+    assert lib.rbos_mlp_fit_seed(10, C.c_void_p(0x10), C.c_void_p(0x20), nrm, C.c_void_p(0x30), C.c_void_p(0x40),
+                                 None, 0, None) == -5

@@ -125,3 +125,54 @@ def test_bos_loss_parameter_gradient_end_to_end():
     l2, _ = grad_errors(g, ref)
     print(f"end-to-end dparams rel-L2 {l2:.2e}")
     assert l2 < 1e-3
+
+
+def test_boundary_loss_and_gradient():
+    """Boundary loss on the x = lo face (the paper's inlet plane), targets from a second
+    network, normalisers from the targets."""
+    m, th = _mlp(4, 20, scale=0.5)
+    _, th_t = _mlp(4, 21, scale=0.5)
+    rng = np.random.default_rng(22)
+    n = 4096 + 17
+    x = np.column_stack([np.full(n, LO[0]), rng.uniform(LO[1], HI[1], n), rng.uniform(LO[2], HI[2], n)])
+    x = x.astype(np.float32)
+    tgt = omlp.forward(th_t, 64, 4, x.astype(np.float64), LO, HI)
+    norms = omlp.boundary_norms(tgt)
+    L_ref, g_ref = omlp.boundary_loss(th, 64, 4, x.astype(np.float64), LO, HI, tgt, norms)
+    xt = torch.from_numpy(x).to(DEV)
+    out, _ = m.forward(xt)
+    dL, loss = api.fit_seed(out, torch.from_numpy(tgt.astype(np.float32)).to(DEV), norms)
+    g = _np(m.backward(dL, xt)).astype(np.float64)
+    assert float(loss[0]) == pytest.approx(L_ref, rel=1e-5)
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"boundary loss {float(loss[0]):.6g} (oracle {L_ref:.6g}), dparams rel-L2 {rel:.2e}")
+    assert rel < 1e-5
+
+
+PDE = dict(Re=50.0, Pe=35.0, Ri=0.8, L=0.5, g1=1.0, g2=0.5, g3=2.0)
+
+
+@pytest.mark.parametrize("depth,n", [(1, 37), (3, 2000), (4, 8192)])
+def test_pde_loss_residuals_and_gradient(depth, n):
+    """The paper's mini-batch holds 8192 collocation points per step."""
+    m, th = _mlp(depth, 30 + depth, scale=0.5)
+    rng = np.random.default_rng(40 + depth)
+    x = rng.uniform(LO, HI, (n, 3)).astype(np.float32)
+    x64 = x.astype(np.float64)
+    L_ref, g_ref = omlp.pde_loss(th, 64, depth, x64, LO, HI, PDE)
+    rm, rv, rh = omlp.pde_residuals(th, 64, depth, x64, LO, HI, PDE)
+    res_ref = np.column_stack([rm, rv, rh])
+    loss, g, res = m.pde_loss(torch.from_numpy(x).to(DEV), PDE["Re"], PDE["Pe"], PDE["Ri"], PDE["L"],
+                              (PDE["g1"], PDE["g2"], PDE["g3"]), want_residuals=True)
+    res, g = _np(res).astype(np.float64), _np(g).astype(np.float64)
+    e_res = np.abs(res - res_ref).max() / np.abs(res_ref).max()
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"depth {depth}, {n} points: loss {float(loss[0]):.6g} (oracle {L_ref:.6g}), residuals max err "
+          f"{e_res:.2e} of max, dparams rel-L2 {rel:.2e}")
+    assert float(loss[0]) == pytest.approx(L_ref, rel=1e-4)
+    assert e_res < 1e-4
+    assert rel < 1e-4
+    # loss and residuals alone (no gradient) give the same values
+    loss2, g2, _ = m.pde_loss(torch.from_numpy(x).to(DEV), PDE["Re"], PDE["Pe"], PDE["Ri"], PDE["L"],
+                              (PDE["g1"], PDE["g2"], PDE["g3"]), want_grad=False)
+    assert g2 is None and float(loss2[0]) == float(loss[0])
