@@ -61,6 +61,12 @@ def parse(argv=None):
     p.add_argument("--radiometry", type=int, default=0, choices=[0, 1],
                    help="weight each ray by |<n_w, v_w>| / |X_w - c|")
     p.add_argument("--sample-seed", type=int, default=1, help="sub-pixel sample key")
+    p.add_argument("--field", default="grid", choices=["grid", "mlp"],
+                   help="mlp: voxel temperatures from the network field, plus its boundary and PDE losses "
+                        "(room1m only)")
+    p.add_argument("--mlp-depth", type=int, default=4, help="network field: hidden layers of 64 units")
+    p.add_argument("--pde-points", type=int, default=8192, help="network field: collocation points per step")
+    p.add_argument("--boundary-points", type=int, default=4096, help="network field: inlet-plane points per step")
     p.add_argument("--ckpt", type=int, default=8, help="checkpoint stride (steps)")
     p.add_argument("--tile", default="8x8", help="forward: rays per wavefront tile")
     p.add_argument("--wpb", type=int, default=4, help="forward: wavefronts per block")
@@ -219,8 +225,76 @@ class Workload:
         self.tracer = api.Tracer(self.scenes, launch, checkpoints=True, adjoint_launch=adj_launch)
         self.fwd_only = api.Tracer(self.scenes, launch, checkpoints=False)
         self.grads = [torch.zeros(tuple(reversed(s.dims)), dtype=torch.float64, device=dev) for s in self.scenes]
+        self.mlp = None
+        if args.field == "mlp":
+            self._setup_mlp(args, dev)
+
+    def _setup_mlp(self, args, dev):
+        """Network field (Sec. 2.D): the voxel temperatures come from an MLP; the target
+        image is the render of a second network's field; the boundary targets are that
+        network's outputs on the inlet plane; collocation points are uniform in the box."""
+        import numpy as np
+        import torch
+
+        import bos_inputs as bi
+        from paper_2509_14442_amd import api
+
+        if args.workload != "room1m":
+            raise SystemExit("--field mlp runs on the room1m workload")
+        desc = self.descs[0]
+        lo, hi, dims = desc.box_lo, desc.box_hi, desc.dims
+        self.T0, self.T_in = 293.0, 303.0
+        D = args.mlp_depth
+
+        def net(seed):
+            th = bi.mlp_params(64, D, seed, out_scale=0.3, bias_std=0.05).astype(np.float32)
+            return api.MLP(torch.from_numpy(th).to(dev), 64, D, lo, hi)
+
+        self.mlp = net(3)
+        target_net = net(4)
+        _, TB = target_net.forward(grid=dims, want_out=False, T0=self.T0, T_in=self.T_in)
+        fB = api.Field.from_temperature(TB.reshape(tuple(reversed(dims))), args.dtype, self.fields[0].scale,
+                                        args.offset)
+        trB = api.Tracer([api.Scene(desc, fB, self.pat)], self.launch, checkpoints=False)
+        trB.forward().render()
+        self.targets = [trB.image[0].clone()]
+        del trB, fB
+        self.pts_b = torch.from_numpy(bi.inlet_points(args.boundary_points, lo, hi, 5).astype(np.float32)).to(dev)
+        self.tgt_b, _ = target_net.forward(self.pts_b)
+        tb = self.tgt_b.double()
+        un = float(tb[:, 2:5].norm(dim=1).max())
+        self.norms_b = [float(tb[:, 0].abs().max()), float(tb[:, 1].abs().max()), un, un, un]
+        self.pts_c = torch.from_numpy(bi.collocation_points(args.pde_points, lo, hi, 6).astype(np.float32)).to(dev)
+        self.pde = dict(Re=100.0, Pe=70.0, Ri=0.5, L=1.0, gamma=(1.0, 1.0, 1.0))
+        self.dparams = torch.zeros_like(self.mlp.params)
+        self.T_grid = None
+        self.data_note = ("synthetic: temperatures from a seeded MLP; target = render of a second seeded MLP's "
+                          "field; boundary data = its outputs on the inlet plane")
+
+    def mlp_forward(self):
+        dims = self.descs[0].dims
+        _, self.T_grid = self.mlp.forward(grid=dims, want_out=False, T0=self.T0, T_in=self.T_in)
+        self.fields[0].encode_temperature(self.T_grid.reshape(tuple(reversed(dims))))
+
+    def mlp_backward(self):
+        """BOS chain, boundary loss and PDE loss, all added into dparams."""
+        from paper_2509_14442_amd import api
+
+        dims = self.descs[0].dims
+        self.dparams.zero_()
+        seed = api.MLP.bos_seed(self.T_grid, self.grads[0].reshape(-1), self.T0, self.T_in)
+        self.mlp.backward(seed, grid=dims, dparams=self.dparams)
+        out_b, _ = self.mlp.forward(self.pts_b)
+        dL_b, self.loss_b = api.fit_seed(out_b, self.tgt_b, self.norms_b)
+        self.mlp.backward(dL_b, self.pts_b, dparams=self.dparams)
+        P = self.pde
+        self.loss_pde, _, _ = self.mlp.pde_loss(self.pts_c, P["Re"], P["Pe"], P["Ri"], P["L"], P["gamma"],
+                                                dparams=self.dparams)
 
     def encode(self):
+        if self.mlp is not None:
+            self.mlp_forward()
+            return
         for f, T in zip(self.fields, self.temps):
             f.encode_temperature(T)
 
@@ -231,6 +305,8 @@ class Workload:
         for g in self.grads:
             g.zero_()
         self.tracer.adjoint(self.grads, zero=False)
+        if self.mlp is not None:
+            self.mlp_backward()
 
 
 def main():
@@ -290,8 +366,8 @@ def main():
 
     # per-kernel timing with HIP events on the stream the kernels run on
     cur = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    acc = np.zeros(5)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    acc = np.zeros(6)
     for _ in range(args.steps):
         ev[0].record(cur)
         W.encode()
@@ -305,9 +381,13 @@ def main():
         ev[4].record(cur)
         tr.adjoint(W.grads, zero=False)
         ev[5].record(cur)
+        if W.mlp is not None:
+            W.mlp_backward()
+        ev[6].record(cur)
         torch.cuda.synchronize()
-        acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(5)]
+        acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(6)]
     k_ms = acc / args.steps
+    mlp_info = mlp_timing(args, W, cur) if W.mlp is not None else None
     fwd_ms = 0.0
     for _ in range(args.steps):
         ev[0].record(cur)
@@ -358,8 +438,9 @@ def main():
         "loss": loss,
         "fwd_ray_steps_per_s": ray_steps / (fwd_ms * 1e-3),
         "fwd_ms": fwd_ms,
-        "kernel_ms": {"field_encode": k_ms[0], "trace_fwd_ckpt": k_ms[1], "render_loss": k_ms[2],
-                      "grad_zero": k_ms[3], "trace_adjoint": k_ms[4]},
+        "kernel_ms": {("mlp_forward_and_encode" if W.mlp is not None else "field_encode"): k_ms[0],
+                      "trace_fwd_ckpt": k_ms[1], "render_loss": k_ms[2], "grad_zero": k_ms[3],
+                      "trace_adjoint": k_ms[4], **({"mlp_backward_all_losses": k_ms[5]} if W.mlp is not None else {})},
         "roofline": {
             "kernel": "k_trace_adj (adjoint)",
             "bound": "alu",
@@ -373,11 +454,61 @@ def main():
     }
     if hasattr(W, "tuned"):
         out["config"]["autotune"] = W.tuned
-    if not args.no_cpu and args.workload == "room1m":
+    if mlp_info is not None:
+        out["config"]["workload"] += (", temperatures from an MLP (64 units x %d tanh layers) at the 2,097,152 voxel "
+                                      "centres, boundary loss on %d inlet points, Boussinesq PDE loss on %d "
+                                      "collocation points" % (args.mlp_depth, args.boundary_points, args.pde_points))
+        out["config"]["field"] = "mlp"
+        out["mlp"] = mlp_info
+    if not args.no_cpu and args.workload == "room1m" and W.mlp is None:
         out["cpu_baseline"], out["err"] = cpu_baseline_and_errors(args, W)
     if args.workload == "room256" and not args.no_cpu:
         out["err"] = subsample_errors(args, W)
     print(json.dumps(out), flush=True)
+
+
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix (published)
+
+
+def mlp_timing(args, W, cur):
+    """HIP-event times of the network-field parts and the MFMA work of the grid forward."""
+    import torch
+
+    from paper_2509_14442_amd import api
+
+    dims = W.descs[0].dims
+    n = dims[0] * dims[1] * dims[2]
+    D = args.mlp_depth
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    acc = [0.0] * 4
+    for _ in range(args.steps):
+        ev[0].record(cur)
+        _, T = W.mlp.forward(grid=dims, want_out=False, T0=W.T0, T_in=W.T_in)
+        ev[1].record(cur)
+        seed = api.MLP.bos_seed(T, W.grads[0].reshape(-1), W.T0, W.T_in)
+        W.mlp.backward(seed, grid=dims, dparams=W.dparams)
+        ev[2].record(cur)
+        out_b, _ = W.mlp.forward(W.pts_b)
+        dL_b, _ = api.fit_seed(out_b, W.tgt_b, W.norms_b)
+        W.mlp.backward(dL_b, W.pts_b, dparams=W.dparams)
+        ev[3].record(cur)
+        P = W.pde
+        W.mlp.pde_loss(W.pts_c, P["Re"], P["Pe"], P["Ri"], P["L"], P["gamma"], dparams=W.dparams)
+        ev[4].record(cur)
+        torch.cuda.synchronize()
+        for i in range(4):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    ms = [a / args.steps for a in acc]
+    flop_point = 2 * (3 * 64 + (D - 1) * 64 * 64 + 64 * 5)
+    achieved = flop_point * n / (ms[0] * 1e-3) / 1e12
+    return {
+        "grid_forward_ms": ms[0], "bos_chain_backward_ms": ms[1], "boundary_loss_ms": ms[2], "pde_loss_ms": ms[3],
+        "params": int(W.mlp.params.numel()), "loss_boundary": float(W.loss_b[0]), "loss_pde": float(W.loss_pde[0]),
+        "roofline_grid_forward": {"kernels": "k_mlp_first + k_mlp_dense x %d + k_mlp_out" % (D - 1), "bound": "mfma",
+                                  "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "flop_per_point": flop_point,
+                                  "points": n},
+    }
 
 
 def _stored_delta(T, dtype, scale, offset):

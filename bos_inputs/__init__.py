@@ -33,3 +33,4 @@ from .fields import (  # noqa: F401
 )
 from .patterns import binary_dots, blurred_noise  # noqa: F401
 from .subsets import pixel_subset, strided_tiles  # noqa: F401
+from .network import mlp_params, mlp_param_shapes, inlet_points, collocation_points  # noqa: F401

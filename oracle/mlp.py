@@ -83,19 +83,6 @@ def voxel_centres(lo, hi, dims) -> np.ndarray:
     return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
 
 
-def init_params(width: int, depth: int, seed: int, out_scale: float = 1.0) -> np.ndarray:
-    """Glorot-uniform weights, zero biases (seeded; random initialisation stands in for a
-    trained network). The last layer is scaled by out_scale."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    shapes = layer_shapes(width, depth)
-    for i, (fi, fo) in enumerate(shapes):
-        lim = np.sqrt(6.0 / (fi + fo))
-        W = rng.uniform(-lim, lim, (fi, fo)) * (out_scale if i == len(shapes) - 1 else 1.0)
-        parts += [W.ravel(), np.zeros(fo)]
-    return np.concatenate(parts)
-
-
 # ------------------------------------------------------------------------------------
 # reverse mode with respect to the parameters
 # ------------------------------------------------------------------------------------

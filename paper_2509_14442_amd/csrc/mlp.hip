@@ -24,6 +24,14 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// tanh x = 1 - 2 / (exp(2x) + 1), with the hardware base-2 exponential (2x / ln 2) and
+// reciprocal: absolute error ~1e-7, saturating to +-1 for large |x|. The library tanhf
+// costs more VALU cycles than a layer's matrix products.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 // Row of the 32 x 32 accumulator held in register r of a lane in half h (its column is
 // the lane index mod 32).
 __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
@@ -44,19 +52,26 @@ __device__ __forceinline__ void xhat(const MlpDev& M, long long p, float x[3]) {
   }
 }
 
-// a_1 = tanh(xhat W_0 + b_0): one thread per (point, unit)
-__global__ __launch_bounds__(256) void k_mlp_first(MlpDev M, float* __restrict__ a1) {
+// a_1 = tanh(xhat W_0 + b_0): one thread per (point, 4 units); xh [n][4] keeps the inputs
+// (the fourth column 0) for the first layer's parameter gradient
+__global__ __launch_bounds__(256) void k_mlp_first(MlpDev M, float* __restrict__ a1, float* __restrict__ xh) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long p = idx >> 6;
-  const int j = (int)(idx & 63);
+  const long long p = idx >> 4;
+  const int j0 = (int)(idx & 15) * 4;
   if (p >= M.n) return;
   float x[3];
   xhat(M, p, x);
+  if (j0 == 0) *reinterpret_cast<f32x4*>(xh + p * 4) = f32x4{x[0], x[1], x[2], 0.0f};
   const float* W = M.params + M.off_w[0];
-  float z = M.params[M.off_b[0] + j];
+  float z[4];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) z = fmaf(x[a], W[a * MLP_WIDTH + j], z);
-  a1[p * MLP_WIDTH + j] = tanhf(z);
+  for (int i = 0; i < 4; ++i) {
+    z[i] = M.params[M.off_b[0] + j0 + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) z[i] = fmaf(x[a], W[a * MLP_WIDTH + j0 + i], z[i]);
+  }
+  *reinterpret_cast<f32x4*>(a1 + p * MLP_WIDTH + j0) =
+      f32x4{tanh_fast(z[0]), tanh_fast(z[1]), tanh_fast(z[2]), tanh_fast(z[3])};
 }
 
 // One 32-row tile of C = A B (A [n][64], B [64][64] row-major, C [n][64]) per wavefront,
@@ -105,7 +120,7 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
           const float y = act[rr * MLP_WIDTH + col];
           v = acc[r] * (1.0f - y * y);
         } else if constexpr (EPI == EPI_TANH) {
-          v = tanhf(acc[r] + bc);
+          v = tanh_fast(acc[r] + bc);
         } else {
           v = acc[r];
         }
@@ -115,35 +130,55 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
   }
 }
 
-// out = a_D W_D + b_D (and T = T0 + dT out_0): one thread per (point, output), 8 slots
-// per point
+// out = a_D W_D + b_D (and T = T0 + dT out_0): one thread per point, its row read with
+// 16-byte loads
 __global__ __launch_bounds__(256) void k_mlp_out(MlpDev M, const float* __restrict__ aD, float* __restrict__ out,
                                                  float* __restrict__ T, float T0, float dT) {
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long p = idx >> 3;
-  const int o = (int)(idx & 7);
-  if (p >= M.n || o >= MLP_OUT) return;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= M.n) return;
   const float* W = M.params + M.off_w[M.depth];
-  const float* a = aD + p * MLP_WIDTH;
-  float z = M.params[M.off_b[M.depth] + o];
-  for (int k = 0; k < MLP_WIDTH; ++k) z = fmaf(a[k], W[k * MLP_OUT + o], z);
-  if (out) out[p * MLP_OUT + o] = z;
-  if (T && o == 0) T[p] = fmaf(dT, z, T0);
+  const float* bo = M.params + M.off_b[M.depth];
+  const f32x4* a4 = reinterpret_cast<const f32x4*>(aD + p * MLP_WIDTH);
+  float z[MLP_OUT];
+#pragma unroll
+  for (int o = 0; o < MLP_OUT; ++o) z[o] = bo[o];
+#pragma unroll 4
+  for (int q = 0; q < MLP_WIDTH / 4; ++q) {
+    const f32x4 v = a4[q];
+    const float a[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int o = 0; o < MLP_OUT; ++o) z[o] = fmaf(a[i], W[(4 * q + i) * MLP_OUT + o], z[o]);
+  }
+  if (out)
+#pragma unroll
+    for (int o = 0; o < MLP_OUT; ++o) out[p * MLP_OUT + o] = z[o];
+  if (T) T[p] = fmaf(dT, z[0], T0);
 }
 
-// delta_D = (dL/dout W_D^T) (1 - a_D^2): one thread per (point, unit)
+// delta_D = (dL/dout W_D^T) (1 - a_D^2): one thread per (point, 4 units)
 __global__ __launch_bounds__(256) void k_mlp_delta_out(MlpDev M, const float* __restrict__ dL,
                                                        const float* __restrict__ aD, float* __restrict__ delta) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long p = idx >> 6;
-  const int j = (int)(idx & 63);
+  const long long p = idx >> 4;
+  const int j0 = (int)(idx & 15) * 4;
   if (p >= M.n) return;
   const float* W = M.params + M.off_w[M.depth];
-  float g = 0.0f;
+  float l[MLP_OUT];
 #pragma unroll
-  for (int o = 0; o < MLP_OUT; ++o) g = fmaf(dL[p * MLP_OUT + o], W[j * MLP_OUT + o], g);
-  const float y = aD[p * MLP_WIDTH + j];
-  delta[p * MLP_WIDTH + j] = g * (1.0f - y * y);
+  for (int o = 0; o < MLP_OUT; ++o) l[o] = dL[p * MLP_OUT + o];
+  const f32x4 y = *reinterpret_cast<const f32x4*>(aD + p * MLP_WIDTH + j0);
+  const float yv[4] = {y.x, y.y, y.z, y.w};
+  float r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float g = 0.0f;
+#pragma unroll
+    for (int o = 0; o < MLP_OUT; ++o) g = fmaf(l[o], W[(j0 + i) * MLP_OUT + o], g);
+    r[i] = g * (1.0f - yv[i] * yv[i]);
+  }
+  *reinterpret_cast<f32x4*>(delta + p * MLP_WIDTH + j0) = f32x4{r[0], r[1], r[2], r[3]};
 }
 
 // WT_l = W_l^T for the hidden layers l = 1 .. depth - 1
@@ -158,8 +193,8 @@ __global__ __launch_bounds__(256) void k_mlp_transpose(MlpDev M, float* __restri
 // Partial parameter gradient of one layer over this block's rows:
 // P[m][j] = sum_i A[i][m] B[i][j] (m < 64, j < 64) and P[4096 + j] = sum_{i < bias_rows} B[i][j].
 // A: the layer's input (XHAT: the first layer's, rows i < M.n the normalised position of
-// point i, rows i = (1 + a) M.n + p the unit vector e_a (the input's derivative along a
-// in a jet); else a [nrows][64]); B: the gradient at its output, ldb columns of which nb
+// point i from xh [n][4], rows i = (1 + a) M.n + p the unit vector e_a (the input's
+// derivative along a in a jet); else a [nrows][64]); B: the gradient at its output, ldb columns of which nb
 // are used. One wavefront per block, the rows along K in 64-row chunks.
 template <bool XHAT>
 __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restrict__ A, const float* __restrict__ B,
@@ -180,15 +215,10 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restr
       const bool ok = row < r1;
       float a[MT], b[2];
       if constexpr (XHAT) {
-        float x[3] = {0.0f, 0.0f, 0.0f};
-        if (ok) {
-          if (row < M.n) {
-            xhat(M, row, x);
-          } else {
-            x[(int)(row / M.n) - 1] = 1.0f;
-          }
-        }
-        a[0] = c < 3 ? x[c] : 0.0f;
+        // A = xh [n][4] for the value rows, e_a for the rows of the input's derivative along a
+        float x = 0.0f;
+        if (ok && c < 3) x = row < M.n ? A[row * 4 + c] : (c == (int)(row / M.n) - 1 ? 1.0f : 0.0f);
+        a[0] = x;
       } else {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) a[mt] = ok ? A[row * MLP_WIDTH + 32 * mt + c] : 0.0f;
@@ -222,16 +252,30 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restr
   }
 }
 
-// dparams[layer] += sum over blocks (in block order) of the partials: W [fi][fo], b [fo]
+// dparams[layer] += sum over blocks of the partials: W [fi][fo], b [fo]. A block takes 16
+// elements; its 16 thread groups sum the blocks b = g, g + 16, ..., and the groups are
+// added in a fixed order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ partial, int nblk, int fi, int fo,
                                                     float* __restrict__ dW, float* __restrict__ db) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= fi * fo + fo) return;
-  const int src = e < fi * fo ? (e / fo) * MLP_WIDTH + e % fo : MLP_WIDTH * MLP_WIDTH + (e - fi * fo);
+  __shared__ float red[16][17];
+  const int el = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int e = blockIdx.x * 16 + el;
+  const int ne = fi * fo + fo;
   float s = 0.0f;
-  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * MLP_PART + src];
-  if (e < fi * fo) dW[e] += s;
-  else db[e - fi * fo] += s;
+  if (e < ne) {
+    const int src = e < fi * fo ? (e / fo) * MLP_WIDTH + e % fo : MLP_WIDTH * MLP_WIDTH + (e - fi * fo);
+#pragma unroll 8
+    for (int b = g; b < nblk; b += 16) s += partial[(long long)b * MLP_PART + src];
+  }
+  red[g][el] = s;
+  __syncthreads();
+  if (g == 0 && e < ne) {
+    float t = red[0][el];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) t += red[k][el];
+    if (e < fi * fo) dW[e] += t;
+    else db[e - fi * fo] += t;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_mlp_bos_seed(long long n, const float* __restrict__ T,
@@ -253,8 +297,9 @@ __global__ __launch_bounds__(256) void k_mlp_bos_seed(long long n, const float* 
 // ------------------------------------------------------------------------------------
 constexpr int JET = 7;
 
-// first layer: the input's jet is (xhat, e_d, 0)
-__global__ __launch_bounds__(256) void k_jet_first(MlpDev M, float* __restrict__ aj, float* __restrict__ zj) {
+// first layer: the input's jet is (xhat, e_d, 0); xh [n][4] as in k_mlp_first
+__global__ __launch_bounds__(256) void k_jet_first(MlpDev M, float* __restrict__ aj, float* __restrict__ zj,
+                                                   float* __restrict__ xh) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long p = idx >> 6;
   const int j = (int)(idx & 63);
@@ -262,11 +307,12 @@ __global__ __launch_bounds__(256) void k_jet_first(MlpDev M, float* __restrict__
   if (p >= n) return;
   float x[3];
   xhat(M, p, x);
+  if (j < 4) xh[p * 4 + j] = j < 3 ? x[j] : 0.0f;
   const float* W = M.params + M.off_w[0];
   float z = M.params[M.off_b[0] + j];
 #pragma unroll
   for (int a = 0; a < 3; ++a) z = fmaf(x[a], W[a * MLP_WIDTH + j], z);
-  const float y = tanhf(z), t = 1.0f - y * y;
+  const float y = tanh_fast(z), t = 1.0f - y * y;
   const long long e = p * MLP_WIDTH + j, ch = n * MLP_WIDTH;
   aj[e] = y;
 #pragma unroll
@@ -322,7 +368,7 @@ __global__ __launch_bounds__(256) void k_jet_dense(long long n, const float* __r
     for (int r = 0; r < 16; ++r) {
       const long long rr = row0 + acc_row(r, h);
       if (rr < n) {
-        const float y = tanhf(acc[0][t][r] + bc), tp = 1.0f - y * y;
+        const float y = tanh_fast(acc[0][t][r] + bc), tp = 1.0f - y * y;
         const float zd = acc[1][t][r], zdd = acc[2][t][r];
         const long long e = rr * MLP_WIDTH + col;
         if (d == 0) aj_next[e] = y;
@@ -519,24 +565,28 @@ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline int blocks_for(long long threads) { return (int)((threads + 255) / 256); }
 
+// blocks (one wavefront each) of the parameter-gradient reduction over `rows` rows: one
+// per 64 rows up to two per SIMD of the 256 compute units
+inline long long wgrad_blocks(long long rows) {
+  const long long b = (rows + 63) / 64;
+  return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+}
+
 }  // namespace
 
 size_t mlp_work_bytes(int depth, long long n) {
-  long long nblk = (n + 63) / 64;
-  if (nblk > 1024) nblk = 1024;
-  if (nblk < 1) nblk = 1;
+  const long long nblk = wgrad_blocks(n);
   size_t b = 0;
   b += al256(sizeof(float) * (size_t)depth * (size_t)n * MLP_WIDTH);
   b += 2 * al256(sizeof(float) * (size_t)n * MLP_WIDTH);
   b += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
   b += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
+  b += al256(sizeof(float) * 4 * (size_t)n);
   return b;
 }
 
 void mlp_work_carve(void* ws, int depth, long long n, MlpWork& w) {
-  long long nblk = (n + 63) / 64;
-  if (nblk > 1024) nblk = 1024;
-  if (nblk < 1) nblk = 1;
+  const long long nblk = wgrad_blocks(n);
   w.nblk = (int)nblk;
   long long rows = (n + nblk - 1) / nblk;
   w.rows_per_block = (rows + 63) / 64 * 64;
@@ -550,13 +600,15 @@ void mlp_work_carve(void* ws, int depth, long long n, MlpWork& w) {
   w.wt = reinterpret_cast<float*>(p);
   p += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
   w.partial = reinterpret_cast<float*>(p);
+  p += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
+  w.xh = reinterpret_cast<float*>(p);
 }
 
 hipError_t launch_mlp_forward(const MlpDev& M, const MlpWork& w, float* out, float* T, float T0, float dT,
                               hipStream_t stream) {
   if (M.n == 0) return hipSuccess;
   const long long n = M.n;
-  hipLaunchKernelGGL(k_mlp_first, dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, w.act);
+  hipLaunchKernelGGL(k_mlp_first, dim3(blocks_for(n * 16)), dim3(256), 0, stream, M, w.act, w.xh);
   for (int l = 1; l < M.depth; ++l) {
     const float* ain = w.act + (size_t)(l - 1) * n * MLP_WIDTH;
     float* aout = w.act + (size_t)l * n * MLP_WIDTH;
@@ -565,7 +617,7 @@ hipError_t launch_mlp_forward(const MlpDev& M, const MlpWork& w, float* out, flo
   }
   if (out || T) {
     const float* aD = w.act + (size_t)(M.depth - 1) * n * MLP_WIDTH;
-    hipLaunchKernelGGL(k_mlp_out, dim3(blocks_for(n * 8)), dim3(256), 0, stream, M, aD, out, T, T0, dT);
+    hipLaunchKernelGGL(k_mlp_out, dim3(blocks_for(n)), dim3(256), 0, stream, M, aD, out, T, T0, dT);
   }
   return hipGetLastError();
 }
@@ -583,7 +635,7 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
   // output layer: dW_D = a_D^T dL, db_D = sum dL; delta_D = (dL W_D^T)(1 - a_D^2)
   hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(64), 0, stream, M, act(D), dL_dout, MLP_OUT, MLP_OUT,
                      part(D), w.rows_per_block, n, n);
-  hipLaunchKernelGGL(k_mlp_delta_out, dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, dL_dout, act(D),
+  hipLaunchKernelGGL(k_mlp_delta_out, dim3(blocks_for(n * 16)), dim3(256), 0, stream, M, dL_dout, act(D),
                      w.delta[0]);
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
@@ -594,11 +646,11 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
                        w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, act(l), w.delta[cur ^ 1]);
     cur ^= 1;
   }
-  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(64), 0, stream, M, nullptr, w.delta[cur], MLP_WIDTH,
+  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(64), 0, stream, M, w.xh, w.delta[cur], MLP_WIDTH,
                      MLP_WIDTH, part(0), w.rows_per_block, n, n);
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? 3 : MLP_WIDTH, fo = l == D ? MLP_OUT : MLP_WIDTH;
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_for(fi * fo + fo)), dim3(256), 0, stream, part(l), w.nblk, fi, fo,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((fi * fo + fo + 15) / 16), dim3(256), 0, stream, part(l), w.nblk, fi, fo,
                        dparams + M.off_w[l], dparams + M.off_b[l]);
   }
   return hipGetLastError();
@@ -606,9 +658,7 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
 
 size_t mlp_jet_work_bytes(int depth, long long n) {
   const long long rows = JET * n;
-  long long nblk = (rows + 63) / 64;
-  if (nblk > 1024) nblk = 1024;
-  if (nblk < 1) nblk = 1;
+  const long long nblk = wgrad_blocks(rows);
   size_t b = 0;
   b += al256(sizeof(float) * (size_t)depth * JET * (size_t)n * MLP_WIDTH);        // a jets
   b += al256(sizeof(float) * (size_t)depth * (JET - 1) * (size_t)n * MLP_WIDTH);  // z jets
@@ -617,6 +667,7 @@ size_t mlp_jet_work_bytes(int depth, long long n) {
   b += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
   b += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
   b += al256(sizeof(float) * (size_t)((n + 255) / 256 + 1));
+  b += al256(sizeof(float) * 4 * (size_t)n);
   return b;
 }
 
@@ -629,9 +680,7 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
     return hipGetLastError();
   }
   const long long rows = JET * n;
-  long long nblk = (rows + 63) / 64;
-  if (nblk > 1024) nblk = 1024;
-  if (nblk < 1) nblk = 1;
+  const long long nblk = wgrad_blocks(rows);
   const long long rpb = ((rows + nblk - 1) / nblk + 63) / 64 * 64;
   unsigned char* q = static_cast<unsigned char*>(ws);
   auto take = [&](size_t bytes) {
@@ -649,12 +698,13 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
   float* wt = take(sizeof(float) * (size_t)(D > 1 ? D - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
   float* partial = take(sizeof(float) * (size_t)(D + 1) * (size_t)nblk * MLP_PART);
   float* lpart = take(sizeof(float) * (size_t)((n + 255) / 256 + 1));
+  float* xh = take(sizeof(float) * 4 * (size_t)n);
   auto A = [&](int l) { return aj + (size_t)(l - 1) * JET * n * MLP_WIDTH; };       // a_l jets, l = 1 .. D
   auto Z = [&](int l) { return zj + (size_t)(l - 1) * (JET - 1) * n * MLP_WIDTH; };  // z_l jets
   auto part = [&](int l) { return partial + (size_t)l * nblk * MLP_PART; };
   const unsigned tiles = (unsigned)((n + 127) / 128);
   // forward
-  hipLaunchKernelGGL(k_jet_first, dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, A(1), Z(1));
+  hipLaunchKernelGGL(k_jet_first, dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, A(1), Z(1), xh);
   for (int l = 1; l < D; ++l)
     hipLaunchKernelGGL(k_jet_dense, dim3(tiles, 3), dim3(256), 0, stream, n, A(l), M.params + M.off_w[l],
                        M.params + M.off_b[l], A(l + 1), Z(l + 1));
@@ -683,12 +733,12 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
     cur ^= 1;
   }
   // first layer: the input jet (xhat, e_d, 0): rows 0 .. 4n of dz_1
-  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3((unsigned)nblk), dim3(64), 0, stream, M, nullptr, dz[cur], MLP_WIDTH,
+  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3((unsigned)nblk), dim3(64), 0, stream, M, xh, dz[cur], MLP_WIDTH,
                      MLP_WIDTH, part(0), rpb, 4 * n, n);
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? 3 : MLP_WIDTH, fo = l == D ? MLP_OUT : MLP_WIDTH;
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks_for(fi * fo + fo)), dim3(256), 0, stream, part(l), (int)nblk, fi, fo,
-                       dparams + M.off_w[l], dparams + M.off_b[l]);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((fi * fo + fo + 15) / 16), dim3(256), 0, stream, part(l), (int)nblk, fi,
+                       fo, dparams + M.off_w[l], dparams + M.off_b[l]);
   }
   return hipGetLastError();
 }

@@ -23,12 +23,14 @@ struct MlpDev {
 
 // Workspace carve-up for one point set (all float arrays, 256-byte aligned):
 // activations a_1 .. a_depth [n][64], two delta buffers [n][64], transposed hidden
-// weights (depth - 1) x [64][64], and per-block partial parameter gradients.
+// weights (depth - 1) x [64][64], per-block partial parameter gradients and the
+// normalised inputs [n][4].
 struct MlpWork {
   float* act;       // depth x [n][64]
   float* delta[2];  // [n][64]
   float* wt;        // (depth - 1) x [64][64]
   float* partial;   // (depth + 1) x nblk x MLP_PART floats
+  float* xh;        // [n][4] normalised inputs (fourth column 0)
   int nblk;         // blocks of the parameter-gradient reduction
   long long rows_per_block;
 };

@@ -15,6 +15,7 @@ import pytest
 import torch
 
 import oracle
+from bos_inputs import mlp_params
 from oracle import mlp as omlp
 from _common import grad_errors, stored_delta
 from bos_inputs import binary_dots, scene_unit_box
@@ -28,7 +29,7 @@ T0, T_IN = 293.0, 303.0
 
 
 def _mlp(depth, seed=1, scale=1.0):
-    th = omlp.init_params(64, depth, seed, out_scale=scale)
+    th = mlp_params(64, depth, seed, out_scale=scale)
     th[np.arange(th.size) % 5 == 2] += 0.02  # non-zero biases
     m = api.MLP(torch.from_numpy(th.astype(np.float32)).to(DEV), 64, depth, LO, HI)
     return m, th.astype(np.float32).astype(np.float64)

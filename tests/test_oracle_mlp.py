@@ -23,6 +23,7 @@ import pytest
 import torch
 
 import oracle
+from bos_inputs import mlp_params
 from oracle import mlp
 
 W, D = 16, 3
@@ -31,7 +32,7 @@ CONSTS = dict(Re=50.0, Pe=35.0, Ri=0.8, L=1.0, g1=1.0, g2=0.5, g3=2.0)
 
 
 def _theta(seed=1, scale=1.0):
-    return mlp.init_params(W, D, seed, out_scale=scale)
+    return mlp_params(W, D, seed, out_scale=scale)
 
 
 def _points(n, seed=2):
