@@ -82,6 +82,14 @@ template <int EPI>
 __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __restrict__ A, const float* __restrict__ B,
                                                    const float* __restrict__ bias, const float* __restrict__ act,
                                                    float* __restrict__ C) {
+  // the block's four wavefronts share the weights, staged in LDS (rows padded to 65)
+  __shared__ float Bs[MLP_WIDTH * 65];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    Bs[(e >> 6) * 65 + (e & 63)] = B[e];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long row0 = ((long long)blockIdx.x * 4 + wave) * 32;
   if (row0 >= n) return;  // whole wavefronts only: every lane takes part in the products
@@ -99,10 +107,22 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
 #pragma unroll
     for (int s = 0; s < 32; ++s) a[s] = 0.0f;
   }
+  // DTANH: the activations at the tile's output positions, loaded before the products so
+  // that their latency overlaps them
+  float yv[2][16];
+  if constexpr (EPI == EPI_DTANH) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long rr = row0 + acc_row(r, h);
+        yv[t][r] = rr < n ? act[rr * MLP_WIDTH + 32 * t + c] : 0.0f;
+      }
+  }
   f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
   for (int s = 0; s < 32; ++s) {
-    const float* pb = B + (32 * h + s) * MLP_WIDTH;
+    const float* pb = Bs + (32 * h + s) * 65;
     acc0 = mfma32(a[s], pb[c], acc0);
     acc1 = mfma32(a[s], pb[32 + c], acc1);
   }
@@ -117,7 +137,7 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
       if (rr < n) {
         float v;
         if constexpr (EPI == EPI_DTANH) {
-          const float y = act[rr * MLP_WIDTH + col];
+          const float y = yv[t][r];
           v = acc[r] * (1.0f - y * y);
         } else if constexpr (EPI == EPI_TANH) {
           v = tanh_fast(acc[r] + bc);
@@ -194,62 +214,66 @@ __global__ __launch_bounds__(256) void k_mlp_transpose(MlpDev M, float* __restri
 // P[m][j] = sum_i A[i][m] B[i][j] (m < 64, j < 64) and P[4096 + j] = sum_{i < bias_rows} B[i][j].
 // A: the layer's input (XHAT: the first layer's, rows i < M.n the normalised position of
 // point i from xh [n][4], rows i = (1 + a) M.n + p the unit vector e_a (the input's
-// derivative along a in a jet); else a [nrows][64]); B: the gradient at its output, ldb columns of which nb
-// are used. One wavefront per block, the rows along K in 64-row chunks.
+// derivative along a in a jet); else a [nrows][64]); B: the gradient at its output, ldb
+// columns of which nb are used. Four wavefronts per block: each 64-row chunk of A and B
+// is staged in LDS with coalesced loads, and wavefront (mt, nt) accumulates the 32 x 32
+// tile P[32 mt ..][32 nt ..] with the rows along K.
 template <bool XHAT>
-__global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev M, const float* __restrict__ A, const float* __restrict__ B,
-                                                  int ldb, int nb, float* __restrict__ partial,
-                                                  long long rows_per_block, long long nrows, long long bias_rows) {
-  constexpr int MT = XHAT ? 1 : 2;
-  const int lane = threadIdx.x, c = lane & 31, h = lane >> 5;
+__global__ __launch_bounds__(256) void k_mlp_wgrad(MlpDev M, const float* __restrict__ A, const float* __restrict__ B,
+                                                   int ldb, int nb, float* __restrict__ partial,
+                                                   long long rows_per_block, long long nrows, long long bias_rows) {
+  __shared__ float As[64 * 65];
+  __shared__ float Bs[64 * 65];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int mt = wave >> 1, nt = wave & 1;
+  const int c = lane & 31, h = lane >> 5;
   const long long r0 = (long long)blockIdx.x * rows_per_block;
   const long long r1 = r0 + rows_per_block < nrows ? r0 + rows_per_block : nrows;
-  f32x16 acc[MT][2];
+  f32x16 acc = {};
+  float bsum = 0.0f;
+  // chunk elements e = t + 256 i (row e / 64, column e % 64), loaded one chunk ahead
+  float av[16], bv[16];
+  auto load_chunk = [&](long long base) {
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = f32x16{};
-  float bsum[2] = {0.0f, 0.0f};
-  for (long long base = r0; base < r1; base += 64) {
-#pragma unroll 4
-    for (int s = 0; s < 32; ++s) {
-      const long long row = base + 32 * h + s;
-      const bool ok = row < r1;
-      float a[MT], b[2];
-      if constexpr (XHAT) {
-        // A = xh [n][4] for the value rows, e_a for the rows of the input's derivative along a
-        float x = 0.0f;
-        if (ok && c < 3) x = row < M.n ? A[row * 4 + c] : (c == (int)(row / M.n) - 1 ? 1.0f : 0.0f);
-        a[0] = x;
-      } else {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) a[mt] = ok ? A[row * MLP_WIDTH + 32 * mt + c] : 0.0f;
-      }
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        const int col = 32 * nt + c;
-        b[nt] = (ok && col < nb) ? B[row * ldb + col] : 0.0f;
-        if (row < bias_rows) bsum[nt] += b[nt];
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        acc[mt][0] = mfma32(a[mt], b[0], acc[mt][0]);
-        if (nb > 32) acc[mt][1] = mfma32(a[mt], b[1], acc[mt][1]);
+    for (int i = 0; i < 16; ++i) {
+      const int e = t + 256 * i, col = e & 63;
+      const long long row = base + (e >> 6);
+      av[i] = 0.0f;
+      bv[i] = 0.0f;
+      if (row < r1) {
+        if constexpr (XHAT) {
+          if (col < 3) av[i] = row < M.n ? A[row * 4 + col] : (col == (int)(row / M.n) - 1 ? 1.0f : 0.0f);
+        } else {
+          av[i] = A[row * MLP_WIDTH + col];
+        }
+        if (col < nb) bv[i] = B[row * ldb + col];
       }
     }
+  };
+  if (r0 < r1) load_chunk(r0);
+  for (long long base = r0; base < r1; base += 64) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = t + 256 * i;
+      As[(e >> 6) * 65 + (e & 63)] = av[i];
+      Bs[(e >> 6) * 65 + (e & 63)] = bv[i];
+    }
+    __syncthreads();
+    if (base + 64 < r1) load_chunk(base + 64);  // in flight during this chunk's products
+#pragma unroll 8
+    for (int s = 0; s < 32; ++s) {
+      const int rr = 32 * h + s;
+      const float bvv = Bs[rr * 65 + 32 * nt + c];
+      acc = mfma32(As[rr * 65 + 32 * mt + c], bvv, acc);
+      if (mt == 0 && base + rr < bias_rows) bsum += bvv;
+    }
+    __syncthreads();
   }
   float* P = partial + (long long)blockIdx.x * MLP_PART;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      if (nt == 1 && nb <= 32) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) P[(32 * mt + acc_row(r, h)) * MLP_WIDTH + 32 * nt + c] = acc[mt][nt][r];
-    }
-#pragma unroll
-  for (int nt = 0; nt < 2; ++nt) {
-    const float other = __shfl_xor(bsum[nt], 32);
-    if (h == 0) P[MLP_WIDTH * MLP_WIDTH + 32 * nt + c] = bsum[nt] + other;
-  }
+  for (int r = 0; r < 16; ++r) P[(32 * mt + acc_row(r, h)) * MLP_WIDTH + 32 * nt + c] = acc[r];
+  const float other = __shfl_xor(bsum, 32);
+  if (mt == 0 && h == 0) P[MLP_WIDTH * MLP_WIDTH + 32 * nt + c] = bsum + other;
 }
 
 // dparams[layer] += sum over blocks of the partials: W [fi][fo], b [fo]. A block takes 16
@@ -565,11 +589,11 @@ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline int blocks_for(long long threads) { return (int)((threads + 255) / 256); }
 
-// blocks (one wavefront each) of the parameter-gradient reduction over `rows` rows: one
-// per 64 rows up to two per SIMD of the 256 compute units
+// blocks (four wavefronts each) of the parameter-gradient reduction over `rows` rows: one
+// per 64 rows, up to two per compute unit
 inline long long wgrad_blocks(long long rows) {
   const long long b = (rows + 63) / 64;
-  return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+  return b < 1 ? 1 : (b > 512 ? 512 : b);
 }
 
 }  // namespace
@@ -633,20 +657,20 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
     hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)(D - 1) * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0,
                        stream, M, w.wt);
   // output layer: dW_D = a_D^T dL, db_D = sum dL; delta_D = (dL W_D^T)(1 - a_D^2)
-  hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(64), 0, stream, M, act(D), dL_dout, MLP_OUT, MLP_OUT,
+  hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(256), 0, stream, M, act(D), dL_dout, MLP_OUT, MLP_OUT,
                      part(D), w.rows_per_block, n, n);
   hipLaunchKernelGGL(k_mlp_delta_out, dim3(blocks_for(n * 16)), dim3(256), 0, stream, M, dL_dout, act(D),
                      w.delta[0]);
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
     // dW_l = a_l^T delta_{l+1}; delta_l = (delta_{l+1} W_l^T)(1 - a_l^2)
-    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(64), 0, stream, M, act(l), w.delta[cur], MLP_WIDTH,
+    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(256), 0, stream, M, act(l), w.delta[cur], MLP_WIDTH,
                        MLP_WIDTH, part(l), w.rows_per_block, n, n);
     hipLaunchKernelGGL((k_mlp_dense<EPI_DTANH>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, w.delta[cur],
                        w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, act(l), w.delta[cur ^ 1]);
     cur ^= 1;
   }
-  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(64), 0, stream, M, w.xh, w.delta[cur], MLP_WIDTH,
+  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(256), 0, stream, M, w.xh, w.delta[cur], MLP_WIDTH,
                      MLP_WIDTH, part(0), w.rows_per_block, n, n);
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? 3 : MLP_WIDTH, fo = l == D ? MLP_OUT : MLP_WIDTH;
@@ -717,14 +741,14 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
   if (D > 1)
     hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)(D - 1) * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0,
                        stream, M, wt);
-  hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(64), 0, stream, M, A(D), dj, MLP_OUT, MLP_OUT,
+  hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(256), 0, stream, M, A(D), dj, MLP_OUT, MLP_OUT,
                      part(D), rpb, rows, n);
   hipLaunchKernelGGL((k_jet_act_back<true>), dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, dj, A(D),
                      Z(D), dz[0]);
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
     // dW_l = sum_c a_l^c^T dz_{l+1}^c (bias: value channel); G = dz_{l+1} W_l^T; dz_l
-    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(64), 0, stream, M, A(l), dz[cur], MLP_WIDTH,
+    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(256), 0, stream, M, A(l), dz[cur], MLP_WIDTH,
                        MLP_WIDTH, part(l), rpb, rows, n);
     hipLaunchKernelGGL((k_mlp_dense<EPI_NONE>), dim3((unsigned)((rows + 127) / 128)), dim3(256), 0, stream, rows,
                        dz[cur], wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, nullptr, G);
@@ -733,7 +757,7 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
     cur ^= 1;
   }
   // first layer: the input jet (xhat, e_d, 0): rows 0 .. 4n of dz_1
-  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3((unsigned)nblk), dim3(64), 0, stream, M, xh, dz[cur], MLP_WIDTH,
+  hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3((unsigned)nblk), dim3(256), 0, stream, M, xh, dz[cur], MLP_WIDTH,
                      MLP_WIDTH, part(0), rpb, 4 * n, n);
   for (int l = 0; l <= D; ++l) {
     const int fi = l == 0 ? 3 : MLP_WIDTH, fo = l == D ? MLP_OUT : MLP_WIDTH;
