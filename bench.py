@@ -348,10 +348,14 @@ def main():
         W.step()
         torch.cuda.synchronize()
         g_eager = [g.clone() for g in W.grads]
-        graph.replay()
-        torch.cuda.synchronize()
-        for g, ge in zip(W.grads, g_eager):  # the replay reproduces the eager step
-            assert torch.allclose(g, ge, rtol=1e-9, atol=1e-12 * float(ge.abs().max()) + 1e-300)
+        p_eager = W.dparams.clone() if W.mlp is not None else None
+        for _ in range(2):  # every replay reproduces the eager step
+            graph.replay()
+            torch.cuda.synchronize()
+            for g, ge in zip(W.grads, g_eager):
+                assert torch.allclose(g, ge, rtol=1e-9, atol=1e-12 * float(ge.abs().max()) + 1e-300)
+            if p_eager is not None:
+                assert torch.allclose(W.dparams, p_eager, rtol=1e-5, atol=1e-6 * float(p_eager.abs().max()))
 
     # timed region: whole steps
     torch.cuda.synchronize()

@@ -121,3 +121,43 @@ def test_autotune_picks_valid_config(tmp_path):
     for i in range(len(scenes)):
         assert torch.equal(tr.uv[i], ref.uv[i])
         assert torch.linalg.norm(g[i] - g_ref[i]) <= 1e-5 * torch.linalg.norm(g_ref[i])
+
+
+def test_batch_mixing_samples_weights_and_pixel_lists():
+    """One launch over scenes with different samples per pixel, radiometric weights and a
+    pixel list (tile offsets of every scene span its sample planes): each scene equals its
+    own launch, and one is checked against the oracle."""
+    b = _batch(4)
+    rng = np.random.default_rng(9)
+    scenes = []
+    for i, (s, T) in enumerate(b):
+        d = s.desc.replace(spp=(1, 3, 2, 4)[i], seed=50 + i, radiometry=i % 2)
+        ids = None
+        if i == 2:
+            ids = torch.from_numpy(np.sort(rng.choice(d.width * d.height, 77, replace=False)).astype(np.int32)).to(DEV)
+        scenes.append((api.Scene(d, s.field, s.pattern, ids), T))
+    sc = [s for s, _ in scenes]
+    lams = [torch.from_numpy(rng.standard_normal((s.n_rays, 2)).astype(np.float32)).to(DEV) for s in sc]
+    lam_d = [torch.from_numpy(rng.standard_normal((s.n_rays, 3)).astype(np.float32)).to(DEV) for s in sc]
+    launch = api.make_launch((8, 8), 4, persistent=True, blocks_per_cu=2)
+    trb = api.Tracer(sc, launch, want_dir=True)
+    trb.forward().render()
+    gb = trb.adjoint(dL_duv=lams, dL_ddir=lam_d)
+    torch.cuda.synchronize()
+    for i, s in enumerate(sc):
+        tr1 = api.Tracer([s], None, want_dir=True)
+        tr1.forward().render()
+        g1 = tr1.adjoint(dL_duv=[lams[i]], dL_ddir=[lam_d[i]])
+        torch.cuda.synchronize()
+        assert torch.equal(trb.uv[i], tr1.uv[0]) and torch.equal(trb.wall_dir[i], tr1.wall_dir[0])
+        assert torch.equal(trb.image[i], tr1.image[0])
+        d = (gb[i] - g1[0]).abs().max().item()
+        assert d <= 1e-12 * g1[0].abs().max().item(), d
+    s, T = scenes[3]  # 4 samples per pixel, no weight
+    F = oracle.grid_field(stored_delta(T), s.desc.box_lo, s.desc.box_hi)
+    ref = oracle.trace(F, s.desc)
+    ok = np.isfinite(ref["uv"][:, 0])
+    assert exit_error(_np(trb.uv[3])[ok], ref["uv"][ok]).max() <= 1e-6
+    g_ref = oracle.adjoint(F, s.desc, _np(lams[3]).astype(np.float64), dL_ddir=_np(lam_d[3]).astype(np.float64))
+    g = _np(gb[3])
+    assert np.linalg.norm(g - g_ref) <= 1e-3 * np.linalg.norm(g_ref)
