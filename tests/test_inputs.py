@@ -56,3 +56,25 @@ def test_batch_recipe():
         assert 4 <= len(spec.plumes) <= 8
     # deterministic per seed
     assert bi.scenes_batch(2)[1][1] == bi.scenes_batch(2)[1][1]
+
+
+def test_network_inputs_seeded_and_shaped():
+    import bos_inputs as bi
+
+    lo, hi = (0.0, 0.0, 0.0), (4.0, 4.0, 3.0)
+    th = bi.mlp_params(64, 4, 7, out_scale=0.3, bias_std=0.05)
+    assert th.size == 3 * 64 + 64 + 3 * (64 * 64 + 64) + 64 * 5 + 5
+    assert np.array_equal(th, bi.mlp_params(64, 4, 7, out_scale=0.3, bias_std=0.05))
+    assert not np.array_equal(th, bi.mlp_params(64, 4, 8, out_scale=0.3, bias_std=0.05))
+    # Glorot bound per layer, the last one scaled
+    o = 0
+    shapes = bi.mlp_param_shapes(64, 4)
+    for i, (fi, fo) in enumerate(shapes):
+        lim = np.sqrt(6.0 / (fi + fo)) * (0.3 if i == len(shapes) - 1 else 1.0)
+        W = th[o:o + fi * fo]
+        assert np.abs(W).max() <= lim and np.abs(W).max() > 0.5 * lim
+        o += fi * fo + fo
+    pb = bi.inlet_points(1000, lo, hi, 5)
+    assert np.all(pb[:, 0] == lo[0]) and np.all((pb[:, 1:] >= lo[1:]) & (pb[:, 1:] <= hi[1:]))
+    pc = bi.collocation_points(1000, lo, hi, 6)
+    assert np.all((pc >= lo) & (pc <= hi)) and np.array_equal(pc, bi.collocation_points(1000, lo, hi, 6))
