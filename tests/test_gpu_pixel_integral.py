@@ -140,10 +140,12 @@ def test_sampled_radiometric_gradient_locked_differences():
     tr = _tracer(w)
     tr.forward().render([torch.from_numpy(target.astype(np.float32)).to(DEV)])
     g = _np(tr.adjoint()[0])
-    F = oracle.grid_field(stored_delta(w.T32), w.scene.box_lo, w.scene.box_hi)
+    F, ref = _oracle(w)
+    _, dL, dLd, dLp = oracle.loss_pixels(ref["image"], target, 4, ref["dI"], ref["dId"], ref["dIp"])
+    g_or = oracle.adjoint(F, w.scene, dL, dL_ddir=dLd, dL_dpath=dLp)
     gmax = np.abs(g).max()
     rng = np.random.default_rng(29)
-    vox = rng.choice(np.flatnonzero(np.abs(g) > 1e-2 * gmax), 16, replace=False)
+    vox = rng.choice(np.flatnonzero(np.abs(g_or) > 1e-2 * np.abs(g_or).max()), 16, replace=False)  # oracle's choice
     pat = w.pattern32.astype(np.float64)
     fd1 = oracle.fd_voxels(F, w.scene, pat, target, vox, h=1e-7)
     fd2 = oracle.fd_voxels(F, w.scene, pat, target, vox, h=2e-7)

@@ -97,9 +97,11 @@ def test_ql_adjoint_locked_differences_including_entry_layer():
     tr = _tracer(w)
     tr.forward().render([torch.from_numpy(target).to(DEV)])
     g = _np(tr.adjoint()[0])
-    F = oracle.grid_field(stored_delta(w.T32), w.scene.box_lo, w.scene.box_hi)
+    F, ref = oracle_forward(w, stored_delta(w.T32))
+    _, dL = oracle.loss(ref["image"], target.astype(np.float64), ref["dI"])
+    g_or = oracle.adjoint(F, w.scene, dL)
     gmax = np.abs(g).max()
-    cand = np.flatnonzero(np.abs(g) > 1e-2 * gmax)
+    cand = np.flatnonzero(np.abs(g_or) > 1e-2 * np.abs(g_or).max())  # voxels chosen by the oracle
     nx, ny, _ = w.scene.dims
     entry = cand[(cand // nx) % ny == 0]
     rng = np.random.default_rng(23)
