@@ -49,6 +49,16 @@ def room_workload(dims=(128, 128, 128), width=512, height=512, seed=2, max_steps
     return Workload(sc, T.astype(np.float32), bi.blurred_noise(12, (pat, pat)))
 
 
+def expected_scale(T32: np.ndarray, dtype: str, offset: float = 0.0) -> float:
+    """The power-of-two code scale for a temperature field, derived here from the seeded
+    input: the largest s with s * max |eta - 1 - c| <= 2^14 (1 for FP32)."""
+    if dtype == "f32":
+        return 1.0
+    t = T32.astype(np.float64)
+    bound = max(abs(RHO0G * T0 / t.min() - offset), abs(RHO0G * T0 / t.max() - offset))
+    return float(2.0 ** np.floor(np.log2(2.0 ** 14 / bound)))
+
+
 def stored_delta(T32: np.ndarray, dtype: str = "f32", scale: float = 1.0, offset: float = 0.0) -> np.ndarray:
     """eta - 1 exactly as stored (the oracle's own binary32 arithmetic and codes), FP64."""
     d32 = oracle.delta_from_temperature_f32(T32, RHO0G, T0)

@@ -10,8 +10,8 @@ import pytest
 import torch
 
 import oracle
-from _common import (CODES, RHO0G, T0, unit_box_workload, exit_error, oracle_forward, room_workload,
-                     stored_delta)
+from _common import (CODES, RHO0G, T0, unit_box_workload, exit_error, expected_scale, oracle_forward,
+                     room_workload, stored_delta)
 from paper_2509_14442_amd import api
 
 pytestmark = pytest.mark.gpu
@@ -64,12 +64,14 @@ def test_field_codes_bit_exact(dtype, offset):
     torch.cuda.synchronize()
     nx, ny, nz = field.dims
     got = _np(field.buf).view(np.uint32 if dtype == "f32" else np.uint16).reshape(nz + 1, ny + 1, nx + 1, 8)
+    scale = expected_scale(w.T32, dtype, offset)
+    assert field.scale == scale
     d32 = oracle.delta_from_temperature_f32(w.T32, RHO0G, T0)
-    ref = oracle.encode(d32, CODES[dtype], field.scale, offset)
+    ref = oracle.encode(d32, CODES[dtype], scale, offset)
     ref = ref.view(np.uint32) if dtype == "f32" else ref
     assert np.array_equal(got, _expected_records(ref))
     if dtype != "f32":
-        q = oracle.decode(ref, CODES[dtype], field.scale, 0.0) * field.scale
+        q = oracle.decode(ref, CODES[dtype], scale, 0.0) * scale
         assert np.abs(q).max() <= 2 ** 14  # scale keeps the codes in range
 
 

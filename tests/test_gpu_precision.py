@@ -20,7 +20,7 @@ import pytest
 import torch
 
 import oracle
-from _common import RHO0G, exit_error, oracle_forward, room_workload, stored_delta
+from _common import RHO0G, exit_error, expected_scale, oracle_forward, room_workload, stored_delta
 from paper_2509_14442_amd import api
 from test_gpu_forward import DEV, _np, gpu_trace
 
@@ -39,7 +39,8 @@ def _exact_delta(T32):
 def test_16bit_forward_against_dequantised_and_exact(dtype, offset):
     w = room_workload((128, 128, 128), 256, 256, seed=2)
     tr = gpu_trace(w, dtype, None, offset)
-    scale = tr.scenes[0].field.scale
+    scale = expected_scale(w.T32, dtype, offset)
+    assert tr.scenes[0].field.scale == scale
     uv, ns = _np(tr.uv[0]), _np(tr.n_steps[0])
     fin = np.isfinite(uv[:, 0])
 
@@ -70,7 +71,9 @@ def test_16bit_adjoint_against_dequantised(dtype, offset):
     tr = api.Tracer([sc])
     tr.forward()
     g = _np(tr.adjoint(dL_duv=[torch.from_numpy(lam).to(DEV)])[0])
-    F = oracle.grid_field(stored_delta(w.T32, dtype, field.scale, offset), w.scene.box_lo, w.scene.box_hi)
+    scale = expected_scale(w.T32, dtype, offset)
+    assert field.scale == scale
+    F = oracle.grid_field(stored_delta(w.T32, dtype, scale, offset), w.scene.box_lo, w.scene.box_hi)
     g_ref = oracle.adjoint(F, w.scene, lam.astype(np.float64), ids)
     l2 = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     assert l2 < 1e-3, l2

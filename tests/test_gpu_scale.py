@@ -21,7 +21,8 @@ import torch
 import bench
 import bos_inputs as bi
 import oracle
-from _common import (RHO0G, Workload, exit_error, grad_errors, oracle_forward, room_workload, stored_delta)
+from _common import (RHO0G, Workload, exit_error, expected_scale, grad_errors, oracle_forward, room_workload,
+                     stored_delta)
 from paper_2509_14442_amd import api
 from test_gpu_forward import DEV, _np
 
@@ -140,7 +141,9 @@ def test_room256_fp16_subsample():
     uv, ns = _np(tr.uv[0]), _np(tr.n_steps[0])
     ids = bi.pixel_subset(desc.width * desc.height, 4096, 15)
     w.pixel_ids = ids
-    F, ref = oracle_forward(w, stored_delta(T, "f16", field.scale, RHO0G))
+    scale = expected_scale(T, "f16", RHO0G)
+    assert field.scale == scale
+    F, ref = oracle_forward(w, stored_delta(T, "f16", scale, RHO0G))
     ok = np.isfinite(ref["uv"][:, 0])
     assert np.array_equal(ok, np.isfinite(uv[ids, 0]))
     assert (ns[ids] != ref["n_steps"]).sum() <= 1
