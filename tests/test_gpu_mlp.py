@@ -1,5 +1,6 @@
 """GPU parity of the network field (Sec. 2.D) against the oracle: the MLP forward at
-arbitrary points and at the voxel centres (FP32 on the matrix cores vs FP64), its
+arbitrary points and at the voxel centres (FP32 on the matrix cores vs FP64; depths 1 to
+the largest, 8), its
 parameter gradient for given per-point output seeds, and the BOS loss's parameter
 gradient end to end (MLP -> T on the voxel grid -> eta -> trace -> render -> adjoint ->
 chain to T_nd -> MLP backward).
@@ -35,7 +36,7 @@ def _mlp(depth, seed=1, scale=1.0):
     return m, th.astype(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("depth,n", [(1, 1), (3, 1000), (4, 4099), (6, 333)])
+@pytest.mark.parametrize("depth,n", [(1, 1), (3, 1000), (4, 4099), (6, 333), (8, 257)])
 def test_forward_at_points(depth, n):
     m, th = _mlp(depth)
     x = np.random.default_rng(depth).uniform(LO, HI, (n, 3)).astype(np.float32)
@@ -56,7 +57,7 @@ def test_forward_on_the_voxel_grid():
     assert np.abs(_np(T) - omlp.temperature(ref[:, 0], T0, T_IN)).max() <= 3e-4
 
 
-@pytest.mark.parametrize("depth,n", [(1, 70), (4, 5000), (5, 131072)])
+@pytest.mark.parametrize("depth,n", [(1, 70), (4, 5000), (5, 131072), (8, 3001)])
 def test_parameter_gradient_for_given_seeds(depth, n):
     m, th = _mlp(depth, 3)
     rng = np.random.default_rng(10 + depth)
@@ -157,7 +158,7 @@ def test_boundary_loss_and_gradient():
 PDE = dict(Re=50.0, Pe=35.0, Ri=0.8, L=0.5, g1=1.0, g2=0.5, g3=2.0)
 
 
-@pytest.mark.parametrize("depth,n", [(1, 37), (3, 2000), (4, 8192)])
+@pytest.mark.parametrize("depth,n", [(1, 37), (3, 2000), (4, 8192), (8, 500)])
 def test_pde_loss_residuals_and_gradient(depth, n):
     """The paper's mini-batch holds 8192 collocation points per step."""
     m, th = _mlp(depth, 30 + depth, scale=0.5)
