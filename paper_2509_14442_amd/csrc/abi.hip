@@ -2,6 +2,7 @@
 // launches of the field, forward, render and adjoint kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -173,7 +174,7 @@ long long ckpt_entries(const rbos_scene* S) {
 }
 
 struct Layout {
-  size_t table, queues, partials, total;
+  size_t table, queues, partials, tile_cost, tile_order, total;
   long long total_tiles;
   int total_render_blocks;
 };
@@ -192,7 +193,9 @@ Layout layout(const rbos_scene* scenes, int n, const Launch& L) {
   }
   y.total_tiles = tiles;
   y.total_render_blocks = (int)rblocks;
-  y.total = align256(y.partials + sizeof(float) * (size_t)(rblocks > 0 ? rblocks : 1));
+  y.tile_cost = align256(y.partials + sizeof(float) * (size_t)(rblocks > 0 ? rblocks : 1));
+  y.tile_order = align256(y.tile_cost + sizeof(int) * (size_t)(tiles > 0 ? tiles : 1));
+  y.total = align256(y.tile_order + sizeof(int) * (size_t)(tiles > 0 ? tiles : 1));
   return y;
 }
 
@@ -360,6 +363,12 @@ int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::Launch
   plan.queues = reinterpret_cast<unsigned int*>(ws + P.Y.queues);
   plan.total_render_blocks = P.Y.total_render_blocks;
   plan.partials = reinterpret_cast<float*>(ws + P.Y.partials);
+  plan.tile_cost = reinterpret_cast<int*>(ws + P.Y.tile_cost);
+  plan.tile_order = reinterpret_cast<int*>(ws + P.Y.tile_order);
+  int longest = 1;
+  for (const SceneDev& d : P.table) longest = std::max(longest, d.max_steps);
+  plan.order_shift = 0;
+  while ((longest >> plan.order_shift) >= 1024) ++plan.order_shift;
   plan.ckpt_k = P.table.empty() ? 0 : P.table[0].ckpt_k;
   plan.tracer = P.table.empty() ? 0 : P.table[0].tracer;
   if (P.L.persistent) {
@@ -533,7 +542,12 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
   hipStream_t stream_h = static_cast<hipStream_t>(stream);
   rc = finish_launch(P, workspace, stream_h, plan);
   if (rc) return rc;
-  hipError_t e = rbos::launch_trace_adj(plan, stream_h);
+  hipError_t e = hipSuccess;
+  if (plan.persistent) {
+    e = rbos::launch_tile_order(plan, stream_h);
+    if (e != hipSuccess) return fail(RBOS_E_HIP, "tile order launch failed: %s", hipGetErrorString(e));
+  }
+  e = rbos::launch_trace_adj(plan, stream_h);
   if (e != hipSuccess) return fail(RBOS_E_HIP, "adjoint launch failed: %s", hipGetErrorString(e));
   return RBOS_OK;
 }

@@ -22,6 +22,9 @@ struct LaunchPlan {
   int tracer;               // shared by all scenes: 0 nonlinear, 1 quasi-linear
   int total_render_blocks;  // render: sum of per-scene blocks
   float* partials;          // render: per-block partial loss sums
+  int* tile_cost;           // adjoint, persistent: longest ray of each tile (steps)
+  int* tile_order;          // adjoint, persistent: processing order of the tiles
+  int order_shift;          // cost >> order_shift is the sort key (< 1024)
 };
 
 // Grid of a persistent kernel: blocks_per_cu blocks on every compute unit, or as many as
@@ -42,6 +45,8 @@ inline int persistent_grid(Kernel kernel, const LaunchPlan& P, size_t lds_bytes)
 hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream);
 hipError_t launch_render(const LaunchPlan& P, hipStream_t stream);
 hipError_t launch_trace_adj(const LaunchPlan& P, hipStream_t stream);
+// persistent adjoint: fill P.tile_order from the forward's step counts
+hipError_t launch_tile_order(const LaunchPlan& P, hipStream_t stream);
 hipError_t launch_field_pack(int nx, int ny, int nz, const float* src, int from_temperature, float rho0G, float T0,
                              int dtype, float scale, float offset, void* field, hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int value, int n, hipStream_t stream);

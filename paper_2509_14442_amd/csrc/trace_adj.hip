@@ -583,7 +583,8 @@ __global__ __launch_bounds__(256) void k_trace_adj_ql(const SceneDev* __restrict
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_trace_adj_ql_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
-                                                                 int total_tiles, unsigned int* __restrict__ queues) {
+                                                                 int total_tiles, unsigned int* __restrict__ queues,
+                                                                 const int* __restrict__ order) {
   const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   const int xcd = blockIdx.x & 7;
   extern __shared__ float lds[];
@@ -597,6 +598,7 @@ __global__ __launch_bounds__(256) void k_trace_adj_ql_persistent(const SceneDev*
       if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
       t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
       if (t >= q_end) break;
+      t = wave_uniform(gld(order + t));
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];
       adjoint_tile_ql<DT>(S, t - S.tile_begin, lane, cache);
@@ -610,7 +612,7 @@ static hipError_t launch_adj_ql(const LaunchPlan& P, hipStream_t stream) {
   if (P.persistent) {
     const int grid = persistent_grid(k_trace_adj_ql_persistent<DT>, P, lds);
     hipLaunchKernelGGL((k_trace_adj_ql_persistent<DT>), dim3(grid), dim3(64 * P.wpb), lds, stream, P.scenes,
-                       P.n_scenes, P.total_tiles, P.queues);
+                       P.n_scenes, P.total_tiles, P.queues, P.tile_order);
   } else {
     int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
     hipLaunchKernelGGL((k_trace_adj_ql<DT>), dim3(nblocks), dim3(64 * P.wpb), lds, stream, P.scenes, P.n_scenes,
@@ -633,7 +635,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 template <int DT, int KS, bool STORED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj_persistent(
-    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, unsigned int* __restrict__ queues) {
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, unsigned int* __restrict__ queues,
+    const int* __restrict__ order) {
   const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   const int xcd = blockIdx.x & 7;
   extern __shared__ float lds[];
@@ -647,6 +650,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
       t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
       if (t >= q_end) break;
+      t = wave_uniform(gld(order + t));
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];
       adjoint_tile<DT, KS, STORED>(S, t - S.tile_begin, lane, replay);
@@ -660,7 +664,7 @@ static hipError_t launch_adj_t(const LaunchPlan& P, hipStream_t stream) {
   if (P.persistent) {
     const int grid = persistent_grid(k_trace_adj_persistent<DT, KS, STORED>, P, lds);
     hipLaunchKernelGGL((k_trace_adj_persistent<DT, KS, STORED>), dim3(grid), dim3(64 * P.wpb), lds, stream,
-                       P.scenes, P.n_scenes, P.total_tiles, P.queues);
+                       P.scenes, P.n_scenes, P.total_tiles, P.queues, P.tile_order);
   } else {
     int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
     hipLaunchKernelGGL((k_trace_adj<DT, KS, STORED>), dim3(nblocks), dim3(64 * P.wpb), lds, stream, P.scenes,
@@ -675,6 +679,70 @@ static hipError_t launch_adj_dt(const LaunchPlan& P, hipStream_t stream) {
   // chunks of 8 step-start states in LDS: stride 1 fills them from the checkpoints,
   // strides 8, 16, ... replay them
   return P.ckpt_k == 1 ? launch_adj_t<DT, 8, true>(P, stream) : launch_adj_t<DT, 8, false>(P, stream);
+}
+
+// Processing order of the persistent adjoint. A tile's reverse sweep lasts as long as
+// its longest ray, and the tiles of the per-XCD ranges differ by up to ~1.5x (rays that
+// leave the box through a side face are short). Taken in index order, the long tiles
+// that start last leave most wavefront slots idle at the end of the launch. Each range
+// is therefore taken longest first: its tiles are counting-sorted by the forward's
+// largest step count (ties in any order), so the short tiles fill the end.
+__global__ __launch_bounds__(256) void k_tile_cost(const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles,
+                                                   int* __restrict__ cost) {
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int gtile = blockIdx.x * 4 + wave;
+  if (gtile >= total_tiles) return;  // whole wavefront
+  const SceneDev& S = scenes[find_scene(scenes, n_scenes, gtile)];
+  int r = 0, pix = 0, smp = 0, n = 0;
+  if (tile_ray(S, gtile - S.tile_begin, lane, r, pix, smp)) n = max(gld(S.n_steps + r), 0);
+  n = wave_max_nonneg(n);  // all 64 lanes active
+  if (lane == 0) cost[gtile] = n;
+}
+
+constexpr int ORDER_KEYS = 1024;
+
+__device__ __forceinline__ int order_key(int cost, int shift) {
+  return ORDER_KEYS - 1 - min(cost >> shift, ORDER_KEYS - 1);  // longest first
+}
+
+// one block per per-XCD range [b, e) of the persistent kernels' queues
+__global__ __launch_bounds__(ORDER_KEYS) void k_tile_order(const int* __restrict__ cost, int total_tiles, int shift,
+                                                           int* __restrict__ order) {
+  __shared__ int start[ORDER_KEYS];
+  const int tid = threadIdx.x;
+  const int b = (int)(((long long)total_tiles * blockIdx.x) >> 3);
+  const int e = (int)(((long long)total_tiles * (blockIdx.x + 1)) >> 3);
+  start[tid] = 0;
+  __syncthreads();
+  for (int t = b + tid; t < e; t += ORDER_KEYS) atomicAdd(&start[order_key(gld(cost + t), shift)], 1);
+  __syncthreads();
+  // exclusive prefix sum of the key counts (Hillis-Steele)
+  const int count = start[tid];
+  int v = count;
+  for (int d = 1; d < ORDER_KEYS; d <<= 1) {
+    const int add = tid >= d ? start[tid - d] : 0;
+    __syncthreads();
+    v += add;
+    start[tid] = v;
+    __syncthreads();
+  }
+  start[tid] = v - count;
+  __syncthreads();
+  for (int t = b + tid; t < e; t += ORDER_KEYS) {
+    const int pos = atomicAdd(&start[order_key(gld(cost + t), shift)], 1);
+    order[b + pos] = t;
+  }
+}
+
+hipError_t launch_tile_order(const LaunchPlan& P, hipStream_t stream) {
+  if (P.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_cost, dim3((P.total_tiles + 3) / 4), dim3(256), 0, stream, P.scenes, P.n_scenes,
+                     P.total_tiles, P.tile_cost);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_order, dim3(8), dim3(ORDER_KEYS), 0, stream, P.tile_cost, P.total_tiles, P.order_shift,
+                     P.tile_order);
+  return hipGetLastError();
 }
 
 hipError_t launch_trace_adj(const LaunchPlan& P, hipStream_t stream) {
