@@ -67,7 +67,7 @@ def parse(argv=None):
     p.add_argument("--mlp-depth", type=int, default=4, help="network field: hidden layers of 64 units")
     p.add_argument("--pde-points", type=int, default=8192, help="network field: collocation points per step")
     p.add_argument("--boundary-points", type=int, default=4096, help="network field: inlet-plane points per step")
-    p.add_argument("--ckpt", type=int, default=8, help="checkpoint stride (steps)")
+    p.add_argument("--ckpt", type=int, default=6, help="checkpoint stride (steps): 6 replays chunks of 6 at 4 wavefronts per SIMD")
     p.add_argument("--tile", default="8x8", help="forward: rays per wavefront tile")
     p.add_argument("--wpb", type=int, default=4, help="forward: wavefronts per block")
     p.add_argument("--persistent", type=int, default=0, help="forward: persistent blocks with tile queues")

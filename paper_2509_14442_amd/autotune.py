@@ -29,7 +29,7 @@ LAUNCHES: List[Tuple[Tuple[int, int], int, bool, int]] = [
     ((8, 8), 2, True, 0),
     ((8, 8), 4, True, 2),
 ]
-STRIDES = (1, 8, 16, 32)  # 1: every step stored (24 B per ray-step), no replay
+STRIDES = (1, 6, 8, 16, 32)  # 1: every step stored (24 B per ray-step), no replay; 6: 4 wavefronts per SIMD
 
 
 def _bucket(x: float) -> int:

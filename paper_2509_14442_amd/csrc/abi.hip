@@ -116,9 +116,9 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
     return fail(RBOS_E_RANGE, "scene %d: max_steps must be in [1, 65536]", idx);
   if (S->tracer != RBOS_TRACER_NONLINEAR && S->tracer != RBOS_TRACER_QUASILINEAR)
     return fail(RBOS_E_RANGE, "scene %d: tracer must be RBOS_TRACER_NONLINEAR or RBOS_TRACER_QUASILINEAR", idx);
-  if (S->ckpt_stride != 0 && S->ckpt_stride != 1 &&
+  if (S->ckpt_stride != 0 && S->ckpt_stride != 1 && S->ckpt_stride != 6 &&
       !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
-    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 1 or a multiple of 8 up to 256 (got %d)", idx,
+    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 1, 6 or a multiple of 8 up to 256 (got %d)", idx,
                 S->ckpt_stride);
   if (need_render) {
     if (!S->pattern) return fail(RBOS_E_NULL, "scene %d: pattern is NULL", idx);

@@ -19,10 +19,13 @@ namespace rbos {
 
 // Everything the reverse sweep needs about one sample.
 struct SampleRev {
-  Cell C;
+  float f[3];        // fraction within the cell
+  int key;           // cell_key of the cell
   float g[3], H[3];  // code-unit gradient and mixed second derivatives
   float eta;         // 1 + delta
 };
+
+__device__ __forceinline__ int cell_key(const Cell& C);
 
 template <int DT>
 __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, SampleRev& R) {
@@ -31,7 +34,9 @@ __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, Sam
   float q;
   trilinear_h(c, C.f, q, R.g, R.H);
   R.eta = fmaf(q, S.dec, S.one_plus_off);
-  R.C = C;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) R.f[a] = C.f[a];
+  R.key = cell_key(C);
 }
 
 // Reverse of K = force(P) for an adjoint v = dL/dK: returns p = dL/dP (grid units) and
@@ -52,7 +57,7 @@ __device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R,
   p[1] = fmaf(ds, R.g[1], R.eta * fmaf(w0, R.H[0], w2 * R.H[2]));
   p[2] = fmaf(ds, R.g[2], R.eta * fmaf(w0, R.H[1], w1 * R.H[2]));
   // corner weights: w = X_i Y_j Z_k with X_0 = 1 - fx, X_1 = fx; dX_i/du = -1, +1
-  const float fx = R.C.f[0], fy = R.C.f[1], fz = R.C.f[2];
+  const float fx = R.f[0], fy = R.f[1], fz = R.f[2];
   const float X[2] = {1.0f - fx, fx}, Y[2] = {1.0f - fy, fy}, Z[2] = {1.0f - fz, fz};
   const float ed = R.eta * S.inv_dec;
   const float Wx = w0 * ed, Wy = w1 * ed, Wz = w2 * ed;
@@ -300,18 +305,19 @@ __device__ __forceinline__ void adjoint_ray_setup(const SceneDev& S, int tile, i
 }
 
 // Initial condition v0 = (1 + delta(x0)) dir: dL/d delta_c += w_c(x0) sum_a tb0_a dir_a /
-// voxel_a, with tb0 = dL/dv0 in grid units. Contributions of lanes with `active`.
-__device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, bool active, const float tb0[3],
-                                           Accum& A, Pending& P, int lane) {
+// voxel_a, with tb0 = dL/dv0 in grid units and V = v0 (m per unit t). Contributions of
+// lanes with `active`.
+__device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, const float V[3], bool active,
+                                           const float tb0[3], Accum& A, Pending& P, int lane) {
   int key0 = 0;
   float c0v[8];
   if (active) {
     Cell C0;
     locate3(S, B.U0hi, B.U0lo, C0);
-    const float vn = sqrtf(B.V[0] * B.V[0] + B.V[1] * B.V[1] + B.V[2] * B.V[2]);
+    const float vn = sqrtf(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
     float kap = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) kap = fmaf(tb0[a], (B.V[a] / vn) * dd_to_f(S.inv_vox[a]), kap);
+    for (int a = 0; a < 3; ++a) kap = fmaf(tb0[a], (V[a] / vn) * dd_to_f(S.inv_vox[a]), kap);
     const float X[2] = {1.0f - C0.f[0], C0.f[0]}, Y[2] = {1.0f - C0.f[1], C0.f[1]}, Z[2] = {1.0f - C0.f[2], C0.f[2]};
 #pragma unroll
     for (int k = 0; k < 8; ++k) c0v[k] = kap * (X[k & 1] * Y[(k >> 1) & 1] * Z[k >> 2]);
@@ -466,7 +472,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rs[a] += p[a];
             ts[a] = fmaf(h_2, p[a], ts[a]);
           }
-          key = cell_key(R2.C);
+          key = R2.key;
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
@@ -479,14 +485,20 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rb[a] = rs[a] + p[a];
             tb[a] = ts[a];
           }
-          key = cell_key(R1.C);
+          key = R1.key;
         }
         accumulate(S, A, act, key, ct, lane, P);
       }
       chunk_end(S, P, lane);
     }
   }
-  entry_term(S, B, active, tb, A, P, lane);
+  // v0 from the ray header again rather than held in registers through the sweep
+  float V0[3] = {0.0f, 0.0f, 0.0f};
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) V0[a] = gld(S.ckpt + (size_t)q + (size_t)(12 + a) * (size_t)S.ckpt_pad);
+  }
+  entry_term(S, B, V0, active, tb, A, P, lane);
   flush(S, A, A.key != CELL_NONE, lane, P);
   if (P.occupied) write_out(S, P, P.occupied, lane);
 }
@@ -564,7 +576,7 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
   float tb0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) tb0[a] = fmaf((float)n * h, R.rb[a], R.tb[a]) + pv[a];
-  entry_term(S, B, active, tb0, A, P, lane);
+  entry_term(S, B, B.V, active, tb0, A, P, lane);
   flush(S, A, A.key != CELL_NONE, lane, P);
   if (P.occupied) write_out(S, P, P.occupied, lane);
 }
@@ -621,8 +633,13 @@ static hipError_t launch_adj_ql(const LaunchPlan& P, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// Occupancy: chunks of 8 steps take 13 KB of LDS per wavefront, so 3 wavefronts per SIMD;
+// chunks of 6 take 10 KB, and 4 fit when the registers are held to 128.
+template <int KS>
+constexpr int adj_waves_per_simd() { return KS == 6 ? 4 : 3; }
+
 template <int DT, int KS, bool STORED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_per_simd<KS>()))) void k_trace_adj(
     const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, int wpb, int nblocks) {
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
@@ -634,7 +651,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 }
 
 template <int DT, int KS, bool STORED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_adj_persistent(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_per_simd<KS>()))) void k_trace_adj_persistent(
     const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, unsigned int* __restrict__ queues,
     const int* __restrict__ order) {
   const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
@@ -676,9 +693,11 @@ static hipError_t launch_adj_t(const LaunchPlan& P, hipStream_t stream) {
 template <int DT>
 static hipError_t launch_adj_dt(const LaunchPlan& P, hipStream_t stream) {
   if (P.tracer == 1) return launch_adj_ql<DT>(P, stream);
-  // chunks of 8 step-start states in LDS: stride 1 fills them from the checkpoints,
-  // strides 8, 16, ... replay them
-  return P.ckpt_k == 1 ? launch_adj_t<DT, 8, true>(P, stream) : launch_adj_t<DT, 8, false>(P, stream);
+  // chunks of step-start states in LDS: stride 1 fills chunks of 8 from the checkpoints,
+  // stride 6 replays chunks of 6, strides 8, 16, ... chunks of 8
+  if (P.ckpt_k == 1) return launch_adj_t<DT, 8, true>(P, stream);
+  if (P.ckpt_k == 6) return launch_adj_t<DT, 6, false>(P, stream);
+  return launch_adj_t<DT, 8, false>(P, stream);
 }
 
 // Processing order of the persistent adjoint. A tile's reverse sweep lasts as long as

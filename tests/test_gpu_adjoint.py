@@ -58,7 +58,7 @@ def test_loss_and_dl_duv_unit_box():
     assert np.abs(got - dL).max() <= 1e-4 * scale
 
 
-@pytest.mark.parametrize("ckpt", [1, 8, 16, 32])
+@pytest.mark.parametrize("ckpt", [1, 6, 8, 16, 32])
 def test_adjoint_unit_box_matches_oracle(ckpt):
     w = unit_box_workload()
     from bos_inputs import plume_unit_box, temperature_grid
