@@ -115,6 +115,11 @@ def test_forward_output_and_workspace_checks(lib):
     assert rc == -1 and "wall_uv" in msg
     rc, msg = _fwd(lib, s, outs=L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0))
     assert rc == -1 and "ckpt" in msg
+    for k in (1, 6, 8, 256):  # accepted strides: the error is the missing checkpoint buffer
+        s.ckpt_stride = k
+        rc, msg = _fwd(lib, s, outs=L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0))
+        assert rc == -1 and "ckpt" in msg, (k, msg)
+    s.ckpt_stride = 16
     rc, msg = _fwd(lib, s, ws=0)
     assert rc == -5
     rc, msg = _fwd(lib, s, ws_bytes=16)
