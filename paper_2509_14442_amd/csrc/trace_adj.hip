@@ -503,6 +503,26 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   if (P.occupied) write_out(S, P, P.occupied, lane);
 }
 
+// The persistent kernels' per-XCD queues, in order-index space: XCD x owns runs of
+// TILE_RUN tiles, every 8th run (so each XCD gets rows from the whole image and an even
+// share of the work), then an eighth of the tiles past the last whole round of runs.
+constexpr int TILE_RUN = 32;
+
+__device__ __forceinline__ void xcd_tile_range(int total, int x, int& b, int& e) {
+  const int full = total / (8 * TILE_RUN);
+  const int rem = total - full * 8 * TILE_RUN;
+  b = x * full * TILE_RUN + (int)(((long long)rem * x) >> 3);
+  e = (x + 1) * full * TILE_RUN + (int)(((long long)rem * (x + 1)) >> 3);
+}
+
+// i-th tile owned by XCD x (0 <= i < the size of its range)
+__device__ __forceinline__ int xcd_tile(int total, int x, int i) {
+  const int full = total / (8 * TILE_RUN);
+  if (i < full * TILE_RUN) return ((i / TILE_RUN) * 8 + x) * TILE_RUN + i % TILE_RUN;
+  const int rem = total - full * 8 * TILE_RUN;
+  return full * 8 * TILE_RUN + (int)(((long long)rem * x) >> 3) + (i - full * TILE_RUN);
+}
+
 // Quasi-linear form: the stage points lie on the entry line, at its half-step points
 // j = 0 .. 2n (P(j) = U0 + j g2, g2 = V h / 2 in grid units), so the reverse needs no
 // states. The state recursion is linear: with r = dL/dd and tau_k = dL/de after step k,
@@ -603,8 +623,8 @@ __global__ __launch_bounds__(256) void k_trace_adj_ql_persistent(const SceneDev*
   float* cache = lds + wave * (PEND_SLOTS * 8);
   for (int q = 0; q < 8; ++q) {
     const int qx = (xcd + q) & 7;
-    const int q_begin = (int)(((long long)total_tiles * qx) >> 3);
-    const int q_end = (int)(((long long)total_tiles * (qx + 1)) >> 3);
+    int q_begin, q_end;
+    xcd_tile_range(total_tiles, qx, q_begin, q_end);
     while (true) {
       int t = 0;
       if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
@@ -660,8 +680,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_p
   float* replay = lds + wave * lds_floats_per_wave<KS>();
   for (int q = 0; q < 8; ++q) {
     const int qx = (xcd + q) & 7;
-    const int q_begin = (int)(((long long)total_tiles * qx) >> 3);
-    const int q_end = (int)(((long long)total_tiles * (qx + 1)) >> 3);
+    int q_begin, q_end;
+    xcd_tile_range(total_tiles, qx, q_begin, q_end);
     while (true) {
       int t = 0;
       if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
@@ -724,16 +744,17 @@ __device__ __forceinline__ int order_key(int cost, int shift) {
   return ORDER_KEYS - 1 - min(cost >> shift, ORDER_KEYS - 1);  // longest first
 }
 
-// one block per per-XCD range [b, e) of the persistent kernels' queues
+// one block per XCD: the tiles it owns, longest first, into its range [b, e) of order
 __global__ __launch_bounds__(ORDER_KEYS) void k_tile_order(const int* __restrict__ cost, int total_tiles, int shift,
                                                            int* __restrict__ order) {
   __shared__ int start[ORDER_KEYS];
-  const int tid = threadIdx.x;
-  const int b = (int)(((long long)total_tiles * blockIdx.x) >> 3);
-  const int e = (int)(((long long)total_tiles * (blockIdx.x + 1)) >> 3);
+  const int tid = threadIdx.x, x = blockIdx.x;
+  int b, e;
+  xcd_tile_range(total_tiles, x, b, e);
   start[tid] = 0;
   __syncthreads();
-  for (int t = b + tid; t < e; t += ORDER_KEYS) atomicAdd(&start[order_key(gld(cost + t), shift)], 1);
+  for (int i = tid; i < e - b; i += ORDER_KEYS)
+    atomicAdd(&start[order_key(gld(cost + xcd_tile(total_tiles, x, i)), shift)], 1);
   __syncthreads();
   // exclusive prefix sum of the key counts (Hillis-Steele)
   const int count = start[tid];
@@ -747,7 +768,8 @@ __global__ __launch_bounds__(ORDER_KEYS) void k_tile_order(const int* __restrict
   }
   start[tid] = v - count;
   __syncthreads();
-  for (int t = b + tid; t < e; t += ORDER_KEYS) {
+  for (int i = tid; i < e - b; i += ORDER_KEYS) {
+    const int t = xcd_tile(total_tiles, x, i);
     const int pos = atomicAdd(&start[order_key(gld(cost + t), shift)], 1);
     order[b + pos] = t;
   }
