@@ -211,6 +211,27 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
   return ((k / XCD_RUN) * 8 + x) * XCD_RUN + k % XCD_RUN;
 }
 
+// The persistent kernels' per-XCD queues (in the adjoint, positions in its tile order):
+// XCD x owns runs of TILE_RUN tiles, every 8th run (so each XCD gets rows from the whole
+// image and an even share of the work), then an eighth of the tiles past the last whole
+// round of runs.
+constexpr int TILE_RUN = 32;
+
+__device__ __forceinline__ void xcd_tile_range(int total, int x, int& b, int& e) {
+  const int full = total / (8 * TILE_RUN);
+  const int rem = total - full * 8 * TILE_RUN;
+  b = x * full * TILE_RUN + (int)(((long long)rem * x) >> 3);
+  e = (x + 1) * full * TILE_RUN + (int)(((long long)rem * (x + 1)) >> 3);
+}
+
+// i-th tile owned by XCD x (0 <= i < the size of its range)
+__device__ __forceinline__ int xcd_tile(int total, int x, int i) {
+  const int full = total / (8 * TILE_RUN);
+  if (i < full * TILE_RUN) return ((i / TILE_RUN) * 8 + x) * TILE_RUN + i % TILE_RUN;
+  const int rem = total - full * 8 * TILE_RUN;
+  return full * 8 * TILE_RUN + (int)(((long long)rem * x) >> 3) + (i - full * TILE_RUN);
+}
+
 // The same value in every lane, made visible as such to the compiler (kept in an SGPR, so
 // that the scene record it indexes is read with scalar loads).
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }

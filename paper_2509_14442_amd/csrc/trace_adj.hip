@@ -503,26 +503,6 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   if (P.occupied) write_out(S, P, P.occupied, lane);
 }
 
-// The persistent kernels' per-XCD queues, in order-index space: XCD x owns runs of
-// TILE_RUN tiles, every 8th run (so each XCD gets rows from the whole image and an even
-// share of the work), then an eighth of the tiles past the last whole round of runs.
-constexpr int TILE_RUN = 32;
-
-__device__ __forceinline__ void xcd_tile_range(int total, int x, int& b, int& e) {
-  const int full = total / (8 * TILE_RUN);
-  const int rem = total - full * 8 * TILE_RUN;
-  b = x * full * TILE_RUN + (int)(((long long)rem * x) >> 3);
-  e = (x + 1) * full * TILE_RUN + (int)(((long long)rem * (x + 1)) >> 3);
-}
-
-// i-th tile owned by XCD x (0 <= i < the size of its range)
-__device__ __forceinline__ int xcd_tile(int total, int x, int i) {
-  const int full = total / (8 * TILE_RUN);
-  if (i < full * TILE_RUN) return ((i / TILE_RUN) * 8 + x) * TILE_RUN + i % TILE_RUN;
-  const int rem = total - full * 8 * TILE_RUN;
-  return full * 8 * TILE_RUN + (int)(((long long)rem * x) >> 3) + (i - full * TILE_RUN);
-}
-
 // Quasi-linear form: the stage points lie on the entry line, at its half-step points
 // j = 0 .. 2n (P(j) = U0 + j g2, g2 = V h / 2 in grid units), so the reverse needs no
 // states. The state recursion is linear: with r = dL/dd and tau_k = dL/de after step k,

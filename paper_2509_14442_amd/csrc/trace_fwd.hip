@@ -157,8 +157,8 @@ __global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ 
   trace_one<DT, QL>(S, r, pix, smp);
 }
 
-// Persistent form: blocks pull tiles from per-XCD queues (contiguous tile ranges), and
-// steal from the other XCDs' ranges once their own is drained.
+// Persistent form: blocks pull tiles from per-XCD queues (every 8th run of tiles), and
+// steal from the other XCDs' queues once their own is drained.
 template <int DT, bool QL>
 __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __restrict__ scenes, int n_scenes,
                                                               int total_tiles, unsigned int* __restrict__ queues) {
@@ -166,13 +166,14 @@ __global__ __launch_bounds__(256) void k_trace_fwd_persistent(const SceneDev* __
   const int xcd = blockIdx.x & 7;
   for (int q = 0; q < 8; ++q) {
     const int qx = (xcd + q) & 7;
-    const int q_begin = (int)(((long long)total_tiles * qx) >> 3);
-    const int q_end = (int)(((long long)total_tiles * (qx + 1)) >> 3);
+    int q_begin, q_end;
+    xcd_tile_range(total_tiles, qx, q_begin, q_end);
     while (true) {
       int t = 0;
       if (lane == 0) t = (int)atomicAdd(&queues[qx], 1u);
-      t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
-      if (t >= q_end) break;
+      t = wave_uniform(t);  // lane 0's claim (all lanes active)
+      if (t >= q_end - q_begin) break;
+      t = xcd_tile(total_tiles, qx, t);
       const int si = find_scene(scenes, n_scenes, t);
       const SceneDev& S = scenes[si];
       const int tile = t - S.tile_begin;
