@@ -508,7 +508,7 @@ def mlp_timing(args, W, cur):
     return {
         "grid_forward_ms": ms[0], "bos_chain_backward_ms": ms[1], "boundary_loss_ms": ms[2], "pde_loss_ms": ms[3],
         "params": int(W.mlp.params.numel()), "loss_boundary": float(W.loss_b[0]), "loss_pde": float(W.loss_pde[0]),
-        "roofline_grid_forward": {"kernels": "k_mlp_first + k_mlp_dense x %d + k_mlp_out" % (D - 1), "bound": "mfma",
+        "roofline_grid_forward": {"kernels": "k_mlp_forward_fused (%d layers)" % (D + 1), "bound": "mfma",
                                   "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                                   "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "flop_per_point": flop_point,
                                   "points": n},

@@ -3,10 +3,11 @@
 // point as dL/d(outputs), and the chain from dL/d(eta - 1) on the voxel grid to
 // dL/dT_nd (eta - 1 = rho0 G T0 / T, T = T0 + (T_in - T0) T_nd).
 //
-// The 64 x 64 layers are v_mfma_f32_32x32x2f32 products (FP32 inputs and accumulation):
-// one wavefront computes a 32-point x 64-unit tile, its lanes holding the tile's inputs
-// along K in two halves (lane half h supplies k = 32h + s at step s), with the bias and
-// tanh applied to the accumulators before the store. The parameter gradient, a sum over
+// The 64 x 64 layers are v_mfma_f32_32x32x2f32 products (FP32 inputs and accumulation).
+// The forward runs all layers of 32 points in one wavefront, the activations staying in
+// registers between layers (k_mlp_forward_fused). The backward's products take one
+// 32-point x 64-unit tile per wavefront, its lanes holding the tile's inputs along K in
+// two halves (lane half h supplies k = 32h + s at step s). The parameter gradient, a sum over
 // points of outer products, runs on the same instruction with the points as K; each
 // block reduces a fixed range of points and a second kernel sums the blocks in order,
 // so the result does not depend on scheduling.
@@ -52,36 +53,12 @@ __device__ __forceinline__ void xhat(const MlpDev& M, long long p, float x[3]) {
   }
 }
 
-// a_1 = tanh(xhat W_0 + b_0): one thread per (point, 4 units); xh [n][4] keeps the inputs
-// (the fourth column 0) for the first layer's parameter gradient
-__global__ __launch_bounds__(256) void k_mlp_first(MlpDev M, float* __restrict__ a1, float* __restrict__ xh) {
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long p = idx >> 4;
-  const int j0 = (int)(idx & 15) * 4;
-  if (p >= M.n) return;
-  float x[3];
-  xhat(M, p, x);
-  if (j0 == 0) *reinterpret_cast<f32x4*>(xh + p * 4) = f32x4{x[0], x[1], x[2], 0.0f};
-  const float* W = M.params + M.off_w[0];
-  float z[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    z[i] = M.params[M.off_b[0] + j0 + i];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) z[i] = fmaf(x[a], W[a * MLP_WIDTH + j0 + i], z[i]);
-  }
-  *reinterpret_cast<f32x4*>(a1 + p * MLP_WIDTH + j0) =
-      f32x4{tanh_fast(z[0]), tanh_fast(z[1]), tanh_fast(z[2]), tanh_fast(z[3])};
-}
-
 // One 32-row tile of C = A B (A [n][64], B [64][64] row-major, C [n][64]) per wavefront,
-// then the epilogue: EPI_TANH: C = tanh(C + bias); EPI_DTANH: C *= 1 - a^2 (a [n][64]);
-// EPI_NONE: C as is.
-enum { EPI_TANH = 0, EPI_DTANH = 1, EPI_NONE = 2 };
+// then the epilogue: EPI_DTANH: C *= 1 - a^2 (a [n][64]); EPI_NONE: C as is.
+enum { EPI_DTANH = 1, EPI_NONE = 2 };
 template <int EPI>
 __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __restrict__ A, const float* __restrict__ B,
-                                                   const float* __restrict__ bias, const float* __restrict__ act,
-                                                   float* __restrict__ C) {
+                                                   const float* __restrict__ act, float* __restrict__ C) {
   // the block's four wavefronts share the weights, staged in LDS (rows padded to 65)
   __shared__ float Bs[MLP_WIDTH * 65];
 #pragma unroll
@@ -130,7 +107,6 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
   for (int t = 0; t < 2; ++t) {
     const f32x16& acc = t == 0 ? acc0 : acc1;
     const int col = 32 * t + c;
-    const float bc = EPI == EPI_TANH ? bias[col] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const long long rr = row0 + acc_row(r, h);
@@ -139,8 +115,6 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
         if constexpr (EPI == EPI_DTANH) {
           const float y = yv[t][r];
           v = acc[r] * (1.0f - y * y);
-        } else if constexpr (EPI == EPI_TANH) {
-          v = tanh_fast(acc[r] + bc);
         } else {
           v = acc[r];
         }
@@ -150,31 +124,109 @@ __global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __r
   }
 }
 
-// out = a_D W_D + b_D (and T = T0 + dT out_0): one thread per point, its row read with
-// 16-byte loads
-__global__ __launch_bounds__(256) void k_mlp_out(MlpDev M, const float* __restrict__ aD, float* __restrict__ out,
-                                                 float* __restrict__ T, float T0, float dT) {
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= M.n) return;
-  const float* W = M.params + M.off_w[M.depth];
-  const float* bo = M.params + M.off_b[M.depth];
-  const f32x4* a4 = reinterpret_cast<const f32x4*>(aD + p * MLP_WIDTH);
-  float z[MLP_OUT];
-#pragma unroll
-  for (int o = 0; o < MLP_OUT; ++o) z[o] = bo[o];
-#pragma unroll 4
-  for (int q = 0; q < MLP_WIDTH / 4; ++q) {
-    const f32x4 v = a4[q];
-    const float a[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int o = 0; o < MLP_OUT; ++o) z[o] = fmaf(a[i], W[(4 * q + i) * MLP_OUT + o], z[o]);
+// Fused forward: every layer of 32 points per wavefront, the activations kept in
+// registers from layer to layer (each layer's are still written out for the backward
+// pass). The hidden layers run transposed, C^T = W^T A^T (units as rows, points as
+// columns), so that one layer's accumulators are the next layer's B operand as they
+// stand: register r of the unit tile t in a lane of half h holds unit 32 t + acc_row(r, h)
+// of point lane % 32, and step s = 16 t + r of the next product takes, in half h, that
+// register with the weight W[32 t + acc_row(r, h)][unit] as the A operand (the two
+// halves supply the two K values of the step). The block stages all weights in LDS once
+// and its wavefronts loop over groups of 32 points.
+constexpr int FUSED_PITCH = 72;  // LDS row pitch of a staged 64 x 64 weight matrix
+
+__host__ __device__ constexpr int fused_lds_floats(int depth) {
+  return (depth - 1) * MLP_WIDTH * FUSED_PITCH + depth * MLP_WIDTH + 3 * MLP_WIDTH + MLP_WIDTH * MLP_OUT + 8;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward_fused(MlpDev M, float* __restrict__ act, float* __restrict__ xh,
+                                                           float* __restrict__ out, float* __restrict__ T, float T0,
+                                                           float dT) {
+  extern __shared__ float lds[];
+  const int D = M.depth;
+  float* Wh = lds;                                         // W_1 .. W_{D-1}, rows padded
+  float* bh = Wh + (D - 1) * MLP_WIDTH * FUSED_PITCH;      // b_0 .. b_{D-1}
+  float* W0 = bh + D * MLP_WIDTH;                          // [3][64]
+  float* WD = W0 + 3 * MLP_WIDTH;                          // [64][5]
+  float* bD = WD + MLP_WIDTH * MLP_OUT;                    // [5]
+  const float* P = M.params;
+  for (int e = threadIdx.x; e < (D - 1) * MLP_WIDTH * MLP_WIDTH; e += 256) {
+    const int l = e / (MLP_WIDTH * MLP_WIDTH), k = (e / MLP_WIDTH) % MLP_WIDTH, u = e % MLP_WIDTH;
+    Wh[(l * MLP_WIDTH + k) * FUSED_PITCH + u] = P[M.off_w[l + 1] + k * MLP_WIDTH + u];
   }
-  if (out)
+  for (int e = threadIdx.x; e < D * MLP_WIDTH; e += 256) bh[e] = P[M.off_b[e / MLP_WIDTH] + e % MLP_WIDTH];
+  for (int e = threadIdx.x; e < 3 * MLP_WIDTH; e += 256) W0[e] = P[M.off_w[0] + e];
+  for (int e = threadIdx.x; e < MLP_WIDTH * MLP_OUT; e += 256) WD[e] = P[M.off_w[D] + e];
+  if (threadIdx.x < MLP_OUT) bD[threadIdx.x] = P[M.off_b[D] + threadIdx.x];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+  const long long n = M.n;
+  const long long stride = (long long)gridDim.x * 4;
+  for (long long g = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); g * 32 < n; g += stride) {
+    const long long p = g * 32 + c;
+    const bool valid = p < n;
+    float x[3] = {0.0f, 0.0f, 0.0f};
+    if (valid) xhat(M, p, x);
+    if (valid && h == 0) *reinterpret_cast<f32x4*>(xh + p * 4) = f32x4{x[0], x[1], x[2], 0.0f};
+    // a[16 t + r]: unit 32 t + acc_row(r, h) of point p
+    float a[32];
 #pragma unroll
-    for (int o = 0; o < MLP_OUT; ++o) out[p * MLP_OUT + o] = z[o];
-  if (T) T[p] = fmaf(dT, z[0], T0);
+    for (int i = 0; i < 32; ++i) {
+      const int u = 32 * (i >> 4) + acc_row(i & 15, h);
+      float z = bh[u];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) z = fmaf(x[d], W0[d * MLP_WIDTH + u], z);
+      a[i] = tanh_fast(z);
+    }
+    for (int l = 0; l < D; ++l) {
+      if (l > 0) {
+        const float* W = Wh + (l - 1) * MLP_WIDTH * FUSED_PITCH;
+        f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+          const float* w = W + (32 * (s >> 4) + acc_row(s & 15, h)) * FUSED_PITCH;
+          acc0 = mfma32(w[c], a[s], acc0);
+          acc1 = mfma32(w[32 + c], a[s], acc1);
+        }
+        const float* b = bh + l * MLP_WIDTH;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          a[r] = tanh_fast(acc0[r] + b[acc_row(r, h)]);
+          a[16 + r] = tanh_fast(acc1[r] + b[32 + acc_row(r, h)]);
+        }
+      }
+      if (valid) {  // a_{l+1} [n][64]: units 32 t + 8 j + 4 h .. +3 are a[16 t + 4 j .. +3]
+        float* dst = act + (size_t)l * (size_t)n * MLP_WIDTH + p * MLP_WIDTH + 4 * h;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          *reinterpret_cast<f32x4*>(dst + 32 * (q >> 2) + 8 * (q & 3)) =
+              f32x4{a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]};
+      }
+    }
+    if (out || T) {
+      float z[MLP_OUT];
+#pragma unroll
+      for (int o = 0; o < MLP_OUT; ++o) z[o] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const int u = 32 * (i >> 4) + acc_row(i & 15, h);
+#pragma unroll
+        for (int o = 0; o < MLP_OUT; ++o) z[o] = fmaf(a[i], WD[u * MLP_OUT + o], z[o]);
+      }
+#pragma unroll
+      for (int o = 0; o < MLP_OUT; ++o) {  // the two halves hold the point's two unit sets
+        auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(z[o]), __float_as_uint(z[o]), false, false);
+        z[o] = (__uint_as_float(sw[0]) + __uint_as_float(sw[1])) + bD[o];
+      }
+      if (valid && h == 0) {
+        if (out)
+#pragma unroll
+          for (int o = 0; o < MLP_OUT; ++o) out[p * MLP_OUT + o] = z[o];
+        if (T) T[p] = fmaf(dT, z[0], T0);
+      }
+    }
+  }
 }
 
 // delta_D = (dL/dout W_D^T) (1 - a_D^2): one thread per (point, 4 units)
@@ -321,7 +373,7 @@ __global__ __launch_bounds__(256) void k_mlp_bos_seed(long long n, const float* 
 // ------------------------------------------------------------------------------------
 constexpr int JET = 7;
 
-// first layer: the input's jet is (xhat, e_d, 0); xh [n][4] as in k_mlp_first
+// first layer: the input's jet is (xhat, e_d, 0); xh [n][4] as in k_mlp_forward_fused
 __global__ __launch_bounds__(256) void k_jet_first(MlpDev M, float* __restrict__ aj, float* __restrict__ zj,
                                                    float* __restrict__ xh) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -631,18 +683,20 @@ void mlp_work_carve(void* ws, int depth, long long n, MlpWork& w) {
 hipError_t launch_mlp_forward(const MlpDev& M, const MlpWork& w, float* out, float* T, float T0, float dT,
                               hipStream_t stream) {
   if (M.n == 0) return hipSuccess;
-  const long long n = M.n;
-  hipLaunchKernelGGL(k_mlp_first, dim3(blocks_for(n * 16)), dim3(256), 0, stream, M, w.act, w.xh);
-  for (int l = 1; l < M.depth; ++l) {
-    const float* ain = w.act + (size_t)(l - 1) * n * MLP_WIDTH;
-    float* aout = w.act + (size_t)l * n * MLP_WIDTH;
-    hipLaunchKernelGGL((k_mlp_dense<EPI_TANH>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, ain,
-                       M.params + M.off_w[l], M.params + M.off_b[l], nullptr, aout);
+  const size_t lds = sizeof(float) * (size_t)fused_lds_floats(M.depth);
+  // up to 133 KB of staged weights (8 hidden layers): allow the block more than the
+  // default dynamic LDS once
+  static size_t lds_allowed = 0;
+  if (lds > lds_allowed) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_forward_fused),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    lds_allowed = lds;
   }
-  if (out || T) {
-    const float* aD = w.act + (size_t)(M.depth - 1) * n * MLP_WIDTH;
-    hipLaunchKernelGGL(k_mlp_out, dim3(blocks_for(n)), dim3(256), 0, stream, M, aD, out, T, T0, dT);
-  }
+  const long long groups = (M.n + 31) / 32;
+  const long long blocks = (groups + 3) / 4;
+  const int grid = (int)(blocks < 2048 ? blocks : 2048);
+  hipLaunchKernelGGL(k_mlp_forward_fused, dim3(grid), dim3(256), lds, stream, M, w.act, w.xh, out, T, T0, dT);
   return hipGetLastError();
 }
 
@@ -667,7 +721,7 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
     hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(256), 0, stream, M, act(l), w.delta[cur], MLP_WIDTH,
                        MLP_WIDTH, part(l), w.rows_per_block, n, n);
     hipLaunchKernelGGL((k_mlp_dense<EPI_DTANH>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, w.delta[cur],
-                       w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, act(l), w.delta[cur ^ 1]);
+                       w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, act(l), w.delta[cur ^ 1]);
     cur ^= 1;
   }
   hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(256), 0, stream, M, w.xh, w.delta[cur], MLP_WIDTH,
@@ -751,7 +805,7 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
     hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(256), 0, stream, M, A(l), dz[cur], MLP_WIDTH,
                        MLP_WIDTH, part(l), rpb, rows, n);
     hipLaunchKernelGGL((k_mlp_dense<EPI_NONE>), dim3((unsigned)((rows + 127) / 128)), dim3(256), 0, stream, rows,
-                       dz[cur], wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, nullptr, G);
+                       dz[cur], wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, G);
     hipLaunchKernelGGL((k_jet_act_back<false>), dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, G, A(l),
                        Z(l), dz[cur ^ 1]);
     cur ^= 1;
