@@ -5,12 +5,11 @@
 //
 // The 64 x 64 layers are v_mfma_f32_32x32x2f32 products (FP32 inputs and accumulation).
 // The forward runs all layers of 32 points in one wavefront, the activations staying in
-// registers between layers (k_mlp_forward_fused). The backward's products take one
-// 32-point x 64-unit tile per wavefront, its lanes holding the tile's inputs along K in
-// two halves (lane half h supplies k = 32h + s at step s). The parameter gradient, a sum over
+// registers between layers (k_mlp_forward_fused). The parameter gradient, a sum over
 // points of outer products, runs on the same instruction with the points as K; each
 // block reduces a fixed range of points and a second kernel sums the blocks in order,
-// so the result does not depend on scheduling.
+// so the result does not depend on scheduling. The gradient one layer down is computed
+// from the same chunk of points staged in LDS (k_mlp_wgrad with a product).
 #include <hip/hip_runtime.h>
 
 #include "mlp_launch.hpp"
@@ -50,77 +49,6 @@ __device__ __forceinline__ void xhat(const MlpDev& M, long long p, float x[3]) {
     x[0] = (float)(2 * i + 1) / (float)M.nx - 1.0f;
     x[1] = (float)(2 * j + 1) / (float)M.ny - 1.0f;
     x[2] = (float)(2 * k + 1) / (float)M.nz - 1.0f;
-  }
-}
-
-// One 32-row tile of C = A B (A [n][64], B [64][64] row-major, C [n][64]) per wavefront,
-// then the epilogue: EPI_DTANH: C *= 1 - a^2 (a [n][64]); EPI_NONE: C as is.
-enum { EPI_DTANH = 1, EPI_NONE = 2 };
-template <int EPI>
-__global__ __launch_bounds__(256) void k_mlp_dense(long long n, const float* __restrict__ A, const float* __restrict__ B,
-                                                   const float* __restrict__ act, float* __restrict__ C) {
-  // the block's four wavefronts share the weights, staged in LDS (rows padded to 65)
-  __shared__ float Bs[MLP_WIDTH * 65];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    Bs[(e >> 6) * 65 + (e & 63)] = B[e];
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long row0 = ((long long)blockIdx.x * 4 + wave) * 32;
-  if (row0 >= n) return;  // whole wavefronts only: every lane takes part in the products
-  const int c = lane & 31, h = lane >> 5;
-  const long long row = row0 + c;
-  float a[32];
-  if (row < n) {
-    const f32x4* pa = reinterpret_cast<const f32x4*>(A + row * MLP_WIDTH + 32 * h);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const f32x4 v = pa[q];
-      a[4 * q] = v.x; a[4 * q + 1] = v.y; a[4 * q + 2] = v.z; a[4 * q + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int s = 0; s < 32; ++s) a[s] = 0.0f;
-  }
-  // DTANH: the activations at the tile's output positions, loaded before the products so
-  // that their latency overlaps them
-  float yv[2][16];
-  if constexpr (EPI == EPI_DTANH) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const long long rr = row0 + acc_row(r, h);
-        yv[t][r] = rr < n ? act[rr * MLP_WIDTH + 32 * t + c] : 0.0f;
-      }
-  }
-  f32x16 acc0 = {}, acc1 = {};
-#pragma unroll
-  for (int s = 0; s < 32; ++s) {
-    const float* pb = Bs + (32 * h + s) * 65;
-    acc0 = mfma32(a[s], pb[c], acc0);
-    acc1 = mfma32(a[s], pb[32 + c], acc1);
-  }
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const f32x16& acc = t == 0 ? acc0 : acc1;
-    const int col = 32 * t + c;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const long long rr = row0 + acc_row(r, h);
-      if (rr < n) {
-        float v;
-        if constexpr (EPI == EPI_DTANH) {
-          const float y = yv[t][r];
-          v = acc[r] * (1.0f - y * y);
-        } else {
-          v = acc[r];
-        }
-        C[rr * MLP_WIDTH + col] = v;
-      }
-    }
   }
 }
 
@@ -270,13 +198,28 @@ __global__ __launch_bounds__(256) void k_mlp_transpose(MlpDev M, float* __restri
 // columns of which nb are used. Four wavefronts per block: each 64-row chunk of A and B
 // is staged in LDS with coalesced loads, and wavefront (mt, nt) accumulates the 32 x 32
 // tile P[32 mt ..][32 nt ..] with the rows along K.
-template <bool XHAT>
+// With PROD, the same staged chunk also gives the gradient one layer down, written to
+// Cout [nrows][64]: Cout = B WT (WT = W^T [64][64], B 64 columns wide), times 1 - A^2
+// for PROD_DTANH. Wavefront (mt, nt) computes its rows 32 mt .. and units 32 nt .., so
+// A and B are read from HBM once for both products.
+enum { PROD_NONE = 0, PROD_DTANH = 1, PROD_PLAIN = 2 };
+template <bool XHAT, int PROD = PROD_NONE>
 __global__ __launch_bounds__(256) void k_mlp_wgrad(MlpDev M, const float* __restrict__ A, const float* __restrict__ B,
                                                    int ldb, int nb, float* __restrict__ partial,
-                                                   long long rows_per_block, long long nrows, long long bias_rows) {
+                                                   long long rows_per_block, long long nrows, long long bias_rows,
+                                                   const float* __restrict__ WT = nullptr,
+                                                   float* __restrict__ Cout = nullptr) {
   __shared__ float As[64 * 65];
   __shared__ float Bs[64 * 65];
+  __shared__ float Ws[PROD != PROD_NONE ? 64 * 65 : 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if constexpr (PROD != PROD_NONE) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = t + 256 * i;
+      Ws[(e >> 6) * 65 + (e & 63)] = WT[e];
+    }
+  }
   const int mt = wave >> 1, nt = wave & 1;
   const int c = lane & 31, h = lane >> 5;
   const long long r0 = (long long)blockIdx.x * rows_per_block;
@@ -318,6 +261,28 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(MlpDev M, const float* __rest
       const float bvv = Bs[rr * 65 + 32 * nt + c];
       acc = mfma32(As[rr * 65 + 32 * mt + c], bvv, acc);
       if (mt == 0 && base + rr < bias_rows) bsum += bvv;
+    }
+    if constexpr (PROD != PROD_NONE) {
+      // rows 32 mt + acc_row(r, h), units 32 nt + c of B WT; K = the 64 columns of B,
+      // lane half h supplying k = 32 h + s at step s
+      f32x16 d = {};
+#pragma unroll 8
+      for (int s = 0; s < 32; ++s) {
+        const int k = 32 * h + s;
+        d = mfma32(Bs[(32 * mt + c) * 65 + k], Ws[k * 65 + 32 * nt + c], d);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = 32 * mt + acc_row(r, h);
+        if (base + rr < r1) {
+          float v = d[r];
+          if constexpr (PROD == PROD_DTANH) {
+            const float y = As[rr * 65 + 32 * nt + c];
+            v *= 1.0f - y * y;
+          }
+          Cout[(base + rr) * MLP_WIDTH + 32 * nt + c] = v;
+        }
+      }
     }
     __syncthreads();
   }
@@ -718,10 +683,9 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
     // dW_l = a_l^T delta_{l+1}; delta_l = (delta_{l+1} W_l^T)(1 - a_l^2)
-    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(256), 0, stream, M, act(l), w.delta[cur], MLP_WIDTH,
-                       MLP_WIDTH, part(l), w.rows_per_block, n, n);
-    hipLaunchKernelGGL((k_mlp_dense<EPI_DTANH>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, stream, n, w.delta[cur],
-                       w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, act(l), w.delta[cur ^ 1]);
+    hipLaunchKernelGGL((k_mlp_wgrad<false, PROD_DTANH>), dim3(w.nblk), dim3(256), 0, stream, M, act(l), w.delta[cur],
+                       MLP_WIDTH, MLP_WIDTH, part(l), w.rows_per_block, n, n,
+                       w.wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, w.delta[cur ^ 1]);
     cur ^= 1;
   }
   hipLaunchKernelGGL((k_mlp_wgrad<true>), dim3(w.nblk), dim3(256), 0, stream, M, w.xh, w.delta[cur], MLP_WIDTH,
@@ -802,10 +766,8 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
     // dW_l = sum_c a_l^c^T dz_{l+1}^c (bias: value channel); G = dz_{l+1} W_l^T; dz_l
-    hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(256), 0, stream, M, A(l), dz[cur], MLP_WIDTH,
-                       MLP_WIDTH, part(l), rpb, rows, n);
-    hipLaunchKernelGGL((k_mlp_dense<EPI_NONE>), dim3((unsigned)((rows + 127) / 128)), dim3(256), 0, stream, rows,
-                       dz[cur], wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, nullptr, G);
+    hipLaunchKernelGGL((k_mlp_wgrad<false, PROD_PLAIN>), dim3((unsigned)nblk), dim3(256), 0, stream, M, A(l), dz[cur],
+                       MLP_WIDTH, MLP_WIDTH, part(l), rpb, rows, n, wt + (size_t)(l - 1) * MLP_WIDTH * MLP_WIDTH, G);
     hipLaunchKernelGGL((k_jet_act_back<false>), dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, G, A(l),
                        Z(l), dz[cur ^ 1]);
     cur ^= 1;
