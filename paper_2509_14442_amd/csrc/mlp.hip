@@ -157,37 +157,17 @@ __global__ __launch_bounds__(256) void k_mlp_forward_fused(MlpDev M, float* __re
   }
 }
 
-// delta_D = (dL/dout W_D^T) (1 - a_D^2): one thread per (point, 4 units)
-__global__ __launch_bounds__(256) void k_mlp_delta_out(MlpDev M, const float* __restrict__ dL,
-                                                       const float* __restrict__ aD, float* __restrict__ delta) {
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  const long long p = idx >> 4;
-  const int j0 = (int)(idx & 15) * 4;
-  if (p >= M.n) return;
-  const float* W = M.params + M.off_w[M.depth];
-  float l[MLP_OUT];
-#pragma unroll
-  for (int o = 0; o < MLP_OUT; ++o) l[o] = dL[p * MLP_OUT + o];
-  const f32x4 y = *reinterpret_cast<const f32x4*>(aD + p * MLP_WIDTH + j0);
-  const float yv[4] = {y.x, y.y, y.z, y.w};
-  float r[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float g = 0.0f;
-#pragma unroll
-    for (int o = 0; o < MLP_OUT; ++o) g = fmaf(l[o], W[(j0 + i) * MLP_OUT + o], g);
-    r[i] = g * (1.0f - yv[i] * yv[i]);
-  }
-  *reinterpret_cast<f32x4*>(delta + p * MLP_WIDTH + j0) = f32x4{r[0], r[1], r[2], r[3]};
-}
-
-// WT_l = W_l^T for the hidden layers l = 1 .. depth - 1
+// WT_l = W_l^T for the hidden layers l = 1 .. depth - 1, then the output layer's W_D^T
+// (5 x 64) padded with zero rows to 64 x 64, so that its product runs like the others
 __global__ __launch_bounds__(256) void k_mlp_transpose(MlpDev M, float* __restrict__ wt) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   const int l = 1 + idx / (MLP_WIDTH * MLP_WIDTH);
-  if (l >= M.depth) return;
+  if (l > M.depth) return;
   const int e = idx % (MLP_WIDTH * MLP_WIDTH), k = e / MLP_WIDTH, j = e % MLP_WIDTH;
-  wt[(l - 1) * MLP_WIDTH * MLP_WIDTH + j * MLP_WIDTH + k] = M.params[M.off_w[l] + k * MLP_WIDTH + j];
+  float v;
+  if (l < M.depth) v = M.params[M.off_w[l] + k * MLP_WIDTH + j];
+  else v = j < MLP_OUT ? M.params[M.off_w[l] + k * MLP_OUT + j] : 0.0f;
+  wt[(l - 1) * MLP_WIDTH * MLP_WIDTH + j * MLP_WIDTH + k] = v;
 }
 
 // Partial parameter gradient of one layer over this block's rows:
@@ -199,7 +179,7 @@ __global__ __launch_bounds__(256) void k_mlp_transpose(MlpDev M, float* __restri
 // is staged in LDS with coalesced loads, and wavefront (mt, nt) accumulates the 32 x 32
 // tile P[32 mt ..][32 nt ..] with the rows along K.
 // With PROD, the same staged chunk also gives the gradient one layer down, written to
-// Cout [nrows][64]: Cout = B WT (WT = W^T [64][64], B 64 columns wide), times 1 - A^2
+// Cout [nrows][64]: Cout = B WT (WT = W^T as 64 x 64, zero rows past B's nb columns), times 1 - A^2
 // for PROD_DTANH. Wavefront (mt, nt) computes its rows 32 mt .. and units 32 nt .., so
 // A and B are read from HBM once for both products.
 enum { PROD_NONE = 0, PROD_DTANH = 1, PROD_PLAIN = 2 };
@@ -620,7 +600,7 @@ size_t mlp_work_bytes(int depth, long long n) {
   size_t b = 0;
   b += al256(sizeof(float) * (size_t)depth * (size_t)n * MLP_WIDTH);
   b += 2 * al256(sizeof(float) * (size_t)n * MLP_WIDTH);
-  b += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
+  b += al256(sizeof(float) * (size_t)depth * MLP_WIDTH * MLP_WIDTH);
   b += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
   b += al256(sizeof(float) * 4 * (size_t)n);
   return b;
@@ -639,7 +619,7 @@ void mlp_work_carve(void* ws, int depth, long long n, MlpWork& w) {
   w.delta[1] = reinterpret_cast<float*>(p);
   p += al256(sizeof(float) * (size_t)n * MLP_WIDTH);
   w.wt = reinterpret_cast<float*>(p);
-  p += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
+  p += al256(sizeof(float) * (size_t)depth * MLP_WIDTH * MLP_WIDTH);
   w.partial = reinterpret_cast<float*>(p);
   p += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
   w.xh = reinterpret_cast<float*>(p);
@@ -672,13 +652,11 @@ hipError_t launch_mlp_backward(const MlpDev& M, const MlpWork& w, const float* d
   const int D = M.depth;
   auto act = [&](int l) { return w.act + (size_t)(l - 1) * n * MLP_WIDTH; };  // a_l, l = 1 .. D
   auto part = [&](int l) { return w.partial + (size_t)l * w.nblk * MLP_PART; };
-  if (D > 1)
-    hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)(D - 1) * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0,
-                       stream, M, w.wt);
+  hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)D * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0, stream, M,
+                     w.wt);
   // output layer: dW_D = a_D^T dL, db_D = sum dL; delta_D = (dL W_D^T)(1 - a_D^2)
-  hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3(w.nblk), dim3(256), 0, stream, M, act(D), dL_dout, MLP_OUT, MLP_OUT,
-                     part(D), w.rows_per_block, n, n);
-  hipLaunchKernelGGL(k_mlp_delta_out, dim3(blocks_for(n * 16)), dim3(256), 0, stream, M, dL_dout, act(D),
+  hipLaunchKernelGGL((k_mlp_wgrad<false, PROD_DTANH>), dim3(w.nblk), dim3(256), 0, stream, M, act(D), dL_dout, MLP_OUT,
+                     MLP_OUT, part(D), w.rows_per_block, n, n, w.wt + (size_t)(D - 1) * MLP_WIDTH * MLP_WIDTH,
                      w.delta[0]);
   int cur = 0;
   for (int l = D - 1; l >= 1; --l) {
@@ -706,7 +684,7 @@ size_t mlp_jet_work_bytes(int depth, long long n) {
   b += al256(sizeof(float) * (size_t)depth * (JET - 1) * (size_t)n * MLP_WIDTH);  // z jets
   b += 2 * al256(sizeof(float) * JET * (size_t)n * MLP_OUT);                      // output jets, seeds
   b += 3 * al256(sizeof(float) * JET * (size_t)n * MLP_WIDTH);                    // dz x 2, G
-  b += al256(sizeof(float) * (size_t)(depth > 1 ? depth - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
+  b += al256(sizeof(float) * (size_t)depth * MLP_WIDTH * MLP_WIDTH);
   b += al256(sizeof(float) * (size_t)(depth + 1) * (size_t)nblk * MLP_PART);
   b += al256(sizeof(float) * (size_t)((n + 255) / 256 + 1));
   b += al256(sizeof(float) * 4 * (size_t)n);
@@ -737,7 +715,7 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
   float* dj = take(sizeof(float) * JET * (size_t)n * MLP_OUT);
   float* dz[2] = {take(chw * JET), take(chw * JET)};
   float* G = take(chw * JET);
-  float* wt = take(sizeof(float) * (size_t)(D > 1 ? D - 1 : 1) * MLP_WIDTH * MLP_WIDTH);
+  float* wt = take(sizeof(float) * (size_t)D * MLP_WIDTH * MLP_WIDTH);
   float* partial = take(sizeof(float) * (size_t)(D + 1) * (size_t)nblk * MLP_PART);
   float* lpart = take(sizeof(float) * (size_t)((n + 255) / 256 + 1));
   float* xh = take(sizeof(float) * 4 * (size_t)n);
@@ -756,9 +734,8 @@ hipError_t launch_mlp_pde(const MlpDev& M, void* ws, const PdeConst& P, float* l
   if (loss) hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, lpart, blocks_for(n), loss);
   if (!dparams) return hipGetLastError();
   // reverse
-  if (D > 1)
-    hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)(D - 1) * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0,
-                       stream, M, wt);
+  hipLaunchKernelGGL(k_mlp_transpose, dim3(blocks_for((long long)D * MLP_WIDTH * MLP_WIDTH)), dim3(256), 0, stream, M,
+                     wt);
   hipLaunchKernelGGL((k_mlp_wgrad<false>), dim3((unsigned)nblk), dim3(256), 0, stream, M, A(D), dj, MLP_OUT, MLP_OUT,
                      part(D), rpb, rows, n);
   hipLaunchKernelGGL((k_jet_act_back<true>), dim3(blocks_for(n * MLP_WIDTH)), dim3(256), 0, stream, M, dj, A(D),
