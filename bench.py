@@ -43,6 +43,7 @@ FLOP_ADJ_STEP = 700
 FLOP_FWD_STEP_QL = 150
 FLOP_ADJ_STEP_QL = 320
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+PEAK_HBM_BYTES_PER_S = 8.0e12  # MI355X HBM3E (published)
 TRACERS = {"nonlinear": 0, "quasilinear": 1}
 
 
@@ -453,6 +454,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic,
+            # the counted HBM bytes per launch over the launch time, against the HBM peak
+            "hbm_frac": None if traffic is None else traffic / adj_s / PEAK_HBM_BYTES_PER_S,
             "flop_per_ray_step": flop_adj,
         },
     }
