@@ -182,3 +182,32 @@ def test_pde_loss_residuals_and_gradient(depth, n):
     loss2, g2, _ = m.pde_loss(torch.from_numpy(x).to(DEV), PDE["Re"], PDE["Pe"], PDE["Ri"], PDE["L"],
                               (PDE["g1"], PDE["g2"], PDE["g3"]), want_grad=False)
     assert g2 is None and float(loss2[0]) == float(loss[0])
+
+
+def test_network_field_at_bench_size():
+    """The network field as the benchmark runs it: depth 4 on the 128^3 voxel centres of the
+    4 x 4 x 3 m room (2,097,152 points, the largest launch of these kernels), checked on
+    4096 sampled voxels: the outputs and T there, and the parameter gradient of seeds
+    that are non-zero only at those voxels (so the oracle needs only them)."""
+    import bos_inputs as bi
+
+    lo, hi, dims = (0.0, 0.0, 0.0), (4.0, 4.0, 3.0), (128, 128, 128)
+    th = bi.mlp_params(64, 4, 3, out_scale=0.3, bias_std=0.05).astype(np.float32)
+    m = api.MLP(torch.from_numpy(th).to(DEV), 64, 4, lo, hi)
+    th64 = th.astype(np.float64)
+    out, T = m.forward(grid=dims, T0=T0, T_in=T_IN)
+    n = 128 ** 3
+    rng = np.random.default_rng(50)
+    idx = np.sort(rng.choice(n, 4096, replace=False))
+    xc = omlp.voxel_centres(lo, hi, dims)[idx]
+    ref = omlp.forward(th64, 64, 4, xc, lo, hi)
+    got = _np(out)[idx].astype(np.float64)
+    assert np.abs(got - ref).max() <= 2e-5
+    assert np.abs(_np(T)[idx] - omlp.temperature(ref[:, 0], T0, T_IN)).max() <= 3e-4
+    lam = np.zeros((n, 5), np.float32)
+    lam[idx] = rng.standard_normal((4096, 5)).astype(np.float32)
+    g = _np(m.backward(torch.from_numpy(lam).to(DEV), grid=dims)).astype(np.float64)
+    g_ref = omlp.vjp_params(th64, 64, 4, xc, lo, hi, lam[idx].astype(np.float64))
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"128^3 grid: max |out - oracle| {np.abs(got - ref).max():.2e} on 4096 voxels, dparams rel-L2 {rel:.2e}")
+    assert rel < 1e-5
