@@ -161,3 +161,59 @@ def test_batch_mixing_samples_weights_and_pixel_lists():
     g_ref = oracle.adjoint(F, s.desc, _np(lams[3]).astype(np.float64), dL_ddir=_np(lam_d[3]).astype(np.float64))
     g = _np(gb[3])
     assert np.linalg.norm(g - g_ref) <= 1e-3 * np.linalg.norm(g_ref)
+
+
+def test_batch64_bench_workload_on_sampled_rays():
+    """The 64-scene workload of the benchmark (grids 48-192 per axis, cameras 128-1024 per
+    side, 20.6M rays, checkpoint stride 6) in one persistent forward and one persistent
+    adjoint launch. Per scene, 24 sampled rays: their wall exits against the oracle, and
+    the gradient of seeds that are non-zero only on them against the oracle's adjoint of
+    those rays."""
+    import bench
+
+    args = bench.parse([])
+    pat_np = bi.blurred_noise(12, (1024, 1024)).astype(np.float32)
+    pat = torch.from_numpy(pat_np).to(DEV)
+    launch = api.make_launch((8, 8), 4, persistent=True)
+    adj_launch = api.make_launch((8, 8), 2, persistent=True)
+    scenes, temps = [], []
+    for sc, spec in bi.scenes_batch(64):
+        sc = sc.replace(ckpt_stride=args.ckpt)
+        T = bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32)
+        f = api.Field.from_temperature(torch.from_numpy(T).to(DEV), "f32")
+        scenes.append(api.Scene(sc, f, pat))
+        temps.append(T)
+    assert sum(s.n_rays for s in scenes) > 20_000_000
+    tr = api.Tracer(scenes, launch, adjoint_launch=adj_launch)
+    tr.forward()
+    rng = np.random.default_rng(64)
+    lams, samples = [], []
+    for s in scenes:
+        ids = np.sort(rng.choice(s.n_rays, 24, replace=False)).astype(np.int32)
+        lam = np.zeros((s.n_rays, 2), np.float32)
+        lam[ids] = rng.standard_normal((24, 2)).astype(np.float32)
+        samples.append(ids)
+        lams.append(torch.from_numpy(lam).to(DEV))
+    grads = tr.adjoint(dL_duv=lams)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in range(64):
+        sc, ids = scenes[i].desc, samples[i]
+        F = oracle.grid_field(stored_delta(temps[i]), sc.box_lo, sc.box_hi)
+        ref = oracle.trace(F, sc, ids)
+        ok = np.isfinite(ref["uv"][:, 0])
+        uv = _np(tr.uv[i])[ids]
+        assert np.array_equal(ok, np.isfinite(uv[:, 0])), i
+        if ok.any():
+            assert exit_error(uv[ok], ref["uv"][ok]).max() <= 1e-6, i
+        g_ref = oracle.adjoint(F, sc, _np(lams[i])[ids].astype(np.float64), ids)
+        g = _np(grads[i])
+        if np.linalg.norm(g_ref) > 0:
+            rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+            worst = max(worst, rel)
+            assert rel < 1e-3, (i, rel)
+        else:
+            assert not g.any(), i
+    print(f"64-scene batch: worst per-scene gradient rel-L2 {worst:.2e}")
+    del tr, grads, lams, scenes
+    torch.cuda.empty_cache()  # ~55 GB of checkpoints
