@@ -220,7 +220,8 @@ size_t rbos_ckpt_bytes(const rbos_scene* scene);
 
 /* Bytes of device workspace needed by rbos_trace_forward / rbos_render /
    rbos_trace_adjoint for this set of scenes (scene table, queue counters, loss
-   partials). One workspace may serve all three calls in stream order. */
+   partials, the persistent adjoint's per-tile step counts and tile order). One
+   workspace may serve all three calls in stream order. */
 size_t rbos_workspace_bytes(const rbos_scene* scenes, int32_t n_scenes);
 
 /* Trace every ray of every scene (Eq. 1 with Sharma steps) to the back wall; one launch
@@ -238,8 +239,10 @@ int rbos_render(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out
 
 /* Back-propagate dL/d(u, v) (and dL/d(wall_dir)) per ray through the wall step and
    every Sharma step (replayed from the forward checkpoints) to dL/d(eta - 1) per voxel,
-   accumulated in FP64 into io[s].grad. Needs the same scenes (ckpt_stride > 0), the forward outputs and
-   the unmodified field. */
+   accumulated in FP64 into io[s].grad. Needs the same scenes (ckpt_stride > 0), the
+   forward outputs and the unmodified field. A persistent launch first orders the tiles
+   by the forward's step counts (longest first); the order changes only the order of
+   the FP64 additions. */
 int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
                        const rbos_adjoint_io* io, const rbos_launch* launch, void* workspace,
                        size_t ws_bytes, void* stream);
