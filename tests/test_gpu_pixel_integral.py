@@ -194,3 +194,39 @@ def test_room_1m_pixels_4_samples_in_bench_configuration():
     g_ref = oracle.adjoint(F, w.scene, lam.astype(np.float64), ids, dL_ddir=lam_d.astype(np.float64))
     l2, frac = grad_errors(g, g_ref)
     assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
+
+
+def test_paper_acquisition_geometry_two_samples():
+    """The acquisition stated in Sec. 3.A-3.B: camera and projector 29 m in front of the
+    room, 100 x 100 sensor, 64^3 grid, 2 samples per pixel with the radiometric weight.
+    Whole image: exits, wall directions and pixel values against the oracle, and the
+    gradient of the pixel loss against the oracle's adjoint."""
+    sc = bi.scene_paper_geometry().replace(spp=2, seed=31, radiometry=1, ckpt_stride=bench.parse([]).ckpt)
+    lo, hi = sc.box_lo, sc.box_hi
+    T = bi.temperature_grid(bi.plumes_room(8, lo, hi), lo, hi, sc.dims).astype(np.float32)
+    T2 = bi.temperature_grid(bi.plumes_room(9, lo, hi), lo, hi, sc.dims).astype(np.float32)
+    from _common import Workload
+    w = Workload(sc, T, bi.blurred_noise(12, (sc.pat_w, sc.pat_h)))
+    tr = _tracer(w)
+    F, ref = _oracle(w)
+    tr.forward()
+    _check_forward(w, tr, ref)
+    # target: the oracle's image of the second field
+    w2 = Workload(sc, T2, w.pattern)
+    target = _oracle(w2)[1]["image"].astype(np.float32)
+    tr.render([torch.from_numpy(target).to(DEV)])
+    assert np.abs(_np(tr.image[0]) - ref["image"]).max() <= 1e-5
+    L, dL, dLd, dLp = oracle.loss_pixels(ref["image"], target.astype(np.float64), 2, ref["dI"], ref["dId"], ref["dIp"])
+    assert float(tr.loss[0]) == pytest.approx(L, rel=1e-4)
+    # the adjoint for the oracle's seeds, against the oracle's adjoint of the same seeds
+    g = _np(tr.adjoint(dL_duv=[torch.from_numpy(dL.astype(np.float32)).to(DEV)],
+                       dL_ddir=[torch.from_numpy(dLd.astype(np.float32)).to(DEV)])[0])
+    g_ref = oracle.adjoint(F, sc, dL, dL_ddir=dLd)
+    l2, frac = grad_errors(g, g_ref)
+    # end to end with the GPU's own seeds, against the loss's gradient (seeds carry the
+    # FP32 rounding of the residuals, so only the L2 bound applies)
+    g_own = _np(tr.adjoint()[0])
+    l2o, _ = grad_errors(g_own, oracle.adjoint(F, sc, dL, dL_ddir=dLd, dL_dpath=dLp))
+    print(f"paper geometry, 2 spp + weight: gradient rel-L2 {l2:.2e} (given seeds), {l2o:.2e} (end to end)")
+    assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
+    assert l2o < 1e-3, l2o
