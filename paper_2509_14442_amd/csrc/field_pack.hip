@@ -21,19 +21,22 @@ __device__ __forceinline__ unsigned int code16(float q, int dtype) {
 __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, const float* __restrict__ src,
                                                     int from_temperature, float rho0G, float T0, int dtype,
                                                     float scale, float offset, void* __restrict__ field) {
+  // at most 449^3 records: 32-bit indices (64-bit division is emulated and costs more
+  // than the record's arithmetic)
   const int px = nx + 1, py = ny + 1, pz = nz + 1;
-  const long long nrec = (long long)px * py * pz;
-  for (long long rec = (long long)blockIdx.x * blockDim.x + threadIdx.x; rec < nrec;
-       rec += (long long)gridDim.x * blockDim.x) {
-    int i = (int)(rec % px) - 1;
-    int j = (int)((rec / px) % py) - 1;
-    int k = (int)(rec / ((long long)px * py)) - 1;
+  const int nrec = px * py * pz;
+  for (int rec = blockIdx.x * blockDim.x + threadIdx.x; rec < nrec; rec += gridDim.x * blockDim.x) {
+    const int row = rec / px;
+    const int i = rec - row * px - 1;
+    const int k = row / py;
+    const int j = row - k * py - 1;
+    const int kc = k - 1;
     float q[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       int x = min(max(i + (c & 1), 0), nx - 1);
       int y = min(max(j + ((c >> 1) & 1), 0), ny - 1);
-      int z = min(max(k + (c >> 2), 0), nz - 1);
+      int z = min(max(kc + (c >> 2), 0), nz - 1);
       float v = src[((size_t)z * ny + y) * nx + x];
       if (from_temperature) {
         float ratio = T0 / v;
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, cons
       q[c] = t * scale;
     }
     if (dtype == DT_F32) {
-      float4* p = reinterpret_cast<float4*>(field) + 2 * rec;
+      float4* p = reinterpret_cast<float4*>(field) + 2 * (size_t)rec;
       p[0] = make_float4(q[0], q[1], q[2], q[3]);
       p[1] = make_float4(q[4], q[5], q[6], q[7]);
     } else {
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, cons
       w.y = code16(q[2], dtype) | (code16(q[3], dtype) << 16);
       w.z = code16(q[4], dtype) | (code16(q[5], dtype) << 16);
       w.w = code16(q[6], dtype) | (code16(q[7], dtype) << 16);
-      reinterpret_cast<uint4*>(field)[rec] = w;
+      reinterpret_cast<uint4*>(field)[(size_t)rec] = w;
     }
   }
 }
