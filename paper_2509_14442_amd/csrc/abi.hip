@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -337,15 +338,17 @@ int prepare(const rbos_scene* scenes, int32_t n_scenes, const rbos_launch* launc
   return RBOS_OK;
 }
 
+// compute units of the current device, queried once per device (safe from any thread)
 int compute_units() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-      cus = v;
-    if (cus <= 0) cus = 256;
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cache[dev].store(v, std::memory_order_relaxed);
   }
-  return cus;
+  return v;
 }
 
 int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::LaunchPlan& plan) {

@@ -12,6 +12,8 @@
 // from the same chunk of points staged in LDS (k_mlp_wgrad with a product).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "mlp_launch.hpp"
 
 namespace rbos {
@@ -629,14 +631,18 @@ hipError_t launch_mlp_forward(const MlpDev& M, const MlpWork& w, float* out, flo
                               hipStream_t stream) {
   if (M.n == 0) return hipSuccess;
   const size_t lds = sizeof(float) * (size_t)fused_lds_floats(M.depth);
-  // up to 133 KB of staged weights (8 hidden layers): allow the block more than the
-  // default dynamic LDS once
-  static size_t lds_allowed = 0;
-  if (lds > lds_allowed) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_forward_fused),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // up to 133 KB of staged weights (8 hidden layers): allow the kernel the largest size
+  // once per device (safe from any thread)
+  static std::atomic<int> lds_set[64];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64 || !lds_set[dev].load(std::memory_order_acquire)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_forward_fused),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(float) * (size_t)fused_lds_floats(MLP_MAX_DEPTH)));
     if (e != hipSuccess) return e;
-    lds_allowed = lds;
+    if (dev >= 0 && dev < 64) lds_set[dev].store(1, std::memory_order_release);
   }
   const long long groups = (M.n + 31) / 32;
   const long long blocks = (groups + 3) / 4;
