@@ -171,7 +171,10 @@ typedef struct rbos_render_io {
 /* Per-scene adjoint inputs/outputs. */
 typedef struct rbos_adjoint_io {
   const float* dL_duv;  /* [dev] [n_rays][2] */
-  double* grad;         /* [dev] [nz][ny][nx] FP64; the gradient w.r.t. eta - 1 is ADDED */
+  double* grad;         /* [dev] [nz][ny][nx] FP64; the gradient w.r.t. eta - 1 is ADDED with
+                           device-scope FP64 atomics that are correct only on coarse-grained
+                           device memory (plain hipMalloc, a torch CUDA tensor); managed,
+                           host-coherent or fine-grained buffers would accumulate wrong sums */
   const float* dL_ddir; /* [dev] [n_rays][3] dL/d(wall_dir); nullable (no direction term) */
 } rbos_adjoint_io;
 
@@ -212,6 +215,19 @@ int rbos_field_from_temperature(int32_t nx, int32_t ny, int32_t nz, const float*
    delta: [dev] [nz][ny][nx] FP32. */
 int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, int32_t dtype,
                       double enc_scale, double enc_offset, void* field, void* stream);
+
+/* Code scale for 16-bit storage (Sec. 2.A: the stored quantity is eta - 1): the largest
+   power of two s with s * max |eta - 1 - enc_offset| <= 2^14 over eta - 1 in
+   [delta_lo, delta_hi], so the codes neither overflow nor (for FP16) fall into the
+   subnormal range; 1 for RBOS_F32. Returns 0 for an unknown dtype or an invalid range.
+   The offset that makes 16-bit storage accurate is the ambient eta - 1 (rho0 G at
+   T = T0): the codes then hold only the perturbation. */
+double rbos_code_scale(int32_t dtype, double delta_lo, double delta_hi, double enc_offset);
+
+/* The same for a temperature field with T in [T_lo, T_hi] kelvin (T_lo > 0):
+   eta - 1 = rho0G T0 / T spans [rho0G T0 / T_hi, rho0G T0 / T_lo]. */
+double rbos_code_scale_temperature(int32_t dtype, double T_lo, double T_hi, double rho0G, double T0,
+                                   double enc_offset);
 
 /* --- Sec. 2.B / 2.C / 2.D: tracing, rendering, gradient ----------------------------- */
 

@@ -74,9 +74,9 @@ STRUCTS = [rbos_scene, rbos_trace_out, rbos_render_io, rbos_adjoint_io, rbos_lau
 
 EXPORTS = [
     "rbos_version", "rbos_last_error", "rbos_field_bytes", "rbos_field_from_temperature",
-    "rbos_field_encode", "rbos_ckpt_bytes", "rbos_workspace_bytes", "rbos_trace_forward",
-    "rbos_render", "rbos_trace_adjoint", "rbos_struct_layout", "rbos_mlp_param_count",
-    "rbos_mlp_workspace_bytes", "rbos_mlp_forward", "rbos_mlp_backward", "rbos_mlp_bos_seed",
+    "rbos_field_encode", "rbos_code_scale", "rbos_code_scale_temperature", "rbos_ckpt_bytes", "rbos_workspace_bytes", "rbos_trace_forward",
+    "rbos_render", "rbos_trace_adjoint", "rbos_struct_layout",
+    "rbos_mlp_param_count", "rbos_mlp_workspace_bytes", "rbos_mlp_forward", "rbos_mlp_backward", "rbos_mlp_bos_seed",
     "rbos_mlp_fit_workspace_bytes", "rbos_mlp_fit_seed", "rbos_mlp_pde_workspace_bytes", "rbos_mlp_pde_loss",
 ]
 
@@ -106,6 +106,9 @@ def load(path: str = LIB_PATH):
         "rbos_field_from_temperature": ([I32, I32, I32, P, C.c_double, C.c_double, I32, C.c_double,
                                          C.c_double, P, P], C.c_int),
         "rbos_field_encode": ([I32, I32, I32, P, I32, C.c_double, C.c_double, P, P], C.c_int),
+        "rbos_code_scale": ([I32, C.c_double, C.c_double, C.c_double], C.c_double),
+        "rbos_code_scale_temperature": ([I32, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
+                                        C.c_double),
         "rbos_ckpt_bytes": ([C.POINTER(rbos_scene)], SZ),
         "rbos_workspace_bytes": ([C.POINTER(rbos_scene), I32], SZ),
         "rbos_trace_forward": ([C.POINTER(rbos_scene), I32, C.POINTER(rbos_trace_out),

@@ -7,7 +7,6 @@ library's HIP kernels. There is no fallback: without librbos.so these functions 
 from __future__ import annotations
 
 import ctypes as C
-import math
 from typing import List, Optional, Sequence
 
 import torch
@@ -36,14 +35,6 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr())
 
 
-def code_scale(dtype: str, max_abs: float) -> float:
-    """Power-of-two scale s with s * max_abs <= 2^14 (16-bit codes: no overflow and, for
-    FP16, codes well inside the normal range); 1 for FP32."""
-    if dtype == "f32" or max_abs <= 0.0:
-        return 1.0
-    return 2.0 ** math.floor(math.log2(2.0 ** 14 / max_abs))
-
-
 class Field:
     """A packed eta - 1 field on the GPU (cell records of the corner codes)."""
 
@@ -62,16 +53,22 @@ class Field:
 
     @classmethod
     def from_temperature(cls, T: torch.Tensor, dtype: str = "f32", scale: Optional[float] = None,
-                         offset: float = 0.0, rho0G: float = RHO0G, T0: float = T_AMBIENT, stream=None):
-        """eta - 1 = rho0G * T0 / T from a [nz][ny][nx] float32 temperature tensor (kelvin)."""
+                         offset: Optional[float] = None, rho0G: float = RHO0G, T0: float = T_AMBIENT, stream=None):
+        """eta - 1 = rho0G * T0 / T from a [nz][ny][nx] float32 temperature tensor (kelvin).
+        offset (None): the ambient eta - 1, rho0G, for 16-bit storage (the codes then hold
+        only the perturbation), 0 for FP32. scale (None): the library's choice for the
+        tensor's temperature range."""
         T = T.contiguous()
         if T.dtype != torch.float32 or T.dim() != 3:
             raise ValueError("T must be a float32 [nz][ny][nx] tensor")
         nz, ny, nx = T.shape
+        if offset is None:
+            offset = 0.0 if dtype == "f32" else float(rho0G)
         if scale is None:
             tmin, tmax = (float(x) for x in torch.aminmax(T))
-            bound = max(abs(rho0G * T0 / tmin - offset), abs(rho0G * T0 / tmax - offset))
-            scale = code_scale(dtype, bound)
+            scale = lib().rbos_code_scale_temperature(DTYPES[dtype], tmin, tmax, rho0G, T0, offset)
+            if not scale > 0.0:
+                raise ValueError(f"no code scale for temperatures in [{tmin}, {tmax}] K")
         f = cls((nx, ny, nz), dtype, scale, offset, T.device)
         f.rho0G, f.T0 = rho0G, T0
         f.encode_temperature(T, stream)
@@ -90,11 +87,18 @@ class Field:
 
     @classmethod
     def from_delta(cls, delta: torch.Tensor, dtype: str = "f32", scale: Optional[float] = None,
-                   offset: float = 0.0, stream=None):
-        """Encode a given eta - 1 field ([nz][ny][nx] float32)."""
-        f = cls(tuple(reversed(delta.shape)), dtype, 1.0 if scale is None else scale, offset, delta.device)
+                   offset: Optional[float] = None, stream=None):
+        """Encode a given eta - 1 field ([nz][ny][nx] float32). offset (None): the middle of
+        the field's range for 16-bit storage, 0 for FP32; scale (None): the library's choice
+        for that range."""
+        dmin, dmax = (float(x) for x in torch.aminmax(delta))
+        if offset is None:
+            offset = 0.0 if dtype == "f32" else 0.5 * (dmin + dmax)
         if scale is None:
-            f.scale = code_scale(dtype, float((delta - offset).abs().max()))
+            scale = lib().rbos_code_scale(DTYPES[dtype], dmin, dmax, offset)
+            if not scale > 0.0:
+                raise ValueError(f"no code scale for eta - 1 in [{dmin}, {dmax}]")
+        f = cls(tuple(reversed(delta.shape)), dtype, scale, offset, delta.device)
         f.encode(delta, stream)
         return f
 

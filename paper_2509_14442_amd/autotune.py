@@ -2,7 +2,9 @@
 
 It times the forward (and, for mode "fwd+adj", render and adjoint) of the given scenes
 with HIP events on the current stream for a list of candidates, and caches the winner
-as JSON keyed by (gfx arch, storage dtype, grid-size bucket, ray-count bucket, mode).
+as JSON keyed by (gfx arch, storage dtype, tracer, samples per pixel, step-cap bucket,
+grid-size bucket, ray-count bucket, scene count, mode). On return (cached or new) the
+scenes carry the chosen checkpoint stride.
 Run it before capturing a graph: tuning launches kernels and allocates buffers.
 """
 
@@ -42,7 +44,11 @@ def cache_key(scenes: Sequence[api.Scene], mode: str) -> str:
     vox = sum(s.dims[0] * s.dims[1] * s.dims[2] for s in scenes) / max(len(scenes), 1)
     rays = sum(s.n_rays for s in scenes)
     dtype = scenes[0].field.dtype if scenes else "f32"
-    return f"v2|{arch}|{dtype}|g{_bucket(vox)}|r{_bucket(rays)}|n{len(scenes)}|{mode}"
+    tracer = int(scenes[0].struct.tracer) if scenes else 0
+    spp = max((s.spp for s in scenes), default=1)
+    steps = max((int(s.struct.max_steps) for s in scenes), default=1)
+    return (f"v3|{arch}|{dtype}|t{tracer}|spp{spp}|m{_bucket(steps)}|g{_bucket(vox)}|r{_bucket(rays)}"
+            f"|n{len(scenes)}|{mode}")
 
 
 def ckpt_bytes(scenes: Sequence[api.Scene], stride: int) -> int:
@@ -94,7 +100,10 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
         with open(cache) as f:
             db = json.load(f)
         if key in db and not force:
-            return db[key]
+            entry = db[key]
+            for s in scenes:
+                s.struct.ckpt_stride = entry["ckpt_stride"]
+            return entry
     if hbm_budget is None:
         free, _ = torch.cuda.mem_get_info()
         hbm_budget = int(free * 0.5)

@@ -381,6 +381,48 @@ int finish_launch(Prepared& P, void* workspace, hipStream_t stream, rbos::Launch
   return RBOS_OK;
 }
 
+// Per-scene arguments of the two adjoint entry points, checked and bound into the scene
+// table (host only).
+int adjoint_bind(Prepared& P, const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                 const rbos_adjoint_io* io) {
+  if (n_scenes > 0 && (!outs || !io)) return fail(RBOS_E_NULL, "outs or io is NULL");
+  for (int i = 0; i < n_scenes; ++i) {
+    if (scenes[i].ckpt_stride <= 0) return fail(RBOS_E_UNSUPPORTED, "scene %d: the adjoint needs ckpt_stride > 0", i);
+    if (scenes[i].ckpt_stride != scenes[0].ckpt_stride)
+      return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one adjoint call must share ckpt_stride", i);
+    const bool rays = scenes[i].n_pixels > 0;
+    if (rays && (!outs[i].ckpt || !outs[i].n_steps || !outs[i].status))
+      return fail(RBOS_E_NULL, "scene %d: ckpt, n_steps and status are required", i);
+    if (rays && !io[i].dL_duv) return fail(RBOS_E_NULL, "scene %d: dL_duv is required", i);
+    if (!io[i].grad) return fail(RBOS_E_NULL, "scene %d: grad is required", i);
+    SceneDev& d = P.table[i];
+    d.n_steps = outs[i].n_steps;
+    d.status = outs[i].status;
+    d.ckpt = outs[i].ckpt;
+    d.adj_dL_duv = io[i].dL_duv;
+    d.adj_dL_ddir = io[i].dL_ddir;
+    d.grad = io[i].grad;
+  }
+  return RBOS_OK;
+}
+
+// Enqueue the adjoint: scene table upload into `ws` (the caller's workspace or the
+// static scratch), tile order, adjoint kernel.
+int adjoint_enqueue(Prepared& P, int32_t n_scenes, void* ws, hipStream_t stream_h) {
+  if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
+  rbos::LaunchPlan plan{};
+  int rc = finish_launch(P, ws, stream_h, plan);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  if (plan.persistent) {
+    e = rbos::launch_tile_order(plan, stream_h);
+    if (e != hipSuccess) return fail(RBOS_E_HIP, "tile order launch failed: %s", hipGetErrorString(e));
+  }
+  e = rbos::launch_trace_adj(plan, stream_h);
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "adjoint launch failed: %s", hipGetErrorString(e));
+  return RBOS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -420,6 +462,32 @@ int rbos_field_from_temperature(int32_t nx, int32_t ny, int32_t nz, const float*
 int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, int32_t dtype, double enc_scale,
                       double enc_offset, void* field, void* stream) {
   return field_common(nx, ny, nz, delta, 0, 0.0, 0.0, dtype, enc_scale, enc_offset, field, stream);
+}
+
+// Largest power of two s with s * max |delta - c| <= 2^14 over delta in [lo, hi] (|delta - c|
+// is convex, so its maximum is at an end of the range); 1 for FP32 or a zero range.
+static double code_scale(int32_t dtype, double lo, double hi, double c) {
+  if (dtype == RBOS_F32) return 1.0;
+  if (dtype != RBOS_F16 && dtype != RBOS_BF16) return 0.0;
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !std::isfinite(c) || lo > hi) return 0.0;
+  const double m = std::max(std::fabs(lo - c), std::fabs(hi - c));
+  if (m == 0.0) return 1.0;
+  int e = 0;
+  const double f = std::frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+  return std::ldexp(1.0, (f == 0.5 ? 15 : 14) - e);
+}
+
+double rbos_code_scale(int32_t dtype, double delta_lo, double delta_hi, double enc_offset) {
+  return code_scale(dtype, delta_lo, delta_hi, enc_offset);
+}
+
+double rbos_code_scale_temperature(int32_t dtype, double T_lo, double T_hi, double rho0G, double T0,
+                                   double enc_offset) {
+  if (!(T_lo > 0.0) || !(T_hi >= T_lo) || !std::isfinite(T_hi) || !(rho0G > 0.0) || !std::isfinite(rho0G) ||
+      !(T0 > 0.0) || !std::isfinite(T0))
+    return 0.0;
+  // eta - 1 = rho0 G T0 / T decreases with T
+  return code_scale(dtype, rho0G * T0 / T_hi, rho0G * T0 / T_lo, enc_offset);
 }
 
 size_t rbos_ckpt_bytes(const rbos_scene* S) {
@@ -522,37 +590,9 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
   Prepared P;
   int rc = prepare(scenes, n_scenes, launch, workspace, ws_bytes, false, P);
   if (rc) return rc;
-  if (n_scenes > 0 && (!outs || !io)) return fail(RBOS_E_NULL, "outs or io is NULL");
-  for (int i = 0; i < n_scenes; ++i) {
-    if (scenes[i].ckpt_stride <= 0) return fail(RBOS_E_UNSUPPORTED, "scene %d: the adjoint needs ckpt_stride > 0", i);
-    if (scenes[i].ckpt_stride != scenes[0].ckpt_stride)
-      return fail(RBOS_E_UNSUPPORTED, "scene %d: all scenes of one adjoint call must share ckpt_stride", i);
-    const bool rays = scenes[i].n_pixels > 0;
-    if (rays && (!outs[i].ckpt || !outs[i].n_steps || !outs[i].status))
-      return fail(RBOS_E_NULL, "scene %d: ckpt, n_steps and status are required", i);
-    if (rays && !io[i].dL_duv) return fail(RBOS_E_NULL, "scene %d: dL_duv is required", i);
-    if (!io[i].grad) return fail(RBOS_E_NULL, "scene %d: grad is required", i);
-    SceneDev& d = P.table[i];
-    d.n_steps = outs[i].n_steps;
-    d.status = outs[i].status;
-    d.ckpt = outs[i].ckpt;
-    d.adj_dL_duv = io[i].dL_duv;
-    d.adj_dL_ddir = io[i].dL_ddir;
-    d.grad = io[i].grad;
-  }
-  if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
-  rbos::LaunchPlan plan{};
-  hipStream_t stream_h = static_cast<hipStream_t>(stream);
-  rc = finish_launch(P, workspace, stream_h, plan);
+  rc = adjoint_bind(P, scenes, n_scenes, outs, io);
   if (rc) return rc;
-  hipError_t e = hipSuccess;
-  if (plan.persistent) {
-    e = rbos::launch_tile_order(plan, stream_h);
-    if (e != hipSuccess) return fail(RBOS_E_HIP, "tile order launch failed: %s", hipGetErrorString(e));
-  }
-  e = rbos::launch_trace_adj(plan, stream_h);
-  if (e != hipSuccess) return fail(RBOS_E_HIP, "adjoint launch failed: %s", hipGetErrorString(e));
-  return RBOS_OK;
+  return adjoint_enqueue(P, n_scenes, workspace, static_cast<hipStream_t>(stream));
 }
 
 size_t rbos_mlp_param_count(int32_t width, int32_t depth) {

@@ -260,3 +260,27 @@ def test_pde_and_fit_validation(lib):
     nrm = (C.c_double * 5)(1, 1, 1, 1, 1)
     assert lib.rbos_mlp_fit_seed(10, C.c_void_p(0x10), C.c_void_p(0x20), nrm, C.c_void_p(0x30), C.c_void_p(0x40),
                                  None, 0, None) == -5
+
+
+def test_code_scale(lib):
+    """The library's 16-bit code scale: the largest power of two s with
+    s * max |eta - 1 - c| <= 2^14, here checked against the tests' own derivation from the
+    temperature range, and at the edges of its definition."""
+    import numpy as np
+
+    from _common import RHO0G, T0, expected_scale
+
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        T = rng.uniform(280.0, 330.0, 64).astype(np.float32)
+        for dtype, code in (("f16", L.RBOS_F16), ("bf16", L.RBOS_BF16), ("f32", L.RBOS_F32)):
+            for c in (0.0, RHO0G):
+                s = lib.rbos_code_scale_temperature(code, float(T.min()), float(T.max()), RHO0G, T0, c)
+                assert s == expected_scale(T, dtype, c), (dtype, c, s)
+    # a range whose largest |delta - c| is exactly 2^-16: s = 2^30 puts it at 2^14
+    assert lib.rbos_code_scale(L.RBOS_F16, -2.0 ** -16, 2.0 ** -17, 0.0) == 2.0 ** 30
+    assert lib.rbos_code_scale(L.RBOS_BF16, 1e-4, 1e-4, 1e-4) == 1.0  # nothing to store
+    assert lib.rbos_code_scale(L.RBOS_F32, 0.0, 1.0, 0.5) == 1.0
+    assert lib.rbos_code_scale(7, 0.0, 1.0, 0.0) == 0.0
+    assert lib.rbos_code_scale(L.RBOS_F16, 1.0, 0.0, 0.0) == 0.0
+    assert lib.rbos_code_scale_temperature(L.RBOS_F16, 0.0, 300.0, RHO0G, T0, 0.0) == 0.0

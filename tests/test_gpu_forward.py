@@ -107,7 +107,11 @@ def test_forward_room_512():
     tr = gpu_trace(w)
     err, derr, ref = _compare_forward(w, tr, max_step_mismatch=5)
     assert derr.max() < 1e-7, derr.max()
-    assert int(_np(tr.n_steps[0]).sum()) == int(ref["n_steps"].sum()) or True
+    # a ray whose step count differs (a state within rounding of a box face) moves the
+    # total by at most one step per mismatched ray
+    ns = _np(tr.n_steps[0]).astype(np.int64)
+    mism = int((ns != ref["n_steps"]).sum())
+    assert abs(int(ns.sum()) - int(ref["n_steps"].sum())) <= mism <= 5
 
 
 def test_forward_ragged_camera_and_tiles():

@@ -4,15 +4,19 @@ s a power of two and c an offset), integrated in FP32.
 Each case is compared with the oracle twice:
   * on the dequantised field (exactly the stored values): the arithmetic alone, held to
     the FP32 tolerances (exit point <= 1e-6 m, gradient rel-L2 < 1e-3);
-  * on the unquantised field: storage + arithmetic. With the ambient offset c = 2.7e-4
-    the codes hold only the plume perturbation (|eta - 1 - c| <= 1.4e-5, s = 2^30) and
-    the exit point stays within 1e-5 m (measured at 256 x 256 rays: FP16 1.7e-7 m,
-    BF16 1.2e-6 m). Without an offset (s = 2^25) the half-ulp of eta is 1.2e-7 (FP16)
-    or 9.5e-7 (BF16); this rounding noise is independent per voxel, its gradient adds a
-    random walk to the deflection, and the exit error (FP16 2.7e-5 m, BF16 1.7e-4 m,
-    roughly proportional to the half-ulp) exceeds 1e-5 m and even the RMS BOS
-    displacement (2.1e-5 m). Those two cases are held to regression bounds of about 3x
-    their measured error instead.
+  * on the unquantised field: storage + arithmetic, held to 1e-5 m at the exit point.
+
+The storage default is the ambient offset c = rho0G (eta - 1 at T0 = 293 K): the codes hold
+only the plume perturbation (|eta - 1 - c| <= 1.4e-5, s = 2^30) and the exit point stays
+within 1e-5 m (measured at 256 x 256 rays: FP16 1.7e-7 m, BF16 1.2e-6 m).
+
+Storage without an offset (c = 0, s = 2^25) does NOT meet the 1e-5 m bound and is kept only
+as a labelled non-compliant comparison: the half-ulp of eta is 1.2e-7 (FP16) or 9.5e-7
+(BF16); this rounding noise is independent per voxel, its gradient adds a random walk to
+the deflection, and the exit error (FP16 2.7e-5 m = 2.7x the bound, BF16 1.7e-4 m = 17x,
+roughly proportional to the half-ulp) exceeds even the RMS BOS displacement (2.1e-5 m).
+Those cases assert that they miss the bound (so the claim stays true) and stay below a
+regression ceiling.
 """
 
 import numpy as np
@@ -27,16 +31,18 @@ from test_gpu_forward import DEV, _np, gpu_trace
 pytestmark = pytest.mark.gpu
 
 AMBIENT = RHO0G  # eta - 1 at the ambient temperature
-CASES = [("f16", 0.0), ("f16", AMBIENT), ("bf16", 0.0), ("bf16", AMBIENT)]
-EXACT_EXIT_BOUND = {("f16", 0.0): 1e-4, ("f16", AMBIENT): 1e-5, ("bf16", 0.0): 5e-4, ("bf16", AMBIENT): 1e-5}
+EXIT_BOUND = 1e-5  # m, 16-bit storage against the exact field
+COMPLIANT = [pytest.param("f16", AMBIENT, id="f16-ambient"), pytest.param("bf16", AMBIENT, id="bf16-ambient")]
+# c = 0: (regression ceiling, measured miss factor over EXIT_BOUND)
+NONCOMPLIANT = {"f16": (1e-4, 2.7), "bf16": (5e-4, 17.0)}
+CASES = COMPLIANT + [pytest.param(d, 0.0, id=f"{d}-c0-noncompliant") for d in NONCOMPLIANT]
 
 
 def _exact_delta(T32):
     return oracle.delta_from_temperature(T32.astype(np.float64), RHO0G)
 
 
-@pytest.mark.parametrize("dtype,offset", CASES)
-def test_16bit_forward_against_dequantised_and_exact(dtype, offset):
+def _forward_errors(dtype, offset):
     w = room_workload((128, 128, 128), 256, 256, seed=2)
     tr = gpu_trace(w, dtype, None, offset)
     scale = expected_scale(w.T32, dtype, offset)
@@ -55,9 +61,27 @@ def test_16bit_forward_against_dequantised_and_exact(dtype, offset):
     e_store = exit_error(uv[ok], ex["uv"][ok])
     disp = np.sqrt((ex["duv"][ok] ** 2).sum(1))
     print(f"{dtype} c={offset:g} s={scale:g}: exit vs dequantised max {e_arith.max():.2e} m, "
-          f"vs exact max {e_store.max():.2e} m p99 {np.percentile(e_store, 99):.2e} m, "
+          f"vs exact max {e_store.max():.2e} m p99 {np.percentile(e_store, 99):.2e} m "
+          f"({e_store.max() / EXIT_BOUND:.2f}x the {EXIT_BOUND:g} m bound), "
           f"BOS displacement rms {np.sqrt((disp ** 2).mean()):.2e} m")
-    assert e_store.max() <= EXACT_EXIT_BOUND[(dtype, offset)], e_store.max()
+    return e_store.max()
+
+
+@pytest.mark.parametrize("dtype,offset", COMPLIANT)
+def test_16bit_default_storage_meets_bound(dtype, offset):
+    # the binding's default offset for 16-bit storage is the ambient one
+    f = api.Field.from_temperature(torch.full((4, 4, 4), 300.0, device=DEV), dtype)
+    assert f.offset == offset
+    assert _forward_errors(dtype, offset) <= EXIT_BOUND
+
+
+@pytest.mark.parametrize("dtype", list(NONCOMPLIANT), ids=[f"{d}-c0-noncompliant" for d in NONCOMPLIANT])
+def test_16bit_without_offset_misses_bound(dtype):
+    """Non-compliant comparison: c = 0 storage misses the 1e-5 m bound (by the factor in
+    NONCOMPLIANT, measured); it is selectable but never the default."""
+    ceiling, factor = NONCOMPLIANT[dtype]
+    e = _forward_errors(dtype, 0.0)
+    assert EXIT_BOUND < e <= ceiling, (e, factor)
 
 
 @pytest.mark.parametrize("dtype,offset", CASES)

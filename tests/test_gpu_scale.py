@@ -130,20 +130,25 @@ def test_room32_full_image_adjoint():
     assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
 
 
-def test_room256_fp16_subsample():
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_room256_16bit_ambient_subsample(dtype):
+    """The 256 x 256 x 192 room, 2048 x 1536 rays, <= 1024 steps, with the default 16-bit
+    storage (ambient offset): exits within 1e-6 m of the oracle on the dequantised field and
+    within 1e-5 m on the exact field, gradient within 1e-3, on a seeded 4096-ray subsample."""
     fwd, adj, _ = _bench_launches()
     desc = bi.scene_room_256_3m()
     lo, hi = desc.box_lo, desc.box_hi
     T = bi.temperature_grid(bi.plumes_room(5, lo, hi), lo, hi, desc.dims).astype(np.float32)
     w = Workload(desc, T, bi.blurred_noise(12, (desc.pat_h, desc.pat_w)))
-    tr, field = _tracer(w, fwd, adj, "f16", RHO0G, ckpt=False)
+    print(f"room256 {dtype} ambient subsample", flush=True)
+    tr, field = _tracer(w, fwd, adj, dtype, RHO0G, ckpt=False)
     tr.forward()
     uv, ns = _np(tr.uv[0]), _np(tr.n_steps[0])
     ids = bi.pixel_subset(desc.width * desc.height, 4096, 15)
     w.pixel_ids = ids
-    scale = expected_scale(T, "f16", RHO0G)
+    scale = expected_scale(T, dtype, RHO0G)
     assert field.scale == scale
-    F, ref = oracle_forward(w, stored_delta(T, "f16", scale, RHO0G))
+    F, ref = oracle_forward(w, stored_delta(T, dtype, scale, RHO0G))
     ok = np.isfinite(ref["uv"][:, 0])
     assert np.array_equal(ok, np.isfinite(uv[ids, 0]))
     assert (ns[ids] != ref["n_steps"]).sum() <= 1
@@ -154,7 +159,7 @@ def test_room256_fp16_subsample():
 
     rng = np.random.default_rng(16)
     lam = rng.standard_normal((len(ids), 2)).astype(np.float32)
-    trs, _ = _tracer(w, fwd, adj, "f16", RHO0G, ids=ids)
+    trs, _ = _tracer(w, fwd, adj, dtype, RHO0G, ids=ids)
     trs.forward()
     g = _np(trs.adjoint(dL_duv=[torch.from_numpy(lam).to(DEV)])[0])
     g_ref = oracle.adjoint(F, desc, lam.astype(np.float64), ids)
