@@ -263,6 +263,22 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
                        const rbos_adjoint_io* io, const rbos_launch* launch, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture, tight
+   serving loops, harnesses that forbid hipMalloc): rbos_trace_adjoint without a
+   workspace argument. Same arguments, results and errors otherwise. The scene table,
+   queue counters, per-tile step counts and tile order live in a static device array of
+   RBOS_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on until the
+   process ends (its address is looked up once per device, on the first call with that
+   device current). Calls whose scenes need more than that (rbos_workspace_bytes-sized
+   layout for the given launch) return RBOS_E_WORKSPACE before anything is enqueued. The
+   array is shared by every call on one device and keeps the last call's contents (each
+   call re-initialises what it reads): calls that overlap in time on one device, on any
+   streams or threads, race and must be serialised by the caller. No device memory is
+   allocated or freed. */
+#define RBOS_NOALLOC_SCRATCH_BYTES (4u << 20)
+int rbos_trace_adjoint_noalloc(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                               const rbos_adjoint_io* io, const rbos_launch* launch, void* stream);
+
 /* --- Sec. 2.D: the network field ---------------------------------------------------- */
 
 /* The temperature, pressure and velocity are one MLP of the position (Sec. 2.D):

@@ -13,6 +13,7 @@ D3 = C.c_double * 3
 RBOS_F32, RBOS_F16, RBOS_BF16 = 0, 1, 2
 RBOS_WALL_PRINTED, RBOS_WALL_PROJECTOR = 0, 1
 RBOS_TRACER_NONLINEAR, RBOS_TRACER_QUASILINEAR = 0, 1
+NOALLOC_SCRATCH_BYTES = 4 << 20  # RBOS_NOALLOC_SCRATCH_BYTES
 RAY_MISSED_BOX, RAY_TRUNCATED, RAY_NO_WALL_HIT, RAY_NONFINITE, RAY_OFF_PATTERN = 1, 2, 4, 8, 16
 
 STATUS = {
@@ -75,7 +76,7 @@ STRUCTS = [rbos_scene, rbos_trace_out, rbos_render_io, rbos_adjoint_io, rbos_lau
 EXPORTS = [
     "rbos_version", "rbos_last_error", "rbos_field_bytes", "rbos_field_from_temperature",
     "rbos_field_encode", "rbos_code_scale", "rbos_code_scale_temperature", "rbos_ckpt_bytes", "rbos_workspace_bytes", "rbos_trace_forward",
-    "rbos_render", "rbos_trace_adjoint", "rbos_struct_layout",
+    "rbos_render", "rbos_trace_adjoint", "rbos_trace_adjoint_noalloc", "rbos_struct_layout",
     "rbos_mlp_param_count", "rbos_mlp_workspace_bytes", "rbos_mlp_forward", "rbos_mlp_backward", "rbos_mlp_bos_seed",
     "rbos_mlp_fit_workspace_bytes", "rbos_mlp_fit_seed", "rbos_mlp_pde_workspace_bytes", "rbos_mlp_pde_loss",
 ]
@@ -117,6 +118,8 @@ def load(path: str = LIB_PATH):
                          P, SZ, P], C.c_int),
         "rbos_trace_adjoint": ([C.POINTER(rbos_scene), I32, C.POINTER(rbos_trace_out),
                                 C.POINTER(rbos_adjoint_io), C.POINTER(rbos_launch), P, SZ, P], C.c_int),
+        "rbos_trace_adjoint_noalloc": ([C.POINTER(rbos_scene), I32, C.POINTER(rbos_trace_out),
+                                        C.POINTER(rbos_adjoint_io), C.POINTER(rbos_launch), P], C.c_int),
         "rbos_struct_layout": ([I32, C.POINTER(C.c_size_t), I32], SZ),
         "rbos_mlp_param_count": ([I32, I32], SZ),
         "rbos_mlp_workspace_bytes": ([I32, I32, C.c_int64], SZ),

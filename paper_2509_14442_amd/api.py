@@ -279,10 +279,11 @@ class Tracer:
 
     def adjoint(self, grads: Optional[List[torch.Tensor]] = None, dL_duv: Optional[List[torch.Tensor]] = None,
                 zero: bool = True, stream=None,
-                dL_ddir: Optional[List[Optional[torch.Tensor]]] = None) -> List[torch.Tensor]:
+                dL_ddir: Optional[List[Optional[torch.Tensor]]] = None, noalloc: bool = False) -> List[torch.Tensor]:
         """dL/d(eta - 1) per scene (float64 [nz][ny][nx]); accumulates into `grads` if given.
         Without explicit per-ray seeds, uses the last render's dL/d(u, v) (and, with the
-        radiometric weight, dL/d(direction))."""
+        radiometric weight, dL/d(direction)). noalloc: call rbos_trace_adjoint_noalloc, which
+        keeps its scratch in the library's static device array instead of the workspace."""
         dev = self.workspace.device
         if dL_duv is None:
             dL = self.dL_duv
@@ -306,8 +307,12 @@ class Tracer:
                 dd = dd.to(device=dev, dtype=torch.float32).contiguous()
                 keep.append(dd)
             io[i].dL_ddir = _ptr(dd)
-        L.check(lib().rbos_trace_adjoint(self._arr, self.n, self._outs, io, self._adjoint_launch_ptr(),
-                                         _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
+        if noalloc:
+            L.check(lib().rbos_trace_adjoint_noalloc(self._arr, self.n, self._outs, io, self._adjoint_launch_ptr(),
+                                                     _stream(stream)))
+        else:
+            L.check(lib().rbos_trace_adjoint(self._arr, self.n, self._outs, io, self._adjoint_launch_ptr(),
+                                             _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
         self._keep_adj = keep
         return grads
 

@@ -9,6 +9,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -423,6 +424,36 @@ int adjoint_enqueue(Prepared& P, int32_t n_scenes, void* ws, hipStream_t stream_
   return RBOS_OK;
 }
 
+// Device scratch of rbos_trace_adjoint_noalloc (scene table, queue counters, per-tile
+// step counts and tile order), for callers that cannot allocate. Each device holds its
+// own copy at its own address: host code takes that address from hipGetSymbolAddress,
+// once per device, and never uses the array's name as a device pointer.
+constexpr size_t NOALLOC_SCRATCH_BYTES = RBOS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+
+// Device address of `scratch` on the current device, looked up on the first call per
+// device (with that device current) and kept.
+int noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static void* addr[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(RBOS_E_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RBOS_E_UNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RBOS_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return RBOS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -593,6 +624,28 @@ int rbos_trace_adjoint(const rbos_scene* scenes, int32_t n_scenes, const rbos_tr
   rc = adjoint_bind(P, scenes, n_scenes, outs, io);
   if (rc) return rc;
   return adjoint_enqueue(P, n_scenes, workspace, static_cast<hipStream_t>(stream));
+}
+
+int rbos_trace_adjoint_noalloc(const rbos_scene* scenes, int32_t n_scenes, const rbos_trace_out* outs,
+                               const rbos_adjoint_io* io, const rbos_launch* launch, void* stream) {
+  g_err.clear();
+  Prepared P;
+  // host validation against the scratch size first (no device call): the workspace
+  // pointer given here is only checked for alignment and never dereferenced
+  int rc = prepare(scenes, n_scenes, launch, reinterpret_cast<void*>(uintptr_t{256}), NOALLOC_SCRATCH_BYTES, false, P);
+  if (rc == RBOS_E_WORKSPACE)
+    return fail(RBOS_E_WORKSPACE,
+                "rbos_trace_adjoint_noalloc: these scenes need %zu bytes of device scratch, the static buffer "
+                "holds %zu (use rbos_trace_adjoint with a workspace)",
+                P.Y.total, NOALLOC_SCRATCH_BYTES);
+  if (rc) return rc;
+  rc = adjoint_bind(P, scenes, n_scenes, outs, io);
+  if (rc) return rc;
+  if (n_scenes == 0 || P.Y.total_tiles == 0) return RBOS_OK;
+  void* scratch_dev = nullptr;
+  rc = noalloc_scratch(&scratch_dev);
+  if (rc) return rc;
+  return adjoint_enqueue(P, n_scenes, scratch_dev, static_cast<hipStream_t>(stream));
 }
 
 size_t rbos_mlp_param_count(int32_t width, int32_t depth) {

@@ -262,6 +262,28 @@ def test_pde_and_fit_validation(lib):
                                  None, 0, None) == -5
 
 
+def test_adjoint_noalloc_validation(lib):
+    """The no-allocation adjoint checks its arguments like rbos_trace_adjoint, and rejects
+    scenes whose scratch exceeds the static device array, all before any device call."""
+    outs = L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0x7000)
+    aio = L.rbos_adjoint_io(0xa000, 0xb000)
+    s = _valid_scene()
+    s.ckpt_stride = 0
+    assert lib.rbos_trace_adjoint_noalloc(C.byref(s), 1, C.byref(outs), C.byref(aio), None, None) == -7
+    s.ckpt_stride = 16
+    bad = L.rbos_adjoint_io(0xa000, None)
+    assert lib.rbos_trace_adjoint_noalloc(C.byref(s), 1, C.byref(outs), C.byref(bad), None, None) == -1
+    # 2048 x 2048 pixels x 64 samples: 4M tiles, 8 B of step count and order each
+    s.width = s.height = 2048
+    s.n_pixels = 2048 * 2048
+    s.spp = 64
+    rc = lib.rbos_trace_adjoint_noalloc(C.byref(s), 1, C.byref(outs), C.byref(aio), None, None)
+    msg = lib.rbos_last_error().decode()
+    assert rc == -5 and "static buffer" in msg and str(L.NOALLOC_SCRATCH_BYTES) in msg, msg
+    # nothing to do: no device call either
+    assert lib.rbos_trace_adjoint_noalloc(C.byref(s), 0, C.byref(outs), C.byref(aio), None, None) == 0
+
+
 def test_code_scale(lib):
     """The library's 16-bit code scale: the largest power of two s with
     s * max |eta - 1 - c| <= 2^14, here checked against the tests' own derivation from the
