@@ -33,11 +33,15 @@ if ROOT not in sys.path:
 
 METRIC = "ray-steps/s fwd and fwd+adjoint (128^3 field, 1M rays) vs FP64 err; % HBM/L2"
 
-# Algorithmic FP32 work per ray-step (flops, FMA = 2), counted from the operations of one
-# Sharma step (3 trilinear samples with gradient, stage arithmetic) and of its reverse
-# (replay, 3 samples with second derivatives and their reverse).
+# Algorithmic FP32 work per ray-step (flops, FMA = 2): one Sharma step (3 trilinear samples
+# with gradient, 4 force flops each, stage arithmetic) ~200; its reverse with the replay of
+# the step ~600 (the method's work, whatever an implementation recomputes).
 FLOP_FWD_STEP = 200
-FLOP_ADJ_STEP = 700
+FLOP_ADJ_STEP = 600
+# Field values gathered per ray-step: 24 by the forward (3 samples of 8 corners), 48 by the
+# adjoint (the replay's 24 and the reverse's 24), at 4 bytes (FP32) or 2 (16-bit codes).
+GATHER_FWD_STEP = 24
+GATHER_ADJ_STEP = 48
 # Quasi-linear: 2 samples per step (a step's end point starts the next), and an adjoint
 # without replay (2 samples with second derivatives and their reverse per step).
 FLOP_FWD_STEP_QL = 150
@@ -87,6 +91,9 @@ def parse(argv=None):
                    help="summary of the FETCH_SIZE / WRITE_SIZE counter runs of the adjoint kernel")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
+    p.add_argument("--ceilings", action="store_true",
+                   help="only measure the gather, FMA, FP64-atomic and HBM-copy ceilings and print them")
+    p.add_argument("--no-ceilings", action="store_true", help="skip the live ceiling measurement")
     return p.parse_args(argv)
 
 
@@ -321,6 +328,14 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.ceilings:
+        import torch
+
+        from paper_2509_14442_amd import ceilings
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"ceilings": ceilings.measure("cuda:0")}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -396,20 +411,31 @@ def main():
     k_ms = acc / args.steps
     mlp_info = mlp_timing(args, W, cur) if W.mlp is not None else None
     fwd_ms = 0.0
+    fwd_kernel_ms = 0.0
     for _ in range(args.steps):
         ev[0].record(cur)
         W.fwd_only.forward()
-        W.fwd_only.render(W.targets)
         ev[1].record(cur)
+        W.fwd_only.render(W.targets)
+        ev[2].record(cur)
         torch.cuda.synchronize()
-        fwd_ms += ev[0].elapsed_time(ev[1])
+        fwd_kernel_ms += ev[0].elapsed_time(ev[1])
+        fwd_ms += ev[0].elapsed_time(ev[2])
     fwd_ms /= args.steps
+    fwd_kernel_ms /= args.steps
     assert int(sum(int(n.sum(dtype=torch.int64)) for n in W.fwd_only.n_steps)) == ray_steps
 
     adj_s = k_ms[4] * 1e-3
-    flop_adj = FLOP_ADJ_STEP_QL if args.tracer == "quasilinear" else FLOP_ADJ_STEP
+    ql = args.tracer == "quasilinear"
+    flop_adj = FLOP_ADJ_STEP_QL if ql else FLOP_ADJ_STEP
+    flop_fwd = FLOP_FWD_STEP_QL if ql else FLOP_FWD_STEP
     achieved = flop_adj * ray_steps / adj_s / 1e12
     traffic = read_traffic(args.traffic, args, W)
+    ceil = None
+    if not args.no_ceilings:
+        from paper_2509_14442_amd import ceilings
+
+        ceil = ceilings.measure(dev)
     n_rays = sum(s.n_rays for s in W.scenes)
     names = {
         "room1m": "128^3 room field (4x4x3 m, seeded plumes + 0.5 K/m), 1024x1024 rays, Sharma RK4 h=0.5 voxel, "
@@ -445,6 +471,7 @@ def main():
         "loss": loss,
         "fwd_ray_steps_per_s": ray_steps / (fwd_ms * 1e-3),
         "fwd_ms": fwd_ms,
+        "fwd_kernel_ms": fwd_kernel_ms,
         "kernel_ms": {("mlp_forward_and_encode" if W.mlp is not None else "field_encode"): k_ms[0],
                       "trace_fwd_ckpt": k_ms[1], "render_loss": k_ms[2], "grad_zero": k_ms[3],
                       "trace_adjoint": k_ms[4], **({"mlp_backward_all_losses": k_ms[5]} if W.mlp is not None else {})},
@@ -460,7 +487,32 @@ def main():
             "hbm_frac": None if traffic is None else traffic / adj_s / PEAK_HBM_BYTES_PER_S,
             "flop_per_ray_step": flop_adj,
         },
+        "roofline_fwd": {
+            "kernel": "k_trace_fwd (forward, no checkpoints)",
+            "bound": "alu",
+            "achieved": flop_fwd * ray_steps / (fwd_kernel_ms * 1e-3) / 1e12,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": flop_fwd * ray_steps / (fwd_kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "flop_per_ray_step": flop_fwd,
+        },
     }
+    if ceil is not None:
+        vb = 4 if args.dtype == "f32" else 2
+        gathers = {"roofline": (GATHER_ADJ_STEP, adj_s), "roofline_fwd": (GATHER_FWD_STEP, fwd_kernel_ms * 1e-3)}
+        cg = ceil["gather_coherent_f32_tbps" if vb == 4 else "gather_coherent_16bit_tbps"]
+        for key, (vals, t) in gathers.items():
+            r = out[key]
+            r["fma_ceiling_tflops"] = ceil["fma_fp32_tflops"]
+            r["frac_of_fma_ceiling"] = r["achieved"] / ceil["fma_fp32_tflops"]
+            # field values delivered to the lanes (algorithmic gather bytes) against the
+            # coherent-gather ceiling measured on the same record layout and ray pattern
+            if args.tracer == "nonlinear" or key == "roofline_fwd":
+                per_step = (vals if not ql else 16) * vb
+                got = per_step * ray_steps / t / 1e12
+                r["vl1d"] = {"bytes_per_ray_step": per_step, "achieved_tbps": got, "ceiling_tbps": cg,
+                             "frac": got / cg}
+        out["ceilings"] = ceil
     if hasattr(W, "tuned"):
         out["config"]["autotune"] = W.tuned
     if mlp_info is not None:

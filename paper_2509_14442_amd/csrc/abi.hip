@@ -118,9 +118,10 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
     return fail(RBOS_E_RANGE, "scene %d: max_steps must be in [1, 65536]", idx);
   if (S->tracer != RBOS_TRACER_NONLINEAR && S->tracer != RBOS_TRACER_QUASILINEAR)
     return fail(RBOS_E_RANGE, "scene %d: tracer must be RBOS_TRACER_NONLINEAR or RBOS_TRACER_QUASILINEAR", idx);
-  if (S->ckpt_stride != 0 && S->ckpt_stride != 1 && S->ckpt_stride != 6 &&
-      !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
-    return fail(RBOS_E_UNSUPPORTED, "scene %d: ckpt_stride must be 0, 1, 6 or a multiple of 8 up to 256 (got %d)", idx,
+  if (S->ckpt_stride != 0 && S->ckpt_stride != 1 && S->ckpt_stride != 3 && S->ckpt_stride != 4 &&
+      S->ckpt_stride != 6 && !(S->ckpt_stride % 8 == 0 && S->ckpt_stride <= 256 && S->ckpt_stride > 0))
+    return fail(RBOS_E_UNSUPPORTED,
+                "scene %d: ckpt_stride must be 0, 1, 3, 4, 6 or a multiple of 8 up to 256 (got %d)", idx,
                 S->ckpt_stride);
   if (need_render) {
     if (!S->pattern) return fail(RBOS_E_NULL, "scene %d: pattern is NULL", idx);
@@ -201,6 +202,17 @@ Layout layout(const rbos_scene* scenes, int n, const Launch& L) {
   return y;
 }
 
+// Reciprocal for dividing record indices r < 2^27 by d (1 <= d < 2^18): with
+// L = ceil(log2 d), k = 27 + L and m = ceil(2^k / d), floor(r / d) = (r * m) >> k, because
+// m d - 2^k < d makes the added error r (m d - 2^k) / (d 2^k) < 2^27 / 2^k <= 1 / d, less
+// than the gap to the next integer; m < 2^28 + 1 keeps r * m below 2^56.
+void rec_divisor(int d, unsigned& m, int& k) {
+  int L = 0;
+  while ((1 << L) < d) ++L;
+  k = 27 + L;
+  m = (unsigned)(((1ull << k) + (unsigned long long)d - 1) / (unsigned long long)d);
+}
+
 SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int render_block_begin) {
   SceneDev d;
   std::memset(&d, 0, sizeof d);
@@ -237,6 +249,8 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   }
   d.P0 = S->nx + 1;
   d.P01 = (S->nx + 1) * (S->ny + 1);
+  rec_divisor(d.P0, d.rec_div_m[0], d.rec_div_s[0]);
+  rec_divisor(d.P01, d.rec_div_m[1], d.rec_div_s[1]);
   d.dtype = S->dtype;
   d.field = S->field;
   d.dec = (float)dec;

@@ -127,6 +127,8 @@ struct SceneDev {
   float lo_f[3];       // box lo (m)
   float hi_bound[3];   // n + 1/2: box faces in grid units are 1/2 and n + 1/2
   float n_f[3];        // n (binary32)
+  unsigned rec_div_m[2];  // record index r (< 2^27) / P0 and / P01 as (r * m) >> s
+  int rec_div_s[2];
   df lo[3];            // box lo (m)
   df hi[3];            // box hi (m)
   df inv_vox[3];       // 1 / voxel size
@@ -463,6 +465,17 @@ __device__ __forceinline__ unsigned int cell_index(const SceneDev& S, const Cell
   return (unsigned)C.p[0] + __umul24((unsigned)C.p[1], (unsigned)S.P0) + __umul24((unsigned)C.p[2], (unsigned)S.P01);
 }
 
+// Padded cell indices (p0, p1, p2) of record r: the inverse of cell_index, with the two
+// divisions done as a multiply by a host-computed reciprocal and a shift (exact for
+// r < 2^27, see the ABI).
+__device__ __forceinline__ void cell_of_record(const SceneDev& S, unsigned r, int p[3]) {
+  const unsigned t = (unsigned)(((unsigned long long)r * S.rec_div_m[0]) >> S.rec_div_s[0]);  // r / P0
+  const unsigned z = (unsigned)(((unsigned long long)r * S.rec_div_m[1]) >> S.rec_div_s[1]);  // r / P01
+  p[0] = (int)(r - t * (unsigned)S.P0);
+  p[1] = (int)(t - z * (unsigned)(S.n[1] + 1));
+  p[2] = (int)z;
+}
+
 // Trilinear value q and its grid-unit gradient from the 8 corners.
 __device__ __forceinline__ void trilinear(const float c[8], const float f[3], float& q, float g[3]) {
   float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
@@ -497,17 +510,42 @@ __device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], 
   H[2] = e1 - e0;                  // d2q / dy dz
 }
 
-// Grid-unit force of Eq. (1) at a located point: K_a = (1 + delta) d(delta)/du_a / voxel_a^2.
-template <int DT>
-__device__ __forceinline__ void force_at(const SceneDev& S, const Cell& C, float K[3]) {
-  float c[8];
-  fetch_cell<DT>(S.field, cell_index(S, C), c);
+// Grid-unit force of Eq. (1) from a cell's corner codes and the fractions:
+// K_a = (1 + delta) d(delta)/du_a / voxel_a^2.
+__device__ __forceinline__ void force_of(const SceneDev& S, const float c[8], const float f[3], float K[3]) {
   float q, g[3];
-  trilinear(c, C.f, q, g);
+  trilinear(c, f, q, g);
   float eta = fmaf(q, S.dec, S.one_plus_off);
 #pragma unroll
   for (int a = 0; a < 3; ++a) K[a] = eta * (g[a] * S.km[a]);
 }
+
+template <int DT>
+__device__ __forceinline__ void force_at_rec(const SceneDev& S, unsigned rec, const float f[3], float K[3]) {
+  float c[8];
+  fetch_cell<DT>(S.field, rec, c);
+  force_of(S, c, f, K);
+}
+
+template <int DT>
+__device__ __forceinline__ void force_at(const SceneDev& S, const Cell& C, float K[3]) {
+  force_at_rec<DT>(S, cell_index(S, C), C.f, K);
+}
+
+// Sample recorder of sharma_step: called with the stage (0, 1, 2 for P1, P2, P3), the
+// record index and the located cell of each of a step's three samples. The forward pass
+// records nothing; the adjoint's replay keeps them for the reverse sweep.
+struct NoRecord {
+  __device__ __forceinline__ void operator()(int, unsigned, const Cell&) const {}
+};
+
+// Work issued by sharma_step right after the gather of its first sample (the forward's
+// checkpoint stores): gfx9 counts loads and stores in one in-order counter, so stores
+// issued before that gather would be waited for with it, while stores issued after it
+// complete in the shadow of the step's arithmetic.
+struct NoIssue {
+  __device__ __forceinline__ void operator()() const {}
+};
 
 // ------------------------------------------------------------------------------------
 // ray state in grid units: position = base(t) + d, velocity = V + e, where the base is
@@ -573,10 +611,20 @@ __device__ __forceinline__ float small_part(const RayBase& B, int a, float jf, f
 //   x <- x + h v + h^2/6 (K1 + 2 K2),  v <- v + h/6 (K1 + 4 K2 + K3)
 // The base absorbs the h V part of every position. On return st holds the new state
 // and `C` the located cell of the new position (the next step's first sample).
-template <int DT>
-__device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B, State& st, Cell& C) {
+template <int DT, class Record = NoRecord, class Issue = NoIssue>
+__device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B, State& st, Cell& C,
+                                            const Record& record = Record(), const Issue& issue = Issue()) {
   float K1[3], K2[3], K3[3], bh2[3], bh3[3], sm[3];
-  force_at<DT>(S, C, K1);
+  unsigned rec = cell_index(S, C);
+  record(0, rec, C);
+  {
+    float c[8];
+    fetch_cell<DT>(S.field, rec, c);
+    __builtin_amdgcn_sched_barrier(0);
+    issue();
+    __builtin_amdgcn_sched_barrier(0);
+    force_of(S, c, C.f, K1);
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     bh2[a] = st.bh[a] + B.g2hi[a];
@@ -584,7 +632,9 @@ __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B,
     sm[a] = small_part(B, a, st.jf + 1.0f, dev);
   }
   locate3(S, bh2, sm, C);
-  force_at<DT>(S, C, K2);
+  rec = cell_index(S, C);
+  record(1, rec, C);
+  force_at_rec<DT>(S, rec, C.f, K2);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     bh3[a] = bh2[a] + B.g2hi[a];
@@ -592,7 +642,9 @@ __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B,
     sm[a] = small_part(B, a, st.jf + 2.0f, dev);
   }
   locate3(S, bh3, sm, C);
-  force_at<DT>(S, C, K3);
+  rec = cell_index(S, C);
+  record(2, rec, C);
+  force_at_rec<DT>(S, rec, C.f, K3);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float dn = st.d[a] + fmaf(S.hf, st.e[a], S.h2_6 * fmaf(2.0f, K2[a], K1[a]));

@@ -20,23 +20,28 @@ namespace rbos {
 // Everything the reverse sweep needs about one sample.
 struct SampleRev {
   float f[3];        // fraction within the cell
-  int key;           // cell_key of the cell
+  int key;           // record index of the cell (cell_index)
   float g[3], H[3];  // code-unit gradient and mixed second derivatives
   float eta;         // 1 + delta
 };
 
-__device__ __forceinline__ int cell_key(const Cell& C);
+// A sample from its cell's 8 corner codes, record index and fractions.
+__device__ __forceinline__ void sample_rev_at(const SceneDev& S, const float c[8], unsigned rec, const float f[3],
+                                              SampleRev& R) {
+  float q;
+  trilinear_h(c, f, q, R.g, R.H);
+  R.eta = fmaf(q, S.dec, S.one_plus_off);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) R.f[a] = f[a];
+  R.key = (int)rec;
+}
 
 template <int DT>
 __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, SampleRev& R) {
   float c[8];
-  fetch_cell<DT>(S.field, cell_index(S, C), c);
-  float q;
-  trilinear_h(c, C.f, q, R.g, R.H);
-  R.eta = fmaf(q, S.dec, S.one_plus_off);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) R.f[a] = C.f[a];
-  R.key = cell_key(C);
+  const unsigned rec = cell_index(S, C);
+  fetch_cell<DT>(S.field, rec, c);
+  sample_rev_at(S, c, rec, C.f, R);
 }
 
 // Reverse of K = force(P) for an adjoint v = dL/dK: returns p = dL/dP (grid units) and
@@ -80,12 +85,8 @@ constexpr int CELL_NONE = INT_MIN;
 
 struct Accum {
   float acc[8];
-  int key;  // packed (k+1, j+1, i+1) of the cell's lower corner, CELL_NONE when empty
+  int key;  // record index of the cell (< 2^27), CELL_NONE when empty
 };
-
-__device__ __forceinline__ int cell_key(const Cell& C) {
-  return (C.p[2] << 20) | (C.p[1] << 10) | C.p[0];
-}
 
 // Sum 8 per-lane values over the 64 lanes, all eight at once: each exchange step halves
 // the lanes per value and keeps the values apart (permlane32 / permlane16 swaps between
@@ -133,10 +134,12 @@ struct Pending {
 };
 
 __device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, int c) {
+  int p[3];
+  cell_of_record(S, (unsigned)key, p);
   // apron corners map to the edge voxel they repeat
-  const int x = min(max((key & 1023) - 1 + (c & 1), 0), S.n[0] - 1);
-  const int y = min(max(((key >> 10) & 1023) - 1 + ((c >> 1) & 1), 0), S.n[1] - 1);
-  const int z = min(max((key >> 20) - 1 + (c >> 2), 0), S.n[2] - 1);
+  const int x = min(max(p[0] - 1 + (c & 1), 0), S.n[0] - 1);
+  const int y = min(max(p[1] - 1 + ((c >> 1) & 1), 0), S.n[1] - 1);
+  const int z = min(max(p[2] - 1 + (c >> 2), 0), S.n[2] - 1);
   return &S.grad[((size_t)z * S.n[1] + y) * S.n[0] + x];
 }
 
@@ -207,20 +210,19 @@ __device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lan
   P.touched = 0;
 }
 
-// Merge one sample's contributions (lanes with act) into the accumulators.
+// Merge one sample's contributions (lanes with act) into the accumulators. A lane that
+// enters a new cell restarts from its contribution: acc * 0 + ct (exactly ct, the
+// accumulators being finite), else acc * 1 + ct (exactly acc + ct).
 __device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
                                            int lane, Pending& P) {
   const bool change = act && key != A.key;
   const bool out = change && A.key != CELL_NONE;
   if (__ballot(out)) flush(S, A, out, lane, P);
-  if (change) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
-    A.key = key;
-  }
   if (act) {
+    const float keep = change ? 0.0f : 1.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) A.acc[k] += ct[k];
+    for (int k = 0; k < 8; ++k) A.acc[k] = fmaf(A.acc[k], keep, ct[k]);
+    A.key = key;
   }
 }
 
@@ -321,7 +323,7 @@ __device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, 
     const float X[2] = {1.0f - C0.f[0], C0.f[0]}, Y[2] = {1.0f - C0.f[1], C0.f[1]}, Z[2] = {1.0f - C0.f[2], C0.f[2]};
 #pragma unroll
     for (int k = 0; k < 8; ++k) c0v[k] = kap * (X[k & 1] * Y[(k >> 1) & 1] * Z[k >> 2]);
-    key0 = cell_key(C0);
+    key0 = (int)cell_index(S, C0);
   }
   accumulate(S, A, active, key0, c0v, lane, P);
 }
@@ -458,7 +460,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             rs[a] = rb[a] + p[a];
             ts[a] = fmaf(h, rb[a], tb[a]) + h * p[a];
           }
-          key = cell_key(Q3);
+          key = R3.key;
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
@@ -501,6 +503,192 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   entry_term(S, B, V0, active, tb, A, P, lane);
   flush(S, A, A.key != CELL_NONE, lane, P);
   if (P.occupied) write_out(S, P, P.occupied, lane);
+}
+
+// Recording form (checkpoint strides that are multiples of KS = 3 or 4): the replay of a
+// chunk keeps, for each of its steps, the record index and fractions of the step's three
+// samples as the forward located them (16 bytes per sample and lane in LDS, sample s of
+// step i of lane l at [(i * 3 + s) * 64 + l]). The reverse of a step then reads them back,
+// issues its three cell gathers together and evaluates value, gradient and mixed second
+// derivatives at exactly the forward's cells and fractions, without relocating the
+// samples from the state (no stage points, no K1 / K2, no dependent gathers).
+template <int KS>
+constexpr int rec_floats_per_wave() { return KS * 3 * 64 * 4 + PEND_SLOTS * 8; }
+
+template <int DT, int KS>
+__device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, int lane, float* __restrict__ lds) {
+  AdjRay R;
+  adjoint_ray_setup(S, tile, lane, R);
+  const int q = R.q, n = R.n;
+  const bool active = R.active;
+  const RayBase& B = R.B;
+  float* rb = R.rb;
+  float* tb = R.tb;
+  const int K = S.ckpt_k;  // a multiple of KS
+  const int m_chunks = K / KS;
+  const int nseg = wave_max_nonneg(active ? (n + K - 1) / K : 0);
+
+  Accum A;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
+  A.key = CELL_NONE;
+  Pending P{lds + KS * 3 * 64 * 4, CELL_NONE, 0, 0ull, 0ull};
+  f32x4* smp = reinterpret_cast<f32x4*>(lds);
+  const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6;
+
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    for (int ch = m_chunks - 1; ch >= 0; --ch) {
+      const int c0 = seg * K + ch * KS;  // first step of the chunk
+      const bool lane_chunk = active && c0 < n;
+      if (lane_chunk) {
+        State st;
+        Cell C;
+        state_at_step(B, seg * K, st);
+        if (seg == 0) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
+        } else {
+          load_ckpt(S, q, seg - 1, st);
+        }
+        locate_state(S, B, st, C);
+#pragma unroll 1
+        for (int i = 0; i < ch * KS; ++i) sharma_step<DT>(S, B, st, C);  // to the chunk start
+#pragma unroll 1
+        for (int i = 0; i < KS && c0 + i < n; ++i) {
+          f32x4* row = smp + i * 3 * 64 + lane;
+          sharma_step<DT>(S, B, st, C, [row](int stage, unsigned rec, const Cell& Cs) {
+            row[stage * 64] = f32x4{__uint_as_float(rec), Cs.f[0], Cs.f[1], Cs.f[2]};
+          });
+        }
+      }
+      // reverse the chunk's steps, one stage at a time (C, B, A)
+#pragma unroll 1
+      for (int i = KS - 1; i >= 0; --i) {
+        const bool act = lane_chunk && (c0 + i < n);
+        SampleRev R1, R2, R3;
+        float ab[3], bb[3], rs[3], ts[3], ct[8];
+        int key = 0;
+        if (act) {
+          const f32x4* row = smp + i * 3 * 64 + lane;
+          const f32x4 s1 = row[0], s2 = row[64], s3 = row[128];
+          const unsigned r1 = __float_as_uint(s1.x), r2 = __float_as_uint(s2.x), r3 = __float_as_uint(s3.x);
+          float c1[8], c2[8], c3[8];
+          fetch_cell<DT>(S.field, r3, c3);
+          fetch_cell<DT>(S.field, r2, c2);
+          fetch_cell<DT>(S.field, r1, c1);
+          const float f3[3] = {s3.y, s3.z, s3.w}, f2[3] = {s2.y, s2.z, s2.w}, f1[3] = {s1.y, s1.z, s1.w};
+          sample_rev_at(S, c3, r3, f3, R3);
+          sample_rev_at(S, c2, r2, f2, R2);
+          sample_rev_at(S, c1, r1, f1, R1);
+          // stage C = h K3: adjoint v = h dL/dC
+          float v[3], p[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            ab[a] = fmaf(h_6, rb[a], tb[a] * (1.0f / 6.0f));
+            bb[a] = fmaf(h * (1.0f / 3.0f), rb[a], tb[a] * (2.0f / 3.0f));
+            v[a] = h * (tb[a] * (1.0f / 6.0f));
+          }
+          force_rev(S, R3, v, p, ct);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            bb[a] = fmaf(h_2, p[a], bb[a]);
+            rs[a] = rb[a] + p[a];
+            ts[a] = fmaf(h, rb[a], tb[a]) + h * p[a];
+          }
+          key = R3.key;
+        }
+        accumulate(S, A, act, key, ct, lane, P);
+        if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
+          float v[3], p[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) v[a] = h * bb[a];
+          force_rev(S, R2, v, p, ct);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            ab[a] = fmaf(h * 0.125f, p[a], ab[a]);
+            rs[a] += p[a];
+            ts[a] = fmaf(h_2, p[a], ts[a]);
+          }
+          key = R2.key;
+        }
+        accumulate(S, A, act, key, ct, lane, P);
+        if (act) {  // stage A = h K1, P1 = x
+          float v[3], p[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) v[a] = h * ab[a];
+          force_rev(S, R1, v, p, ct);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            rb[a] = rs[a] + p[a];
+            tb[a] = ts[a];
+          }
+          key = R1.key;
+        }
+        accumulate(S, A, act, key, ct, lane, P);
+      }
+      chunk_end(S, P, lane);
+    }
+  }
+  float V0[3] = {0.0f, 0.0f, 0.0f};
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) V0[a] = gld(S.ckpt + (size_t)q + (size_t)(12 + a) * (size_t)S.ckpt_pad);
+  }
+  entry_term(S, B, V0, active, tb, A, P, lane);
+  flush(S, A, A.key != CELL_NONE, lane, P);
+  if (P.occupied) write_out(S, P, P.occupied, lane);
+}
+
+template <int DT, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 3 ? 4 : 3))) void k_trace_adj_rec(
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, int wpb, int nblocks) {
+  const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
+  if (gtile >= total_tiles) return;  // whole wavefront
+  const int si = find_scene(scenes, n_scenes, gtile);
+  const SceneDev& S = scenes[si];
+  extern __shared__ float lds[];
+  adjoint_tile_rec<DT, KS>(S, gtile - S.tile_begin, lane, lds + wave * rec_floats_per_wave<KS>());
+}
+
+template <int DT, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 3 ? 4 : 3))) void k_trace_adj_rec_persistent(
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, unsigned int* __restrict__ queues,
+    const int* __restrict__ order) {
+  const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
+  const int xcd = blockIdx.x & 7;
+  extern __shared__ float lds[];
+  float* mine = lds + wave * rec_floats_per_wave<KS>();
+  for (int q = 0; q < 8; ++q) {
+    const int qx = (xcd + q) & 7;
+    int q_begin, q_end;
+    xcd_tile_range(total_tiles, qx, q_begin, q_end);
+    while (true) {
+      int t = 0;
+      if (lane == 0) t = (int)atomicAdd(&queues[8 + qx], 1u);
+      t = wave_uniform(t) + q_begin;  // lane 0's claim (all lanes active)
+      if (t >= q_end) break;
+      t = wave_uniform(gld(order + t));
+      const int si = find_scene(scenes, n_scenes, t);
+      const SceneDev& S = scenes[si];
+      adjoint_tile_rec<DT, KS>(S, t - S.tile_begin, lane, mine);
+    }
+  }
+}
+
+template <int DT, int KS>
+static hipError_t launch_adj_rec(const LaunchPlan& P, hipStream_t stream) {
+  const size_t lds = sizeof(float) * rec_floats_per_wave<KS>() * (size_t)P.wpb;
+  if (P.persistent) {
+    const int grid = persistent_grid(k_trace_adj_rec_persistent<DT, KS>, P, lds);
+    hipLaunchKernelGGL((k_trace_adj_rec_persistent<DT, KS>), dim3(grid), dim3(64 * P.wpb), lds, stream, P.scenes,
+                       P.n_scenes, P.total_tiles, P.queues, P.tile_order);
+  } else {
+    int nblocks = (P.total_tiles + P.wpb - 1) / P.wpb;
+    hipLaunchKernelGGL((k_trace_adj_rec<DT, KS>), dim3(nblocks), dim3(64 * P.wpb), lds, stream, P.scenes,
+                       P.n_scenes, P.total_tiles, P.wpb, nblocks);
+  }
+  return hipGetLastError();
 }
 
 // Quasi-linear form: the stage points lie on the entry line, at its half-step points
@@ -568,7 +756,7 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
       const float tj = jf * (0.5f * h);
 #pragma unroll
       for (int a = 0; a < 3; ++a) pv[a] = fmaf(tj, p[a], pv[a]);
-      key = cell_key(C);
+      key = Rs.key;
     }
     accumulate(S, A, act, key, ct, lane, P);
     if ((j & 15) == 15) chunk_end(S, P, lane);
@@ -696,6 +884,8 @@ static hipError_t launch_adj_dt(const LaunchPlan& P, hipStream_t stream) {
   // chunks of step-start states in LDS: stride 1 fills chunks of 8 from the checkpoints,
   // stride 6 replays chunks of 6, strides 8, 16, ... chunks of 8
   if (P.ckpt_k == 1) return launch_adj_t<DT, 8, true>(P, stream);
+  if (P.ckpt_k == 3) return launch_adj_rec<DT, 3>(P, stream);
+  if (P.ckpt_k == 4) return launch_adj_rec<DT, 4>(P, stream);
   if (P.ckpt_k == 6) return launch_adj_t<DT, 6, false>(P, stream);
   return launch_adj_t<DT, 8, false>(P, stream);
 }

@@ -40,39 +40,57 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int
     state_at_step(B, 0, st);
 #pragma unroll
     for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
-    // checkpoint slot s holds the state after (s + 1) K steps; kc counts down to the next
+    // checkpoint slot s holds the state after (s + 1) K steps
     const int q = ckpt_entry(S, r, pix, smp);
     float* ck = S.ckpt ? S.ckpt + (size_t)RAY_HEADER * S.ckpt_pad + (size_t)q : nullptr;
     const size_t slot_stride = 6 * (size_t)S.ckpt_pad;
-    int kc = S.ckpt_k;
     bool exited = false;
-    float Kc[3];  // quasi-linear: force at the current point of the entry line
-    if constexpr (QL) force_at<DT>(S, C, Kc);
-    while (n < S.max_steps) {
-      if (!QL && ck && kc == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          gst(ck + (size_t)a * S.ckpt_pad, st.d[a]);
-          gst(ck + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
-        }
-        ck += slot_stride;
-        kc = S.ckpt_k;
-      }
-      if constexpr (QL) {
-        ql_step<DT>(S, B, st, Kc);
-      } else {
-        sharma_step<DT>(S, B, st, C);
-      }
+    // after each step: count it, stop on a non-finite state or outside the box
+    auto stop = [&]() {
       ++n;
-      --kc;
       if (!state_finite(st)) {
         status |= RAY_NONFINITE;
         exited = true;
-        break;
-      }
-      if (outside_box(S, B, st)) {
+      } else if (outside_box(S, B, st)) {
         exited = true;
-        break;
+      }
+      return exited;
+    };
+    if constexpr (QL) {
+      float Kc[3];  // force at the current point of the entry line
+      force_at<DT>(S, C, Kc);
+      while (n < S.max_steps) {
+        ql_step<DT>(S, B, st, Kc);
+        if (stop()) break;
+      }
+    } else if (!ck) {
+      while (n < S.max_steps) {
+        sharma_step<DT>(S, B, st, C);
+        if (stop()) break;
+      }
+    } else {
+      // Segments of K steps; every segment after the first starts with a step whose start
+      // state is stored. That step is a copy of its own with unconditional stores, issued
+      // after its first gather (see NoIssue): in one loop with a branch around the stores,
+      // the wait for the next gather at the branch's join would have to cover them.
+      const int K = S.ckpt_k;
+      int until = min(K, S.max_steps);
+      while (!exited) {
+        while (n < until) {
+          sharma_step<DT>(S, B, st, C);
+          if (stop()) break;
+        }
+        if (exited || n >= S.max_steps) break;
+        sharma_step<DT>(S, B, st, C, NoRecord(), [&]() {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            gst(ck + (size_t)a * S.ckpt_pad, st.d[a]);
+            gst(ck + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
+          }
+        });
+        ck += slot_stride;
+        if (stop()) break;
+        until = min(n - 1 + K, S.max_steps);
       }
     }
     if (!exited) status |= RAY_TRUNCATED;
@@ -81,7 +99,7 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int
     if (!(status & RAY_NONFINITE)) {
       float dX[3], s = 0.0f;
       const bool hit = wall_deflection(S, B, st, dX, &s);
-      if (ck) store_ray_header(S, ckpt_entry(S, r, pix, smp), B, st, s);
+      if (S.ckpt) store_ray_header(S, ckpt_entry(S, r, pix, smp), B, st, s);
       if (hit) {
         uvd[0] = dX[0] * S.wall_u_f[0] + dX[1] * S.wall_u_f[1] + dX[2] * S.wall_u_f[2];
         uvd[1] = dX[0] * S.wall_v_f[0] + dX[1] * S.wall_v_f[1] + dX[2] * S.wall_v_f[2];

@@ -97,7 +97,7 @@ def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
     (lambda s: setattr(s, "step", 1.0), -3),
     (lambda s: setattr(s, "max_steps", 0), -3),
     (lambda s: setattr(s, "ckpt_stride", 12), -7),
-    (lambda s: setattr(s, "ckpt_stride", 4), -7),
+    (lambda s: setattr(s, "ckpt_stride", 5), -7),
     (lambda s: setattr(s, "tracer", 2), -3),
     (lambda s: setattr(s, "ckpt_stride", 264), -7),
 ])
@@ -115,7 +115,7 @@ def test_forward_output_and_workspace_checks(lib):
     assert rc == -1 and "wall_uv" in msg
     rc, msg = _fwd(lib, s, outs=L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0))
     assert rc == -1 and "ckpt" in msg
-    for k in (1, 6, 8, 256):  # accepted strides: the error is the missing checkpoint buffer
+    for k in (1, 3, 4, 6, 8, 256):  # accepted strides: the error is the missing checkpoint buffer
         s.ckpt_stride = k
         rc, msg = _fwd(lib, s, outs=L.rbos_trace_out(0x3000, 0x4000, 0x5000, 0x6000, 0))
         assert rc == -1 and "ckpt" in msg, (k, msg)

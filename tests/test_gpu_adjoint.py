@@ -58,7 +58,7 @@ def test_loss_and_dl_duv_unit_box():
     assert np.abs(got - dL).max() <= 1e-4 * scale
 
 
-@pytest.mark.parametrize("ckpt", [1, 6, 8, 16, 32])
+@pytest.mark.parametrize("ckpt", [1, 3, 4, 6, 8, 16, 32])
 def test_adjoint_unit_box_matches_oracle(ckpt):
     w = unit_box_workload()
     from bos_inputs import plume_unit_box, temperature_grid
@@ -86,13 +86,14 @@ def test_adjoint_room_subset_matches_oracle():
     assert frac < 5e-3, (l2, frac)
 
 
-def test_adjoint_persistent_and_tiles_agree():
+@pytest.mark.parametrize("ckpt", [16, 3, 4])
+def test_adjoint_persistent_and_tiles_agree(ckpt):
     w = room_workload((48, 40, 32), 96, 80, seed=4)
     rng = np.random.default_rng(1)
     lam = rng.standard_normal((96 * 80, 2)).astype(np.float32)
-    _, g0 = _gpu_loss_and_grad(w, np.zeros(96 * 80, np.float32), dL_duv=lam)
+    _, g0 = _gpu_loss_and_grad(w, np.zeros(96 * 80, np.float32), ckpt=ckpt, dL_duv=lam)
     for launch in (api.make_launch((8, 8), 4, persistent=True, blocks_per_cu=2), api.make_launch((16, 4), 1)):
-        _, g1 = _gpu_loss_and_grad(w, np.zeros(96 * 80, np.float32), launch=launch, dL_duv=lam)
+        _, g1 = _gpu_loss_and_grad(w, np.zeros(96 * 80, np.float32), launch=launch, ckpt=ckpt, dL_duv=lam)
         assert np.linalg.norm(g1 - g0) <= 1e-5 * np.linalg.norm(g0)
 
 

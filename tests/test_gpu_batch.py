@@ -34,8 +34,9 @@ def _run(scenes, launch, lams):
     return tr, grads
 
 
-def test_batched_equals_single_and_oracle():
-    b = _batch()
+@pytest.mark.parametrize("ckpt", [16, 3])
+def test_batched_equals_single_and_oracle(ckpt):
+    b = _batch(ckpt=ckpt)
     scenes = [s for s, _ in b]
     rng = np.random.default_rng(4)
     lams = [torch.from_numpy(rng.standard_normal((s.n_rays, 2)).astype(np.float32)).to(DEV) for s in scenes]
