@@ -57,7 +57,10 @@ def parse(argv=None):
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="room1m", choices=["room1m", "batch64", "room256"])
-    p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    p.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"], help="code type of the stored field")
+    p.add_argument("--layout", default="cell", choices=["cell", "xpair"],
+                   help="field layout: cell records (8 corner codes per cell) or x-pairs (each voxel with its +x "
+                        "neighbour)")
     p.add_argument("--tracer", default="nonlinear", choices=list(TRACERS),
                    help="nonlinear (Eq. 1 coupled) or quasi-linear (forces on the straight entry line)")
     p.add_argument("--offset", type=float, default=None,
@@ -74,7 +77,9 @@ def parse(argv=None):
     p.add_argument("--mlp-depth", type=int, default=4, help="network field: hidden layers of 64 units")
     p.add_argument("--pde-points", type=int, default=8192, help="network field: collocation points per step")
     p.add_argument("--boundary-points", type=int, default=4096, help="network field: inlet-plane points per step")
-    p.add_argument("--ckpt", type=int, default=6, help="checkpoint stride (steps): 6 replays chunks of 6 at 4 wavefronts per SIMD")
+    p.add_argument("--ckpt", type=int, default=3,
+                   help="checkpoint stride (steps) when not tuned: 3 and 4 record each chunk's samples for the "
+                        "reverse, 6 replays chunks of 6, multiples of 8 chunks of 8, 1 stores every state")
     p.add_argument("--tile", default="8x8", help="forward: rays per wavefront tile")
     p.add_argument("--wpb", type=int, default=4, help="forward: wavefronts per block")
     p.add_argument("--persistent", type=int, default=0, help="forward: persistent blocks with tile queues")
@@ -84,7 +89,9 @@ def parse(argv=None):
     p.add_argument("--adj-persistent", type=int, default=1)
     p.add_argument("--adj-blocks-per-cu", type=int, default=0)
     p.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
-    p.add_argument("--tune", type=int, default=1, help="batch64: autotune launch shape and checkpoint stride")
+    p.add_argument("--tune", type=int, default=1,
+                   help="autotune launch shapes, checkpoint stride and field layout before timing (0: use the "
+                        "command-line values)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--traffic", default=TRAFFIC_FILE,
@@ -95,6 +102,11 @@ def parse(argv=None):
                    help="only measure the gather, FMA, FP64-atomic and HBM-copy ceilings and print them")
     p.add_argument("--no-ceilings", action="store_true", help="skip the live ceiling measurement")
     return p.parse_args(argv)
+
+
+def storage(args) -> str:
+    """Storage format of the field: the code type, with "-xpair" for the x-pair layout."""
+    return args.dtype + ("-xpair" if args.layout == "xpair" else "")
 
 
 def launches(args):
@@ -133,7 +145,7 @@ def launch_desc(l) -> dict:
 def traffic_config(args, W) -> dict:
     """What the adjoint's counters depend on: workload, storage, stride and its launch."""
     l = W.adj_launch
-    return {"workload": args.workload, "tracer": args.tracer, "dtype": args.dtype,
+    return {"workload": args.workload, "tracer": args.tracer, "dtype": W.fields[0].dtype,
             "ckpt_stride": str(W.ckpt_stride), "spp": str(args.spp), "radiometry": str(args.radiometry),
             "adj_launch": "%dx%d wpb %d persistent %d bpc %d" % (l.tile_w, l.tile_h, l.waves_per_block,
                                                                  l.persistent, l.blocks_per_cu)}
@@ -194,8 +206,8 @@ class Workload:
             self.pat_np, self.TA_np, self.TB_np = pat_np, TA, TB
             pat = torch.from_numpy(pat_np).to(dev)
             tA = torch.from_numpy(TA).to(dev)
-            fA = api.Field.from_temperature(tA, args.dtype, None, args.offset)
-            fB = api.Field.from_temperature(torch.from_numpy(TB).to(dev), args.dtype, fA.scale, args.offset)
+            fA = api.Field.from_temperature(tA, storage(args), None, args.offset)
+            fB = api.Field.from_temperature(torch.from_numpy(TB).to(dev), storage(args), fA.scale, args.offset)
             trB = api.Tracer([api.Scene(desc, fB, pat)], launch, checkpoints=False)
             trB.forward().render()
             self.targets = [trB.image[0].clone()]
@@ -204,6 +216,8 @@ class Workload:
             self.scenes = [api.Scene(desc, fA, pat)]
             self.pat = pat
             self.data_note = "synthetic: seeded plume fields; target = render of a second seeded field"
+            if args.tune:
+                launch, adj_launch = self._tune(self.scenes, self.targets)
         else:  # batch64
             pat = torch.from_numpy(bi.blurred_noise(12, (1024, 1024)).astype(np.float32)).to(dev)
             self.pat = pat
@@ -212,7 +226,7 @@ class Workload:
                                 seed=args.sample_seed, radiometry=args.radiometry)
                 T = torch.from_numpy(bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32))
                 T = T.to(dev)
-                f = api.Field.from_temperature(T, args.dtype, None, args.offset)
+                f = api.Field.from_temperature(T, storage(args), None, args.offset)
                 self.temps.append(T)
                 self.fields.append(f)
                 self.descs.append(sc)
@@ -220,16 +234,9 @@ class Workload:
             self.targets = [torch.zeros(s.n_pixels, device=dev) for s in self.scenes]
             self.data_note = "synthetic: 64 seeded plume fields; target image = 0"
             if args.tune:
-                from paper_2509_14442_amd import autotune
-
                 # tune on a subset (every 8th scene), then apply to the batch
-                sub = self.scenes[::8]
-                entry = autotune.tune(sub, "fwd+adj", [self.targets[i] for i in range(0, 64, 8)], reps=1)
-                launch = autotune.launch_of(entry)
-                adj_launch = autotune.launch_of(entry, "adj")
-                for s in self.scenes:
-                    s.struct.ckpt_stride = entry["ckpt_stride"]
-                self.tuned = entry
+                launch, adj_launch = self._tune(self.scenes[::8], [self.targets[i] for i in range(0, 64, 8)],
+                                                apply_to=self.scenes)
         self.launch, self.adj_launch = launch, adj_launch
         self.ckpt_stride = int(self.scenes[0].struct.ckpt_stride)
         self.tracer = api.Tracer(self.scenes, launch, checkpoints=True, adjoint_launch=adj_launch)
@@ -238,6 +245,20 @@ class Workload:
         self.mlp = None
         if args.field == "mlp":
             self._setup_mlp(args, dev)
+
+    def _tune(self, sub, targets, apply_to=None):
+        """Autotune on `sub` (launch shapes, stride, layout) and apply the result to every
+        scene; returns the forward and adjoint launches."""
+        from paper_2509_14442_amd import autotune
+
+        entry = autotune.tune(sub, "fwd+adj", targets, reps=1 if apply_to is not None else 2)
+        for i, s in enumerate(apply_to if apply_to is not None else sub):
+            s.struct.ckpt_stride = entry["ckpt_stride"]
+            if entry["layout"] != s.field.layout:
+                s.set_field(s.field.relayout(entry["layout"]))
+                self.fields[i] = s.field
+        self.tuned = entry
+        return autotune.launch_of(entry), autotune.launch_of(entry, "adj")
 
     def _setup_mlp(self, args, dev):
         """Network field (Sec. 2.D): the voxel temperatures come from an MLP; the target
@@ -263,7 +284,7 @@ class Workload:
         self.mlp = net(3)
         target_net = net(4)
         _, TB = target_net.forward(grid=dims, want_out=False, T0=self.T0, T_in=self.T_in)
-        fB = api.Field.from_temperature(TB.reshape(tuple(reversed(dims))), args.dtype, self.fields[0].scale,
+        fB = api.Field.from_temperature(TB.reshape(tuple(reversed(dims))), storage(args), self.fields[0].scale,
                                         args.offset)
         trB = api.Tracer([api.Scene(desc, fB, self.pat)], self.launch, checkpoints=False)
         trB.forward().render()
@@ -462,7 +483,7 @@ def main():
             + (", %d rays per pixel (triangular filter)" % args.spp if args.spp > 1 else "")
             + (", radiometric weight" if args.radiometry else ""),
             "tracer": args.tracer, "spp": args.spp, "radiometry": bool(args.radiometry),
-            "storage": args.dtype, "offset": W.fields[0].offset, "ckpt_stride": W.ckpt_stride,
+            "storage": W.fields[0].dtype, "offset": W.fields[0].offset, "ckpt_stride": W.ckpt_stride,
             "fwd_launch": launch_desc(W.launch), "adj_launch": launch_desc(W.adj_launch),
             "graph": bool(args.graph),
         },
@@ -694,7 +715,7 @@ def subsample_errors(args, W):
     lam = rng.standard_normal((len(rows), 2))
     _, g = _gpu_subset(W, ids, lam)
     uv = W.tracer.uv[0].cpu().numpy().astype(np.float64)[rows]
-    out = {"sample_rays": int(len(rows)), "storage": args.dtype, "offset": f.offset, "scale": f.scale}
+    out = {"sample_rays": int(len(rows)), "storage": storage(args), "offset": f.offset, "scale": f.scale}
     exact = oracle.delta_from_temperature(W.TA_np)
     deq = _stored_delta(W.TA_np, args.dtype, f.scale, f.offset)
     for name, delta in (("vs_dequantised", deq), ("vs_exact", exact)):

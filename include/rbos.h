@@ -68,8 +68,19 @@ typedef enum {
   RBOS_E_UNSUPPORTED = -7  /* valid but unsupported option (e.g. checkpoint stride) */
 } rbos_status;
 
-/* storage type of the field codes q; eta - 1 = enc_offset + q / enc_scale */
-enum { RBOS_F32 = 0, RBOS_F16 = 1, RBOS_BF16 = 2 };
+/* storage format of the field: the type of the codes q (eta - 1 = enc_offset + q /
+   enc_scale) and their layout. RBOS_F32 / F16 / BF16 store cell records (the 8 corner
+   codes of every interpolation cell together: one load per sample, 8 copies of every
+   voxel); the *_XPAIR formats store each voxel with its +x neighbour (four loads per
+   sample, 2 copies of every voxel). See rbos_field_bytes. */
+enum {
+  RBOS_F32 = 0,
+  RBOS_F16 = 1,
+  RBOS_BF16 = 2,
+  RBOS_F32_XPAIR = 3,
+  RBOS_F16_XPAIR = 4,
+  RBOS_BF16_XPAIR = 5
+};
 
 /* back-wall luminance model (Sec. 2.C) */
 enum { RBOS_WALL_PRINTED = 0, RBOS_WALL_PROJECTOR = 1 };
@@ -98,7 +109,7 @@ typedef struct rbos_scene {
   /* field: nx*ny*nz voxels (each in [2, RBOS_MAX_DIM]) on the box [box_lo, box_hi] */
   int32_t nx, ny, nz;
   double box_lo[3], box_hi[3];
-  int32_t dtype;                 /* RBOS_F32 / RBOS_F16 / RBOS_BF16 */
+  int32_t dtype;                 /* storage format RBOS_F32 ... RBOS_BF16_XPAIR */
   double enc_scale, enc_offset;  /* eta - 1 = enc_offset + q / enc_scale; enc_scale > 0 */
   const void* field;             /* [dev] packed field from rbos_field_* (never modified) */
   /* pinhole camera: position, orthonormal forward/right/up, horizontal FOV (degrees) */
@@ -196,11 +207,15 @@ const char* rbos_last_error(void);
 
 /* --- Sec. 2.A: field storage ------------------------------------------------------- */
 
-/* Bytes of the packed field for nx*ny*nz voxels and a storage type (0 if invalid).
-   Layout: one record per interpolation cell (i, j, k), i in [-1, nx-1] etc., i.e.
-   (nx+1)(ny+1)(nz+1) records in x-fastest order starting at cell (-1, -1, -1); each
-   holds the cell's 8 corner codes (32 B for FP32, 16 B for FP16/BF16), corner indices
-   clamped to the grid (the apron cells repeat the edge voxels). */
+/* Bytes of the packed field for nx*ny*nz voxels and a storage format (0 if invalid).
+   Cell records (RBOS_F32, RBOS_F16, RBOS_BF16): one record per interpolation cell
+   (i, j, k), i in [-1, nx-1] etc., i.e. (nx+1)(ny+1)(nz+1) records in x-fastest order
+   starting at cell (-1, -1, -1); each holds the cell's 8 corner codes (32 B for FP32,
+   16 B for FP16/BF16), corner indices clamped to the grid (the apron cells repeat the
+   edge voxels). X-pairs (*_XPAIR): (nx+1)(ny+2)(nz+2) entries (i, j, k), i in [-1, nx-1],
+   j in [-1, ny], k in [-1, nz], x fastest, each holding the codes of voxels
+   (clamp(i), clamp(j), clamp(k)) and (clamp(i+1), clamp(j), clamp(k)) (8 B FP32, 4 B
+   for two 16-bit codes, low half first). */
 size_t rbos_field_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype);
 
 /* Encode eta - 1 from temperature: delta = rho0G * (T0 / T) in binary32 (two correctly

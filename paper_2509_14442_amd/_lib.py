@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "librbos.so")
 D3 = C.c_double * 3
 
 RBOS_F32, RBOS_F16, RBOS_BF16 = 0, 1, 2
+RBOS_F32_XPAIR, RBOS_F16_XPAIR, RBOS_BF16_XPAIR = 3, 4, 5
 RBOS_WALL_PRINTED, RBOS_WALL_PROJECTOR = 0, 1
 RBOS_TRACER_NONLINEAR, RBOS_TRACER_QUASILINEAR = 0, 1
 NOALLOC_SCRATCH_BYTES = 4 << 20  # RBOS_NOALLOC_SCRATCH_BYTES

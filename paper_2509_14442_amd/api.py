@@ -13,7 +13,14 @@ import torch
 
 from . import _lib as L
 
-DTYPES = {"f32": L.RBOS_F32, "f16": L.RBOS_F16, "bf16": L.RBOS_BF16}
+# storage formats: code type, then "-xpair" for the x-pair layout (cell records otherwise)
+DTYPES = {"f32": L.RBOS_F32, "f16": L.RBOS_F16, "bf16": L.RBOS_BF16,
+          "f32-xpair": L.RBOS_F32_XPAIR, "f16-xpair": L.RBOS_F16_XPAIR, "bf16-xpair": L.RBOS_BF16_XPAIR}
+
+
+def code_type(dtype: str) -> str:
+    """"f32", "f16" or "bf16": the type of the stored codes."""
+    return dtype.split("-")[0]
 RHO0G = 2.7e-4  # rho0 * G of air at the ambient state used by the synthetic workloads
 T_AMBIENT = 293.0
 
@@ -63,7 +70,7 @@ class Field:
             raise ValueError("T must be a float32 [nz][ny][nx] tensor")
         nz, ny, nx = T.shape
         if offset is None:
-            offset = 0.0 if dtype == "f32" else float(rho0G)
+            offset = 0.0 if code_type(dtype) == "f32" else float(rho0G)
         if scale is None:
             tmin, tmax = (float(x) for x in torch.aminmax(T))
             scale = lib().rbos_code_scale_temperature(DTYPES[dtype], tmin, tmax, rho0G, T0, offset)
@@ -73,6 +80,22 @@ class Field:
         f.rho0G, f.T0 = rho0G, T0
         f.encode_temperature(T, stream)
         return f
+
+    def relayout(self, layout: str, stream=None) -> "Field":
+        """A new field with the same codes in the other layout ("cell" or "xpair"), encoded
+        from the source this field was last encoded from."""
+        dtype = code_type(self.dtype) + ("-xpair" if layout == "xpair" else "")
+        f = Field(self.dims, dtype, self.scale, self.offset, self.buf.device)
+        if hasattr(self, "rho0G"):
+            f.rho0G, f.T0 = self.rho0G, self.T0
+            f.encode_temperature(self._keep, stream)
+        else:
+            f.encode(self._keep, stream)
+        return f
+
+    @property
+    def layout(self) -> str:
+        return "xpair" if self.dtype.endswith("-xpair") else "cell"
 
     def encode_temperature(self, T: torch.Tensor, stream=None):
         """Re-encode this field in place from a temperature tensor of the same shape."""
@@ -93,7 +116,7 @@ class Field:
         for that range."""
         dmin, dmax = (float(x) for x in torch.aminmax(delta))
         if offset is None:
-            offset = 0.0 if dtype == "f32" else 0.5 * (dmin + dmax)
+            offset = 0.0 if code_type(dtype) == "f32" else 0.5 * (dmin + dmax)
         if scale is None:
             scale = lib().rbos_code_scale(DTYPES[dtype], dmin, dmax, offset)
             if not scale > 0.0:

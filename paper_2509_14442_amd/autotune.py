@@ -31,7 +31,10 @@ LAUNCHES: List[Tuple[Tuple[int, int], int, bool, int]] = [
     ((8, 8), 2, True, 0),
     ((8, 8), 4, True, 2),
 ]
-STRIDES = (1, 6, 8, 16, 32)  # 1: every step stored (24 B per ray-step), no replay; 6: 4 wavefronts per SIMD
+# 1: every step stored (24 B per ray-step), no replay; 3, 4: chunks that record their
+# samples for the reverse; 6: chunks of 6 at 4 wavefronts per SIMD; 8, 16, 32: chunks of 8
+STRIDES = (1, 3, 4, 6, 8, 16, 32)
+LAYOUTS = ("cell", "xpair")
 
 
 def _bucket(x: float) -> int:
@@ -47,7 +50,7 @@ def cache_key(scenes: Sequence[api.Scene], mode: str) -> str:
     tracer = int(scenes[0].struct.tracer) if scenes else 0
     spp = max((s.spp for s in scenes), default=1)
     steps = max((int(s.struct.max_steps) for s in scenes), default=1)
-    return (f"v3|{arch}|{dtype}|t{tracer}|spp{spp}|m{_bucket(steps)}|g{_bucket(vox)}|r{_bucket(rays)}"
+    return (f"v4|{arch}|{dtype}|t{tracer}|spp{spp}|m{_bucket(steps)}|g{_bucket(vox)}|r{_bucket(rays)}"
             f"|n{len(scenes)}|{mode}")
 
 
@@ -84,16 +87,20 @@ def _entry_of(launch_t) -> Dict:
 
 
 def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[torch.Tensor]] = None,
-         strides: Sequence[int] = STRIDES, launches=LAUNCHES, hbm_budget: Optional[int] = None,
-         reps: int = 2, cache: Optional[str] = DEFAULT_CACHE, force: bool = False) -> Dict:
-    """Pick launch shapes and the checkpoint stride for these scenes; returns the cached or
-    new entry {"fwd": launch, "adj": launch, "ckpt_stride", "ms"} (a launch is {"tile",
-    "waves_per_block", "persistent", "blocks_per_cu"}; "adj" is absent for mode "fwd").
+         strides: Sequence[int] = STRIDES, launches=LAUNCHES, layouts: Sequence[str] = LAYOUTS,
+         hbm_budget: Optional[int] = None, reps: int = 2, cache: Optional[str] = DEFAULT_CACHE,
+         force: bool = False) -> Dict:
+    """Pick launch shapes, the checkpoint stride and the field layout for these scenes;
+    returns the cached or new entry {"fwd": launch, "adj": launch, "ckpt_stride", "layout",
+    "ms"} (a launch is {"tile", "waves_per_block", "persistent", "blocks_per_cu"}; "adj" is
+    absent for mode "fwd"). The scenes come back with the chosen stride; the layout is the
+    caller's to apply (Field.relayout).
 
     Stage 1 times the forward trace (with checkpoints at stride 16 unless mode is "fwd")
     for every launch shape, stage 2 the adjoint alone for every shape after one forward
     with the best forward shape, stage 3 the whole forward + render + adjoint for every
-    stride whose checkpoints fit `hbm_budget` (default: half the free device memory)."""
+    stride whose checkpoints fit `hbm_budget` (default: half the free device memory), stage 4
+    the best of those with the scenes' fields re-encoded in each other layout."""
     key = cache_key(scenes, mode)
     db = {}
     if cache and os.path.exists(cache):
@@ -153,6 +160,24 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
             if ms < best[0]:
                 best = (ms, st)
         entry.update({"adj": _entry_of(best_adj), "ckpt_stride": best[1], "ms": best[0]})
+    own = scenes[0].field.layout if scenes else "cell"
+    entry["layout"] = own
+    for lay in layouts:
+        if lay == own or not scenes:
+            continue
+        fields = [s.field for s in scenes]
+        try:
+            for s in scenes:
+                s.set_field(s.field.relayout(lay))
+            if adj:
+                ms = whole(entry["ckpt_stride"])
+            else:
+                ms = _time(tracer(best_fwd, None, 0).forward, reps)
+        finally:
+            for s, f in zip(scenes, fields):
+                s.set_field(f)
+        if ms < entry["ms"]:
+            entry.update({"layout": lay, "ms": ms})
     for s in scenes:
         s.struct.ckpt_stride = entry["ckpt_stride"]
     if cache:

@@ -77,6 +77,8 @@ int check_launch(const rbos_launch* L, Launch& out) {
   return RBOS_OK;
 }
 
+bool valid_dtype(int32_t dtype) { return dtype >= RBOS_F32 && dtype <= RBOS_BF16_XPAIR; }
+
 int check_scene(const rbos_scene* S, int idx, bool need_render) {
   if (S->nx < 2 || S->ny < 2 || S->nz < 2 || S->nx > RBOS_MAX_DIM || S->ny > RBOS_MAX_DIM || S->nz > RBOS_MAX_DIM)
     return fail(RBOS_E_SHAPE, "scene %d: voxel counts must be in [2, %d] (got %d x %d x %d)", idx, RBOS_MAX_DIM, S->nx,
@@ -84,8 +86,7 @@ int check_scene(const rbos_scene* S, int idx, bool need_render) {
   if (!finite3(S->box_lo) || !finite3(S->box_hi) || !(S->box_lo[0] < S->box_hi[0]) ||
       !(S->box_lo[1] < S->box_hi[1]) || !(S->box_lo[2] < S->box_hi[2]))
     return fail(RBOS_E_RANGE, "scene %d: box must be finite with lo < hi on every axis", idx);
-  if (S->dtype != RBOS_F32 && S->dtype != RBOS_F16 && S->dtype != RBOS_BF16)
-    return fail(RBOS_E_DTYPE, "scene %d: unknown dtype %d", idx, S->dtype);
+  if (!valid_dtype(S->dtype)) return fail(RBOS_E_DTYPE, "scene %d: unknown dtype %d", idx, S->dtype);
   if (!pow2(S->enc_scale)) return fail(RBOS_E_RANGE, "scene %d: enc_scale must be a positive power of two", idx);
   if (!std::isfinite(S->enc_offset)) return fail(RBOS_E_RANGE, "scene %d: enc_offset must be finite", idx);
   if (!S->field) return fail(RBOS_E_NULL, "scene %d: field is NULL", idx);
@@ -247,8 +248,11 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
     d.proj_right[a] = to_df(S->proj_right[a]);
     d.proj_up[a] = to_df(S->proj_up[a]);
   }
+  // record strides of the padded cell grid, or entry strides of the x-pair array (one
+  // more row and plane in y and z)
+  d.P1 = rbos::is_xpair(S->dtype) ? S->ny + 2 : S->ny + 1;
   d.P0 = S->nx + 1;
-  d.P01 = (S->nx + 1) * (S->ny + 1);
+  d.P01 = d.P0 * d.P1;
   rec_divisor(d.P0, d.rec_div_m[0], d.rec_div_s[0]);
   rec_divisor(d.P01, d.rec_div_m[1], d.rec_div_s[1]);
   d.dtype = S->dtype;
@@ -265,6 +269,14 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.h2_8 = (float)(h * h / 8.0);
   d.h2_2 = (float)(h * h / 2.0);
   d.h2_6 = (float)(h * h / 6.0);
+  for (int a = 0; a < 3; ++a) {
+    const double vox = (S->box_hi[a] - S->box_lo[a]) / n[a];
+    const double km = dec / (vox * vox);
+    d.c_p2[a] = (float)(h * h / 8.0 * km);
+    d.c_p3[a] = (float)(h * h / 2.0 * km);
+    d.c_x[a] = (float)(h * h / 6.0 * km);
+    d.c_v[a] = (float)(h / 6.0 * km);
+  }
   d.max_steps = S->max_steps;
   d.ckpt_k = S->ckpt_stride > 0 ? S->ckpt_stride : 1;
   d.ckpt_slots = ckpt_slots(S);
@@ -478,8 +490,11 @@ const char* rbos_last_error(void) { return g_err.c_str(); }
 
 size_t rbos_field_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype) {
   if (nx < 2 || ny < 2 || nz < 2 || nx > RBOS_MAX_DIM || ny > RBOS_MAX_DIM || nz > RBOS_MAX_DIM) return 0;
-  size_t rec = dtype == RBOS_F32 ? 32 : (dtype == RBOS_F16 || dtype == RBOS_BF16 ? 16 : 0);
-  return rec * (size_t)(nx + 1) * (size_t)(ny + 1) * (size_t)(nz + 1);
+  if (!valid_dtype(dtype)) return 0;
+  const bool f32 = rbos::code_type(dtype) == rbos::DT_F32;
+  if (rbos::is_xpair(dtype))
+    return (f32 ? 8 : 4) * (size_t)(nx + 1) * (size_t)(ny + 2) * (size_t)(nz + 2);
+  return (f32 ? 32 : 16) * (size_t)(nx + 1) * (size_t)(ny + 1) * (size_t)(nz + 1);
 }
 
 static int field_common(int32_t nx, int32_t ny, int32_t nz, const float* src, int from_t, double rho0G, double T0,
@@ -487,7 +502,7 @@ static int field_common(int32_t nx, int32_t ny, int32_t nz, const float* src, in
   g_err.clear();
   if (nx < 2 || ny < 2 || nz < 2 || nx > RBOS_MAX_DIM || ny > RBOS_MAX_DIM || nz > RBOS_MAX_DIM)
     return fail(RBOS_E_SHAPE, "voxel counts must be in [2, %d]", RBOS_MAX_DIM);
-  if (dtype != RBOS_F32 && dtype != RBOS_F16 && dtype != RBOS_BF16) return fail(RBOS_E_DTYPE, "unknown dtype %d", dtype);
+  if (!valid_dtype(dtype)) return fail(RBOS_E_DTYPE, "unknown dtype %d", dtype);
   if (!src || !field) return fail(RBOS_E_NULL, "input or field pointer is NULL");
   if (!pow2(scale)) return fail(RBOS_E_RANGE, "enc_scale must be a positive power of two");
   if (!std::isfinite(offset)) return fail(RBOS_E_RANGE, "enc_offset must be finite");
@@ -512,8 +527,8 @@ int rbos_field_encode(int32_t nx, int32_t ny, int32_t nz, const float* delta, in
 // Largest power of two s with s * max |delta - c| <= 2^14 over delta in [lo, hi] (|delta - c|
 // is convex, so its maximum is at an end of the range); 1 for FP32 or a zero range.
 static double code_scale(int32_t dtype, double lo, double hi, double c) {
-  if (dtype == RBOS_F32) return 1.0;
-  if (dtype != RBOS_F16 && dtype != RBOS_BF16) return 0.0;
+  if (!valid_dtype(dtype)) return 0.0;
+  if (rbos::code_type(dtype) == rbos::DT_F32) return 1.0;
   if (!std::isfinite(lo) || !std::isfinite(hi) || !std::isfinite(c) || lo > hi) return 0.0;
   const double m = std::max(std::fabs(lo - c), std::fabs(hi - c));
   if (m == 0.0) return 1.0;

@@ -123,9 +123,20 @@ __global__ __launch_bounds__(256) void k_atomic_f64(double* __restrict__ g, int 
   }
 }
 
+// Stream copy: each lane moves 4 x 16 bytes per round (four loads in flight before the
+// stores), rounds striding over the grid.
 __global__ __launch_bounds__(256) void k_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = ld4(src + i);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const f32x4 a = ld4(src + i), b = ld4(src + i + stride), c = ld4(src + i + 2 * stride),
+                d = ld4(src + i + 3 * stride);
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = ld4(src + i);
 }
 
 int status(hipError_t e) { return e == hipSuccess ? 0 : -6; }

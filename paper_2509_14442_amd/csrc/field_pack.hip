@@ -8,7 +8,7 @@ namespace rbos {
 
 __device__ __forceinline__ unsigned int code16(float q, int dtype) {
   // binary32 -> binary16 conversion rounds to nearest, ties to even
-  if (dtype == DT_F16) return (unsigned int)__builtin_bit_cast(unsigned short, (_Float16)q);
+  if (code_type(dtype) == DT_F16) return (unsigned int)__builtin_bit_cast(unsigned short, (_Float16)q);
   unsigned int b = __float_as_uint(q);
   if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return ((b >> 16) & 0x8000u) | 0x7fc0u;
   return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;  // round to nearest, ties to even
@@ -60,13 +60,54 @@ __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, cons
   }
 }
 
+// delta (or eta - 1 from the temperature) and its code q = RN((delta - c) * s) at voxel v
+__device__ __forceinline__ float code_at(const float* __restrict__ src, size_t v, int from_temperature, float rho0G,
+                                         float T0, float scale, float offset) {
+  float d = src[v];
+  if (from_temperature) {
+    float ratio = T0 / d;
+    d = rho0G * ratio;
+  }
+  float t = d - offset;
+  return t * scale;
+}
+
+// X-pair entries: one thread per entry (i, j, k), i in [-1, nx-1], j in [-1, ny],
+// k in [-1, nz], holding voxels (clamp(i), y, z) and (clamp(i+1), y, z) with y = clamp(j),
+// z = clamp(k).
+__global__ __launch_bounds__(256) void k_field_pack_xpair(int nx, int ny, int nz, const float* __restrict__ src,
+                                                          int from_temperature, float rho0G, float T0, int dtype,
+                                                          float scale, float offset, void* __restrict__ field) {
+  const int px = nx + 1, py = ny + 2, pz = nz + 2;
+  const int nent = px * py * pz;  // < 2^27
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nent; e += gridDim.x * blockDim.x) {
+    const int row = e / px;
+    const int i = e - row * px - 1;
+    const int k = row / py;
+    const int y = min(max(row - k * py - 1, 0), ny - 1);
+    const int z = min(max(k - 1, 0), nz - 1);
+    const size_t base = ((size_t)z * ny + y) * nx;
+    const float q0 = code_at(src, base + min(max(i, 0), nx - 1), from_temperature, rho0G, T0, scale, offset);
+    const float q1 = code_at(src, base + min(i + 1, nx - 1), from_temperature, rho0G, T0, scale, offset);
+    if (code_type(dtype) == DT_F32)
+      reinterpret_cast<float2*>(field)[e] = make_float2(q0, q1);
+    else
+      reinterpret_cast<unsigned int*>(field)[e] = code16(q0, dtype) | (code16(q1, dtype) << 16);
+  }
+}
+
 hipError_t launch_field_pack(int nx, int ny, int nz, const float* src, int from_temperature, float rho0G, float T0,
                              int dtype, float scale, float offset, void* field, hipStream_t stream) {
-  long long nrec = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  const bool xp = is_xpair(dtype);
+  long long nrec = xp ? (long long)(nx + 1) * (ny + 2) * (nz + 2) : (long long)(nx + 1) * (ny + 1) * (nz + 1);
   long long blocks = (nrec + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_field_pack, dim3((unsigned)blocks), dim3(256), 0, stream, nx, ny, nz, src, from_temperature,
-                     rho0G, T0, dtype, scale, offset, field);
+  if (xp)
+    hipLaunchKernelGGL(k_field_pack_xpair, dim3((unsigned)blocks), dim3(256), 0, stream, nx, ny, nz, src,
+                       from_temperature, rho0G, T0, dtype, scale, offset, field);
+  else
+    hipLaunchKernelGGL(k_field_pack, dim3((unsigned)blocks), dim3(256), 0, stream, nx, ny, nz, src, from_temperature,
+                       rho0G, T0, dtype, scale, offset, field);
   return hipGetLastError();
 }
 

@@ -115,7 +115,8 @@ __device__ __forceinline__ float dd_to_f(df a) { return a.hi + a.lo; }
 struct SceneDev {
   // field
   int n[3];            // voxels per axis
-  int P0, P01;         // record strides of the padded cell grid: (nx+1), (nx+1)(ny+1)
+  int P0, P01;         // record strides: cell records (nx+1), (nx+1)(ny+1); x-pairs (nx+1), (nx+1)(ny+2)
+  int P1;              // P01 / P0
   int dtype;
   const void* field;   // cell records, starting with cell (-1, -1, -1); cells -1 .. n-1 on every axis
   float dec;           // 1 / enc_scale
@@ -135,6 +136,9 @@ struct SceneDev {
   // integrator
   df h;                // step in t
   float hf, h_2, h_6, h2_8, h2_2, h2_6;
+  // stage coefficients of the force in code units (eta dq/du_a), per axis:
+  // h^2/8 km_a (P2), h^2/2 km_a (P3), h^2/6 km_a (position), h/6 km_a (velocity)
+  float c_p2[3], c_p3[3], c_x[3], c_v[3];
   int max_steps, ckpt_k, ckpt_slots;
   int tracer;          // 0 nonlinear, 1 quasi-linear (forces on the entry line)
   long long ckpt_pad;  // entries per checkpoint component (a multiple of 64)
@@ -192,7 +196,12 @@ enum : int {
   RAY_OFF_PATTERN = 16
 };
 
-enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+// Storage formats: the code type (FP32, FP16, BF16) of eta - 1, stored as cell records
+// (0, 1, 2) or as x-pairs (3, 4, 5; see fetch_cell).
+enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F32_XPAIR = 3, DT_F16_XPAIR = 4, DT_BF16_XPAIR = 5 };
+
+__host__ __device__ constexpr int code_type(int dt) { return dt % 3; }
+__host__ __device__ constexpr bool is_xpair(int dt) { return dt >= 3; }
 
 // ------------------------------------------------------------------------------------
 // work decomposition: XCD-aware block order, tiles of 64 rays
@@ -394,28 +403,53 @@ __device__ __forceinline__ bool wall_hit_straight(const SceneDev& S, const df di
 }
 
 // ------------------------------------------------------------------------------------
-// field: cell records and the trilinear sampler
+// field: cell records or x-pairs, and the trilinear sampler
 // ------------------------------------------------------------------------------------
-// Record of cell (i, j, k), i in [-1, n-1] per axis: the 8 corner codes
-// q[a + 2b + 4c] = code(clamp(i+a), clamp(j+b), clamp(k+c)), indices clamped to the grid.
-// FP32: 8 floats (32 B). FP16/BF16: 8 x 16-bit (16 B), two per 32-bit word.
-// `cell` is relative to the record of cell (0, 0, 0) and may be negative.
+// Cell records: the record of cell (i, j, k), i in [-1, n-1] per axis, holds the 8 corner
+// codes q[a + 2b + 4c] = code(clamp(i+a), clamp(j+b), clamp(k+c)), indices clamped to the
+// grid. FP32: 8 floats (32 B). FP16/BF16: 8 x 16-bit (16 B), two per 32-bit word. One
+// sample is one 32-byte (two 16-byte loads) or 16-byte load at the record index
+// rec = p0 + P0 p1 + P01 p2 of the padded cell (p = i + 1).
+// X-pairs: entry (p0, r1, r2), p0 in [0, nx], r1 in [0, ny + 1], r2 in [0, nz + 1], holds
+// the codes of voxels (clamp(p0 - 1), y, z) and (clamp(p0), y, z) with y = clamp(r1 - 1),
+// z = clamp(r2 - 1): one FP32 pair (8 B) or two 16-bit codes in a 32-bit word. The cell
+// p = (p0, p1, p2) reads the four entries rec, rec + P0, rec + P01, rec + P0 + P01 with
+// rec = p0 + P0 p1 + P01 p2: four loads of 8 or 4 bytes instead of one record, over an
+// array 4 (16-bit) to 8 (FP32) times smaller than the cell records.
 template <int DT>
-__device__ __forceinline__ void fetch_cell(const void* __restrict__ field, unsigned int rec, float c[8]) {
-  // 32-bit byte offset from the array start (at most 449^3 records of 32 B < 4 GiB), so
+__device__ __forceinline__ void fetch_cell(const SceneDev& S, unsigned int rec, float c[8]) {
+  // 32-bit byte offsets from the array start (at most 449^3 records of 32 B < 4 GiB), so
   // the load takes the array base from SGPRs and the offset from one VGPR
-  const unsigned char* base = static_cast<const unsigned char*>(field);
+  const unsigned char* base = static_cast<const unsigned char*>(S.field);
   if constexpr (DT == DT_F32) {
     const f32x4* p = reinterpret_cast<const f32x4*>(base + (rec << 5));
     const f32x4 a = gld(p), b = gld(p + 1);
     c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
     c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+  } else if constexpr (DT == DT_F32_XPAIR) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const unsigned P0 = (unsigned)S.P0, P01 = (unsigned)S.P01;
+    const f32x2 a = gld(reinterpret_cast<const f32x2*>(base + (rec << 3)));
+    const f32x2 b = gld(reinterpret_cast<const f32x2*>(base + ((rec + P0) << 3)));
+    const f32x2 d = gld(reinterpret_cast<const f32x2*>(base + ((rec + P01) << 3)));
+    const f32x2 e = gld(reinterpret_cast<const f32x2*>(base + ((rec + P0 + P01) << 3)));
+    c[0] = a.x; c[1] = a.y; c[2] = b.x; c[3] = b.y;
+    c[4] = d.x; c[5] = d.y; c[6] = e.x; c[7] = e.y;
   } else {
-    const u32x4 w = gld(reinterpret_cast<const u32x4*>(base + (rec << 4)));
-    unsigned int v[4] = {w.x, w.y, w.z, w.w};
+    unsigned int v[4];
+    if constexpr (is_xpair(DT)) {
+      const unsigned P0 = (unsigned)S.P0, P01 = (unsigned)S.P01;
+      v[0] = gld(reinterpret_cast<const unsigned int*>(base + (rec << 2)));
+      v[1] = gld(reinterpret_cast<const unsigned int*>(base + ((rec + P0) << 2)));
+      v[2] = gld(reinterpret_cast<const unsigned int*>(base + ((rec + P01) << 2)));
+      v[3] = gld(reinterpret_cast<const unsigned int*>(base + ((rec + P0 + P01) << 2)));
+    } else {
+      const u32x4 w = gld(reinterpret_cast<const u32x4*>(base + (rec << 4)));
+      v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if constexpr (DT == DT_F16) {
+      if constexpr (code_type(DT) == DT_F16) {
         // Plain v_cvt_f32_f16 on separated halves: left free, the compiler folds the
         // conversions into v_fma_mix_f32 / SDWA forms, which made the FP16 kernels ~10%
         // slower on gfx950. The empty asm statements only hide the values from that fold.
@@ -459,8 +493,8 @@ __device__ __forceinline__ void locate3(const SceneDev& S, const float bhi[3], c
   locate(bhi[2], small[2], S.n_f[2], C.p[2], C.f[2]);
 }
 
-// record of cell C counted from the array start (cell (-1, -1, -1)); 24-bit multiplies
-// (full rate) suffice: indices <= 448, strides <= 449^2
+// record (entry) of cell C counted from the array start (cell (-1, -1, -1)); 24-bit
+// multiplies (full rate) suffice: indices <= 448, strides <= 449 * 450
 __device__ __forceinline__ unsigned int cell_index(const SceneDev& S, const Cell& C) {
   return (unsigned)C.p[0] + __umul24((unsigned)C.p[1], (unsigned)S.P0) + __umul24((unsigned)C.p[2], (unsigned)S.P01);
 }
@@ -472,7 +506,7 @@ __device__ __forceinline__ void cell_of_record(const SceneDev& S, unsigned r, in
   const unsigned t = (unsigned)(((unsigned long long)r * S.rec_div_m[0]) >> S.rec_div_s[0]);  // r / P0
   const unsigned z = (unsigned)(((unsigned long long)r * S.rec_div_m[1]) >> S.rec_div_s[1]);  // r / P01
   p[0] = (int)(r - t * (unsigned)S.P0);
-  p[1] = (int)(t - z * (unsigned)(S.n[1] + 1));
+  p[1] = (int)(t - z * (unsigned)S.P1);
   p[2] = (int)z;
 }
 
@@ -510,6 +544,17 @@ __device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], 
   H[2] = e1 - e0;                  // d2q / dy dz
 }
 
+// Force of Eq. (1) in code units from a cell's corner codes and the fractions:
+// G_a = (1 + delta) dq/du_a; the grid-unit force is K_a = G_a km_a, km_a = dec / voxel_a^2
+// (the Sharma step folds km_a into its stage coefficients).
+__device__ __forceinline__ void force_code(const SceneDev& S, const float c[8], const float f[3], float G[3]) {
+  float q, g[3];
+  trilinear(c, f, q, g);
+  float eta = fmaf(q, S.dec, S.one_plus_off);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) G[a] = eta * g[a];
+}
+
 // Grid-unit force of Eq. (1) from a cell's corner codes and the fractions:
 // K_a = (1 + delta) d(delta)/du_a / voxel_a^2.
 __device__ __forceinline__ void force_of(const SceneDev& S, const float c[8], const float f[3], float K[3]) {
@@ -523,7 +568,7 @@ __device__ __forceinline__ void force_of(const SceneDev& S, const float c[8], co
 template <int DT>
 __device__ __forceinline__ void force_at_rec(const SceneDev& S, unsigned rec, const float f[3], float K[3]) {
   float c[8];
-  fetch_cell<DT>(S.field, rec, c);
+  fetch_cell<DT>(S, rec, c);
   force_of(S, c, f, K);
 }
 
@@ -574,7 +619,7 @@ __device__ __forceinline__ void make_base(const SceneDev& S, const Ray& R, RayBa
   }
   locate3(S, bh, small, C0);
   float c[8];
-  fetch_cell<DT>(S.field, cell_index(S, C0), c);
+  fetch_cell<DT>(S, cell_index(S, C0), c);
   float q, g[3];
   trilinear(c, C0.f, q, g);
   float delta = fmaf(q, S.dec, S.off);
@@ -604,6 +649,20 @@ __device__ __forceinline__ float small_part(const RayBase& B, int a, float jf, f
   return fmaf(jf, B.g2lo[a], B.U0lo[a]) + dev;
 }
 
+// Deviations (grid units) of the stage points of a Sharma step from the state's base
+// point, given the stage forces in code units (G = K / km): P2 = x + h/2 v + h^2/8 K1,
+// P3 = x + h v + h^2/2 K2, with x + h v shared with the position update. The adjoint's
+// reverse relocates stage points with these same functions.
+__device__ __forceinline__ float stage2_dev(const SceneDev& S, const State& st, int a, float G1) {
+  return fmaf(S.c_p2[a], G1, fmaf(S.h_2, st.e[a], st.d[a]));
+}
+__device__ __forceinline__ float stage3_base(const SceneDev& S, const State& st, int a) {
+  return fmaf(S.hf, st.e[a], st.d[a]);
+}
+__device__ __forceinline__ float stage3_dev(const SceneDev& S, int a, float base3, float G2) {
+  return fmaf(S.c_p3[a], G2, base3);
+}
+
 // One Sharma step of Eq. (1) (grid units):
 //   K1 = D(P1), P1 = x
 //   K2 = D(P2), P2 = x + h/2 v + h^2/8 K1
@@ -614,41 +673,48 @@ __device__ __forceinline__ float small_part(const RayBase& B, int a, float jf, f
 template <int DT, class Record = NoRecord, class Issue = NoIssue>
 __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B, State& st, Cell& C,
                                             const Record& record = Record(), const Issue& issue = Issue()) {
-  float K1[3], K2[3], K3[3], bh2[3], bh3[3], sm[3];
+  float G1[3], G2[3], G3[3], bh2[3], bh3[3], sm[3], base3[3];
   unsigned rec = cell_index(S, C);
   record(0, rec, C);
   {
     float c[8];
-    fetch_cell<DT>(S.field, rec, c);
+    fetch_cell<DT>(S, rec, c);
     __builtin_amdgcn_sched_barrier(0);
     issue();
     __builtin_amdgcn_sched_barrier(0);
-    force_of(S, c, C.f, K1);
+    force_code(S, c, C.f, G1);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     bh2[a] = st.bh[a] + B.g2hi[a];
-    float dev = st.d[a] + fmaf(S.h_2, st.e[a], S.h2_8 * K1[a]);
-    sm[a] = small_part(B, a, st.jf + 1.0f, dev);
+    sm[a] = small_part(B, a, st.jf + 1.0f, stage2_dev(S, st, a, G1[a]));
   }
   locate3(S, bh2, sm, C);
   rec = cell_index(S, C);
   record(1, rec, C);
-  force_at_rec<DT>(S, rec, C.f, K2);
+  {
+    float c[8];
+    fetch_cell<DT>(S, rec, c);
+    force_code(S, c, C.f, G2);
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     bh3[a] = bh2[a] + B.g2hi[a];
-    float dev = st.d[a] + fmaf(S.hf, st.e[a], S.h2_2 * K2[a]);
-    sm[a] = small_part(B, a, st.jf + 2.0f, dev);
+    base3[a] = stage3_base(S, st, a);
+    sm[a] = small_part(B, a, st.jf + 2.0f, stage3_dev(S, a, base3[a], G2[a]));
   }
   locate3(S, bh3, sm, C);
   rec = cell_index(S, C);
   record(2, rec, C);
-  force_at_rec<DT>(S, rec, C.f, K3);
+  {
+    float c[8];
+    fetch_cell<DT>(S, rec, c);
+    force_code(S, c, C.f, G3);
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float dn = st.d[a] + fmaf(S.hf, st.e[a], S.h2_6 * fmaf(2.0f, K2[a], K1[a]));
-    float en = st.e[a] + S.h_6 * (fmaf(4.0f, K2[a], K1[a]) + K3[a]);
+    float dn = fmaf(S.c_x[a], fmaf(2.0f, G2[a], G1[a]), base3[a]);
+    float en = fmaf(S.c_v[a], fmaf(4.0f, G2[a], G1[a]) + G3[a], st.e[a]);
     st.d[a] = dn;
     st.e[a] = en;
     st.bh[a] = bh3[a];

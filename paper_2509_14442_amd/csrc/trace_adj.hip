@@ -40,20 +40,24 @@ template <int DT>
 __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, SampleRev& R) {
   float c[8];
   const unsigned rec = cell_index(S, C);
-  fetch_cell<DT>(S.field, rec, c);
+  fetch_cell<DT>(S, rec, c);
   sample_rev_at(S, c, rec, C.f, R);
 }
 
 // Reverse of K = force(P) for an adjoint v = dL/dK: returns p = dL/dP (grid units) and
-// the 8 corner contributions dL/d(delta_c):
+// the sample's contributions to dL/d(delta_c) for the 8 corners of its cell,
 //   w_a = v_a km_a,  sigma = sum_a w_a g_a,
 //   p_b = dec g_b sigma + eta sum_{a != b} w_a H_ab,
-//   dL/d delta_c = w_c sigma + (eta / dec) sum_a w_a dw_c/du_a.
-// (In apron cells the field is constant along the clamped axis: g and H vanish there and
-// the two corners that share one edge voxel receive contributions that add up to the
-// clamped-axis weights.)
+//   dL/d delta_c = w_c sigma + sum_a W_a dw_c/du_a,  W_a = (eta / dec) w_a,
+// with w_c the trilinear weight of corner c. The contributions are multilinear in the
+// fractions (u, v, w) = f, so they are returned as the coefficients M[m] of the 8
+// monomials m = u^(m & 1) v^(m >> 1 & 1) w^(m >> 2): M[m] = sigma m + sum_a W_a dm/du_a.
+// Samples in one cell share the monomials' frame, so their coefficients add up; corner
+// values follow from the totals (corner_of_monomials). In apron cells the field is
+// constant along the clamped axis (g and H vanish there); the two corners that share one
+// edge voxel receive contributions that add up to the clamped-axis weights.
 __device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R, const float v[3], float p[3],
-                                          float contrib[8]) {
+                                          float M[8]) {
   float w0 = v[0] * S.km[0], w1 = v[1] * S.km[1], w2 = v[2] * S.km[2];
   float sigma = fmaf(w0, R.g[0], fmaf(w1, R.g[1], w2 * R.g[2]));
   float ds = S.dec * sigma;
@@ -61,26 +65,36 @@ __device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R,
   p[0] = fmaf(ds, R.g[0], R.eta * fmaf(w1, R.H[0], w2 * R.H[1]));
   p[1] = fmaf(ds, R.g[1], R.eta * fmaf(w0, R.H[0], w2 * R.H[2]));
   p[2] = fmaf(ds, R.g[2], R.eta * fmaf(w0, R.H[1], w1 * R.H[2]));
-  // corner weights: w = X_i Y_j Z_k with X_0 = 1 - fx, X_1 = fx; dX_i/du = -1, +1
-  const float fx = R.f[0], fy = R.f[1], fz = R.f[2];
-  const float X[2] = {1.0f - fx, fx}, Y[2] = {1.0f - fy, fy}, Z[2] = {1.0f - fz, fz};
   const float ed = R.eta * S.inv_dec;
   const float Wx = w0 * ed, Wy = w1 * ed, Wz = w2 * ed;
-  const float alpha[2] = {fmaf(X[0], sigma, -Wx), fmaf(X[1], sigma, Wx)};
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      float yz = Y[j] * Z[k];
-      float sy = j ? Wy : -Wy, sz = k ? Wz : -Wz;
-      float beta = fmaf(sy, Z[k], sz * Y[j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) contrib[i + 2 * j + 4 * k] = fmaf(yz, alpha[i], X[i] * beta);
-    }
-  }
+  const float u = R.f[0], vv = R.f[1], w = R.f[2];
+  M[0] = sigma;                                   // 1
+  M[1] = fmaf(sigma, u, Wx);                      // u
+  M[2] = fmaf(sigma, vv, Wy);                     // v
+  M[4] = fmaf(sigma, w, Wz);                      // w
+  M[3] = fmaf(vv, M[1], Wy * u);                  // uv:  sigma uv + Wx v + Wy u
+  M[5] = fmaf(w, M[1], Wz * u);                   // uw:  sigma uw + Wx w + Wz u
+  M[6] = fmaf(w, M[2], Wz * vv);                  // vw:  sigma vw + Wy w + Wz v
+  M[7] = fmaf(w, M[3], Wz * (u * vv));            // uvw: sigma uvw + Wx vw + Wy uw + Wz uv
 }
 
-// Per-lane merge of corner contributions by cell, flushed across the wavefront.
+// Corner c of a cell from its 8 monomial totals: the trilinear weight of corner
+// (i, j, k) is the product over the axes of (1 - u) (bit 0) or u (bit 1), so monomial m
+// enters corner c when it holds every axis set in c, with the sign (-1) per axis it holds
+// beyond c. Summed in FP64.
+__device__ __forceinline__ double corner_of_monomials(const float* vals, int c) {
+  double g = 0.0;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    if ((m & c) == c) {
+      const double t = (double)vals[m];
+      g += (__popc(m & ~c) & 1) ? -t : t;
+    }
+  }
+  return g;
+}
+
+// Per-lane merge of the samples' monomial coefficients by cell, flushed across the wavefront.
 constexpr int CELL_NONE = INT_MIN;
 
 struct Accum {
@@ -175,7 +189,7 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
         slot = P.next;
         P.next = (P.next + 1) & (PEND_SLOTS - 1);
         const int old = __builtin_amdgcn_readlane(P.key, slot);
-        if (lane < 8) gatomic_add(voxel_of_corner(S, old, lane), (double)P.vals[slot * 8 + lane]);
+        if (lane < 8) gatomic_add(voxel_of_corner(S, old, lane), corner_of_monomials(P.vals + slot * 8, lane));
         wave_lds_order();
       }
       if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
@@ -185,6 +199,11 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
     P.touched |= 1ull << slot;
     wave_lds_order();
     pend &= ~__ballot(mine);
+  }
+  // the flushed lanes restart their sums (accumulate then only adds)
+  if (sel) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
   }
 }
 
@@ -196,7 +215,8 @@ __device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigne
     if (((which >> (8 * q)) & 0xffull) == 0) continue;
     const int idx = q * 64 + lane, slot = idx >> 3;
     const int key = __shfl(P.key, slot);
-    if ((which >> slot) & 1ull) gatomic_add(voxel_of_corner(S, key, idx & 7), (double)P.vals[idx]);
+    if ((which >> slot) & 1ull)
+      gatomic_add(voxel_of_corner(S, key, idx & 7), corner_of_monomials(P.vals + slot * 8, idx & 7));
   }
   wave_lds_order();
   if ((which >> lane) & 1ull) P.key = CELL_NONE;
@@ -210,18 +230,16 @@ __device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lan
   P.touched = 0;
 }
 
-// Merge one sample's contributions (lanes with act) into the accumulators. A lane that
-// enters a new cell restarts from its contribution: acc * 0 + ct (exactly ct, the
-// accumulators being finite), else acc * 1 + ct (exactly acc + ct).
+// Merge one sample's monomial coefficients (lanes with act) into the accumulators. A lane
+// that enters a new cell has had its sums flushed and zeroed (or never held any).
 __device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
                                            int lane, Pending& P) {
   const bool change = act && key != A.key;
   const bool out = change && A.key != CELL_NONE;
   if (__ballot(out)) flush(S, A, out, lane, P);
   if (act) {
-    const float keep = change ? 0.0f : 1.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) A.acc[k] = fmaf(A.acc[k], keep, ct[k]);
+    for (int k = 0; k < 8; ++k) A.acc[k] += ct[k];
     A.key = key;
   }
 }
@@ -320,9 +338,16 @@ __device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, 
     float kap = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) kap = fmaf(tb0[a], (V[a] / vn) * dd_to_f(S.inv_vox[a]), kap);
-    const float X[2] = {1.0f - C0.f[0], C0.f[0]}, Y[2] = {1.0f - C0.f[1], C0.f[1]}, Z[2] = {1.0f - C0.f[2], C0.f[2]};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) c0v[k] = kap * (X[k & 1] * Y[(k >> 1) & 1] * Z[k >> 2]);
+    // kap w_c(x0) as monomial coefficients: kap m(f)
+    const float u = C0.f[0], v = C0.f[1], w = C0.f[2];
+    c0v[0] = kap;
+    c0v[1] = kap * u;
+    c0v[2] = kap * v;
+    c0v[3] = c0v[1] * v;
+    c0v[4] = kap * w;
+    c0v[5] = c0v[1] * w;
+    c0v[6] = c0v[2] * w;
+    c0v[7] = c0v[3] * w;
     key0 = (int)cell_index(S, C0);
   }
   accumulate(S, A, active, key0, c0v, lane, P);
@@ -351,7 +376,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
   A.key = CELL_NONE;
   Pending P{replay + KS * 6 * 64, CELL_NONE, 0, 0ull, 0ull};
-  const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6, h2_8 = S.h2_8, h2_2 = S.h2_2;
+  const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6;
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
     for (int ch = m_chunks - 1; ch >= 0; --ch) {
@@ -421,26 +446,22 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             s.e[a] = replay[(i * 6 + 3 + a) * 64 + lane];
             s.bh[a] = fmaf(s.jf, B.g2hi[a], B.U0hi[a]);
           }
-          float K1[3], K2[3], bh[3], sm[3];
+          float bh[3], sm[3];
           locate_state(S, B, s, Q1);
           sample_rev<DT>(S, Q1, R1);
 #pragma unroll
-          for (int a = 0; a < 3; ++a) K1[a] = R1.eta * (R1.g[a] * S.km[a]);  // as force_at
-#pragma unroll
           for (int a = 0; a < 3; ++a) {
             bh[a] = s.bh[a] + B.g2hi[a];
-            sm[a] = small_part(B, a, s.jf + 1.0f, s.d[a] + fmaf(h_2, s.e[a], h2_8 * K1[a]));
+            sm[a] = small_part(B, a, s.jf + 1.0f, stage2_dev(S, s, a, R1.eta * R1.g[a]));  // as force_code
           }
           Cell Q2;
           locate3(S, bh, sm, Q2);
           sample_rev<DT>(S, Q2, R2);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) K2[a] = R2.eta * (R2.g[a] * S.km[a]);  // as force_at
           Cell Q3;
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             bh[a] = bh[a] + B.g2hi[a];
-            sm[a] = small_part(B, a, s.jf + 2.0f, s.d[a] + fmaf(h, s.e[a], h2_2 * K2[a]));
+            sm[a] = small_part(B, a, s.jf + 2.0f, stage3_dev(S, a, stage3_base(S, s, a), R2.eta * R2.g[a]));
           }
           locate3(S, bh, sm, Q3);
           // stage C = h K3: adjoint v = h dL/dC
@@ -573,9 +594,9 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
           const f32x4 s1 = row[0], s2 = row[64], s3 = row[128];
           const unsigned r1 = __float_as_uint(s1.x), r2 = __float_as_uint(s2.x), r3 = __float_as_uint(s3.x);
           float c1[8], c2[8], c3[8];
-          fetch_cell<DT>(S.field, r3, c3);
-          fetch_cell<DT>(S.field, r2, c2);
-          fetch_cell<DT>(S.field, r1, c1);
+          fetch_cell<DT>(S, r3, c3);
+          fetch_cell<DT>(S, r2, c2);
+          fetch_cell<DT>(S, r1, c1);
           const float f3[3] = {s3.y, s3.z, s3.w}, f2[3] = {s2.y, s2.z, s2.w}, f1[3] = {s1.y, s1.z, s1.w};
           sample_rev_at(S, c3, r3, f3, R3);
           sample_rev_at(S, c2, r2, f2, R2);
@@ -961,7 +982,10 @@ hipError_t launch_trace_adj(const LaunchPlan& P, hipStream_t stream) {
   switch (P.dtype) {
     case DT_F32: return launch_adj_dt<DT_F32>(P, stream);
     case DT_F16: return launch_adj_dt<DT_F16>(P, stream);
-    default: return launch_adj_dt<DT_BF16>(P, stream);
+    case DT_BF16: return launch_adj_dt<DT_BF16>(P, stream);
+    case DT_F32_XPAIR: return launch_adj_dt<DT_F32_XPAIR>(P, stream);
+    case DT_F16_XPAIR: return launch_adj_dt<DT_F16_XPAIR>(P, stream);
+    default: return launch_adj_dt<DT_BF16_XPAIR>(P, stream);
   }
 }
 

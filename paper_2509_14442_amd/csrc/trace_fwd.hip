@@ -226,7 +226,10 @@ hipError_t launch_trace_fwd(const LaunchPlan& P, hipStream_t stream) {
   switch (P.dtype) {
     case DT_F32: return launch_fwd_dt<DT_F32>(P, stream);
     case DT_F16: return launch_fwd_dt<DT_F16>(P, stream);
-    default: return launch_fwd_dt<DT_BF16>(P, stream);
+    case DT_BF16: return launch_fwd_dt<DT_BF16>(P, stream);
+    case DT_F32_XPAIR: return launch_fwd_dt<DT_F32_XPAIR>(P, stream);
+    case DT_F16_XPAIR: return launch_fwd_dt<DT_F16_XPAIR>(P, stream);
+    default: return launch_fwd_dt<DT_BF16_XPAIR>(P, stream);
   }
 }
 

@@ -22,6 +22,8 @@ import oracle  # noqa: E402
 
 RHO0G, T0 = 2.7e-4, 293.0
 CODES = {"f32": oracle.CODE_F32, "f16": oracle.CODE_F16, "bf16": oracle.CODE_BF16}
+# the x-pair storage formats hold the same codes as the cell records of their code type
+CODES.update({k + "-xpair": v for k, v in list(CODES.items())})
 
 
 @dataclasses.dataclass
@@ -52,7 +54,7 @@ def room_workload(dims=(128, 128, 128), width=512, height=512, seed=2, max_steps
 def expected_scale(T32: np.ndarray, dtype: str, offset: float = 0.0) -> float:
     """The power-of-two code scale for a temperature field, derived here from the seeded
     input: the largest s with s * max |eta - 1 - c| <= 2^14 (1 for FP32)."""
-    if dtype == "f32":
+    if dtype.split("-")[0] == "f32":
         return 1.0
     t = T32.astype(np.float64)
     bound = max(abs(RHO0G * T0 / t.min() - offset), abs(RHO0G * T0 / t.max() - offset))

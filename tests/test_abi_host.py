@@ -83,7 +83,7 @@ def _fwd(lib, s, outs=None, launch=None, ws=0x100000, ws_bytes=1 << 20):
     (lambda s: setattr(s, "nx", 1), -2),
     (lambda s: setattr(s, "nz", 500), -2),
     (lambda s: setattr(s, "box_hi", L.D3(0, 1, 1)), -3),
-    (lambda s: setattr(s, "dtype", 5), -4),
+    (lambda s: setattr(s, "dtype", 6), -4),
     (lambda s: setattr(s, "enc_scale", 3.0), -3),
     (lambda s: setattr(s, "field", None), -1),
     (lambda s: setattr(s, "cam_fwd", L.D3(0, 1, 0.1)), -3),
@@ -177,7 +177,7 @@ def test_field_validation_and_sizes(lib):
     assert lib.rbos_field_from_temperature(4, 4, 4, None, 2.7e-4, 293.0, 0, 1.0, 0.0, C.c_void_p(0x20), None) == -1
     assert lib.rbos_field_from_temperature(4, 4, 4, C.c_void_p(0x10), -1.0, 293.0, 0, 1.0, 0.0,
                                            C.c_void_p(0x20), None) == -3
-    assert lib.rbos_field_encode(4, 4, 4, C.c_void_p(0x10), 3, 1.0, 0.0, C.c_void_p(0x20), None) == -4
+    assert lib.rbos_field_encode(4, 4, 4, C.c_void_p(0x10), 7, 1.0, 0.0, C.c_void_p(0x20), None) == -4
     s = _valid_scene()
     # a 19-float ray header plus 6 floats per checkpoint slot, per entry: the image in
     # 8 x 8 pixel blocks (4 x 4 pixels: one block of 64 entries)
@@ -306,3 +306,13 @@ def test_code_scale(lib):
     assert lib.rbos_code_scale(7, 0.0, 1.0, 0.0) == 0.0
     assert lib.rbos_code_scale(L.RBOS_F16, 1.0, 0.0, 0.0) == 0.0
     assert lib.rbos_code_scale_temperature(L.RBOS_F16, 0.0, 300.0, RHO0G, T0, 0.0) == 0.0
+
+
+def test_field_bytes_xpair(lib):
+    # x-pairs: (nx+1)(ny+2)(nz+2) entries of 8 B (FP32) or 4 B (two 16-bit codes)
+    assert lib.rbos_field_bytes(128, 128, 128, L.RBOS_F32_XPAIR) == 8 * 129 * 130 * 130
+    assert lib.rbos_field_bytes(256, 256, 192, L.RBOS_BF16_XPAIR) == 4 * 257 * 258 * 194
+    assert lib.rbos_field_bytes(448, 448, 448, L.RBOS_F16_XPAIR) == 4 * 449 * 450 * 450
+    assert lib.rbos_field_bytes(4, 4, 4, 6) == 0
+    assert lib.rbos_code_scale(L.RBOS_F32_XPAIR, 0.0, 1.0, 0.0) == 1.0
+    assert lib.rbos_code_scale(L.RBOS_BF16_XPAIR, -2.0 ** -16, 0.0, 0.0) == 2.0 ** 30
