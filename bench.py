@@ -94,8 +94,13 @@ def parse(argv=None):
                         "command-line values)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--traffic", default=TRAFFIC_FILE,
-                   help="summary of the FETCH_SIZE / WRITE_SIZE counter runs of the adjoint kernel")
+    p.add_argument("--counters", default=COUNTERS_FILE, help="summary of the counter runs of the tracer kernels")
+    p.add_argument("--profile-kernels", action="store_true",
+                   help="run the fixed dispatch sequence the counter runs profile (implies --tune 0) and exit")
+    p.add_argument("--write-counters", default=None,
+                   help="summarise the counter CSVs of --counter-dirs into this file (for the configuration the "
+                        "other flags name) and exit")
+    p.add_argument("--counter-dirs", nargs="*", default=[])
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration) and exit")
     p.add_argument("--ceilings", action="store_true",
@@ -120,18 +125,22 @@ def launches(args):
     return fwd, adj
 
 
-# HBM traffic of the adjoint kernel on the default workload, from two rocprofv3 --pmc runs.
-# Used only while the kernel's sources hash to the value recorded with the counters.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_adj_room1m_f32_hbm_traffic.md")
-ADJ_SOURCES = ("trace_adj.hip", "rbos_device.hpp", "rbos_launch.hpp")
+# Hardware counters of the tracer kernels (rocprofv3 --pmc runs of `bench.py
+# --profile-kernels`, summarised by `bench.py --write-counters`): vector-L1 accesses, L2
+# requests and HBM bytes per launch. Used only while the kernels' sources hash to the value
+# recorded with the counters and the configuration matches.
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "tracer_room1m_counters.md")
+KERNEL_SOURCES = ("trace_fwd.hip", "trace_adj.hip", "rbos_device.hpp", "rbos_launch.hpp", "abi.hip",
+                  "field_pack.hip", "ceilings.hip")
 COPY_BYTES = 256 << 20
+CEIL_COPY_BYTES = 1 << 30  # ceilings.measure's stream copy: bytes read (and written) per launch
 
 
-def adjoint_source_hash() -> str:
+def kernel_source_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for name in ADJ_SOURCES:
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2509_14442_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -142,30 +151,135 @@ def launch_desc(l) -> dict:
             "persistent": bool(l.persistent), "blocks_per_cu": int(l.blocks_per_cu)}
 
 
-def traffic_config(args, W) -> dict:
-    """What the adjoint's counters depend on: workload, storage, stride and its launch."""
-    l = W.adj_launch
-    return {"workload": args.workload, "tracer": args.tracer, "dtype": W.fields[0].dtype,
-            "ckpt_stride": str(W.ckpt_stride), "spp": str(args.spp), "radiometry": str(args.radiometry),
-            "adj_launch": "%dx%d wpb %d persistent %d bpc %d" % (l.tile_w, l.tile_h, l.waves_per_block,
-                                                                 l.persistent, l.blocks_per_cu)}
+def _launch_str(l) -> str:
+    return "%dx%d wpb %d persistent %d bpc %d" % (l.tile_w, l.tile_h, l.waves_per_block, l.persistent,
+                                                  l.blocks_per_cu)
 
 
-def read_traffic(path, args, W):
-    """HBM bytes per adjoint launch from the counter summary, or None when there is none,
-    it was taken on another configuration, or the kernel has changed since."""
+def counter_key(args, storage_name, ckpt, fwd_launch, adj_launch) -> str:
+    """What the counters depend on: workload, tracer, storage, stride, samples and launches."""
+    return ("%s|%s|%s|k%d|spp%d|radio%d|fwd %s|adj %s" % (args.workload, args.tracer, storage_name, ckpt,
+                                                           args.spp, args.radiometry, _launch_str(fwd_launch),
+                                                           _launch_str(adj_launch)))
+
+
+def read_counters(path, key):
+    """Per-launch counters {name: value} of the block recorded for `key`, or None when there is
+    none or the kernels have changed since."""
     if not path or not os.path.exists(path):
         return None
-    kv = {}
+    blocks, cur = [], {}
     with open(path) as f:
         for line in f:
-            if line.startswith("    ") and ": " in line:
+            if line.strip() == "---":
+                blocks.append(cur)
+                cur = {}
+            elif line.startswith("    ") and ": " in line:
                 k, v = line.strip().split(": ", 1)
-                kv[k] = v
-    want = dict(traffic_config(args, W), source_sha256=adjoint_source_hash())
-    if any(kv.get(k) != v for k, v in want.items()) or "hbm_bytes_per_launch" not in kv:
-        return None
-    return float(kv["hbm_bytes_per_launch"])
+                cur[k] = v
+    blocks.append(cur)
+    h = kernel_source_hash()
+    for b in blocks:
+        if b.get("key") == key and b.get("source_sha256") == h:
+            return {k: float(v) for k, v in b.items() if k not in ("key", "source_sha256")}
+    return None
+
+
+# dispatches of `bench.py --profile-kernels`, in order: the forward of the target image and
+# 3 forwards without checkpoints; 3 steps (forward with checkpoints, render, adjoint); then
+# the ceilings with 2 warm-up launches and 1 timed launch each (the scattered gather twice:
+# the L2-resident footprint, then the 1 GiB one). The last launch of each group is used.
+PROFILE_GROUPS = {
+    "fwd": ("k_trace_fwd", 1, 4),
+    "fwdck": ("k_trace_fwd", 4, 7),
+    "adj": ("k_trace_adj", 0, 3),
+    "copy": ("k_copy", 0, 3),
+    "gather": ("k_gather_coherent<32>", 0, 3),
+    "l2gather": ("k_gather_scattered<32>", 0, 3),
+}
+COUNTER_NAMES = {
+    "TCP_TOTAL_CACHE_ACCESSES_sum": "tcp_accesses", "TCP_TCC_READ_REQ_sum": "tcp_tcc_read_req",
+    "TCP_TCC_WRITE_REQ_sum": "tcp_tcc_write_req", "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum": "tcp_tcc_atomic_req",
+    "TCC_HIT_sum": "tcc_hit", "TCC_MISS_sum": "tcc_miss", "TCC_REQ_sum": "tcc_req", "TCC_EA0_RDREQ_sum": "tcc_ea_rdreq",
+    "FETCH_SIZE": "fetch_kib", "WRITE_SIZE": "write_kib", "SQ_INSTS_VALU": "valu_insts",
+    "SQ_INSTS_VMEM_RD": "vmem_rd_insts", "SQ_INSTS_LDS": "lds_insts", "SQ_WAVES": "waves",
+    "SQ_WAIT_INST_ANY": "wait_inst_any", "SQ_WAVE_CYCLES": "wave_cycles", "SQ_INSTS_SALU": "salu_insts",
+    "SQ_INSTS_VALU_FMA_F32": "valu_fma_f32", "GRBM_GUI_ACTIVE": "gui_active",
+}
+
+
+def write_counters(args):
+    """Summarise rocprofv3 counter_collection.csv files of a --profile-kernels run into a
+    block of the counters file (replacing the block of the same configuration)."""
+    import csv
+    import glob
+
+    import torch  # noqa: F401  (struct types only; no device use)
+
+    from paper_2509_14442_amd import api
+
+    fwd, adj = launches(args)
+    key = counter_key(args, storage(args), args.ckpt, fwd, adj)
+    per = {}  # (group, counter) -> value of the group's last dispatch
+    for d in args.counter_dirs:
+        for fn in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            disp = {}
+            with open(fn) as f:
+                for r in csv.DictReader(f):
+                    kname = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+                    k = (int(r["Dispatch_Id"]), kname, r["Counter_Name"])
+                    disp[k] = disp.get(k, 0.0) + float(r["Counter_Value"])
+            for g, (pat, lo, hi) in PROFILE_GROUPS.items():
+                ids = sorted({i for (i, kn, _) in disp if pat in kn})
+                if len(ids) < hi:
+                    continue
+                last = ids[hi - 1]
+                for (i, kn, cn), v in disp.items():
+                    if i == last and cn in COUNTER_NAMES:
+                        per[(g, COUNTER_NAMES[cn])] = v
+    fetch_scale = CEIL_COPY_BYTES / 1024 / per[("copy", "fetch_kib")] if ("copy", "fetch_kib") in per else None
+    write_scale = CEIL_COPY_BYTES / 1024 / per[("copy", "write_kib")] if ("copy", "write_kib") in per else None
+    lines = ["    key: " + key, "    source_sha256: " + kernel_source_hash()]
+    if fetch_scale and write_scale:
+        lines += ["    calib.fetch_scale: %.4f" % fetch_scale, "    calib.write_scale: %.4f" % write_scale]
+    for (g, c), v in sorted(per.items()):
+        lines.append("    %s.%s: %.6g" % (g, c, v))
+        if c == "fetch_kib" and fetch_scale:
+            lines.append("    %s.hbm_read_bytes: %.6g" % (g, v * 1024 * fetch_scale))
+        if c == "write_kib" and write_scale:
+            lines.append("    %s.hbm_write_bytes: %.6g" % (g, v * 1024 * write_scale))
+    block = "\n".join(lines)
+    out = args.write_counters
+    text = open(out).read() if os.path.exists(out) else ""
+    head, blocks = text, []
+    if "\n    key: " in text:
+        head = text[:text.index("\n    key: ") + 1]
+        blocks = [b for b in text[len(head):].split("\n    ---\n")]
+    blocks = [b.rstrip("\n") for b in blocks if b.strip() and ("key: " + key + "\n") not in b + "\n"]
+    blocks.append(block)
+    if not head:
+        head = ("# Hardware counters per launch of the tracer kernels (see `bench.py --write-counters`)\n\n")
+    with open(out, "w") as f:
+        f.write(head + "\n    ---\n".join(blocks) + "\n")
+    print("wrote block", key, "to", out)
+
+
+def profile_kernels(args, dev):
+    """A fixed dispatch sequence for the counter runs (see PROFILE_GROUPS)."""
+    import torch
+
+    from paper_2509_14442_amd import ceilings
+
+    W = Workload(args, dev)
+    for _ in range(3):
+        W.fwd_only.forward()
+    for _ in range(3):
+        W.step()
+    torch.cuda.synchronize()
+    ceilings.measure(dev, reps=1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": counter_key(args, W.fields[0].dtype, W.ckpt_stride, W.launch, W.adj_launch)}),
+          flush=True)
 
 
 def calibrate_copy():
@@ -349,6 +463,9 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.write_counters:
+        write_counters(args)
+        return
     if args.ceilings:
         import torch
 
@@ -363,6 +480,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_kernels:
+        args.tune = 0
+        profile_kernels(args, dev)
+        return
     W = Workload(args, dev)
     tr = W.tracer
 
@@ -451,7 +572,10 @@ def main():
     flop_adj = FLOP_ADJ_STEP_QL if ql else FLOP_ADJ_STEP
     flop_fwd = FLOP_FWD_STEP_QL if ql else FLOP_FWD_STEP
     achieved = flop_adj * ray_steps / adj_s / 1e12
-    traffic = read_traffic(args.traffic, args, W)
+    cnt = read_counters(args.counters, counter_key(args, W.fields[0].dtype, W.ckpt_stride, W.launch, W.adj_launch))
+    traffic = None
+    if cnt is not None and "adj.hbm_read_bytes" in cnt and "adj.hbm_write_bytes" in cnt:
+        traffic = cnt["adj.hbm_read_bytes"] + cnt["adj.hbm_write_bytes"]
     ceil = None
     if not args.no_ceilings:
         from paper_2509_14442_amd import ceilings
@@ -533,6 +657,28 @@ def main():
                 got = per_step * ray_steps / t / 1e12
                 r["vl1d"] = {"bytes_per_ray_step": per_step, "achieved_tbps": got, "ceiling_tbps": cg,
                              "frac": got / cg}
+        if cnt is not None:
+            # counter rates of this launch against the same counters of the ceiling kernels
+            for key, g, t in (("roofline", "adj", adj_s), ("roofline_fwd", "fwd", fwd_kernel_ms * 1e-3)):
+                r = out[key]
+                m = {}
+                if g + ".tcp_accesses" in cnt and "gather.tcp_accesses" in cnt:
+                    a = cnt[g + ".tcp_accesses"] / t
+                    c = cnt["gather.tcp_accesses"] / (ceil["ms"]["gather"] * 1e-3)
+                    m["vl1d_accesses"] = {"achieved_per_s": a, "ceiling_per_s": c, "frac": a / c,
+                                          "per_launch": cnt[g + ".tcp_accesses"]}
+                if g + ".tcc_req" in cnt and "l2gather.tcc_req" in cnt:
+                    a = cnt[g + ".tcc_req"] / t
+                    c = cnt["l2gather.tcc_req"] / (ceil["ms"]["l2gather"] * 1e-3)
+                    m["l2_requests"] = {"achieved_per_s": a, "ceiling_per_s": c, "frac": a / c,
+                                        "per_launch": cnt[g + ".tcc_req"],
+                                        "hit_rate": cnt.get(g + ".tcc_hit", 0.0) / max(cnt[g + ".tcc_req"], 1.0)}
+                if g + ".hbm_read_bytes" in cnt and g + ".hbm_write_bytes" in cnt:
+                    b = cnt[g + ".hbm_read_bytes"] + cnt[g + ".hbm_write_bytes"]
+                    m["hbm"] = {"bytes_per_launch": b, "achieved_tbps": b / t / 1e12,
+                                "ceiling_tbps": ceil["hbm_copy_tbps"], "frac": b / t / 1e12 / ceil["hbm_copy_tbps"],
+                                "frac_of_peak": b / t / PEAK_HBM_BYTES_PER_S}
+                r["memory"] = m
         out["ceilings"] = ceil
     if hasattr(W, "tuned"):
         out["config"]["autotune"] = W.tuned

@@ -59,12 +59,14 @@ def measure(dev="cuda:0", reps: int = 5) -> Dict[str, float]:
     lib = load()
     n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     out: Dict[str, float] = {}
+    times: Dict[str, float] = {}  # ms per launch of each ceiling kernel
 
     # plain FP32 FMA rate: 8 wavefronts per SIMD on every compute unit
     blocks, iters = 16 * n_cu, 4096
     buf = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
     ms = _time_ms(lambda s: lib.ceil_fma(C.c_void_p(buf.data_ptr()), blocks, iters, s), reps)
     out["fma_fp32_tflops"] = blocks * 256 * iters * 32 / (ms * 1e-3) / 1e12
+    times["fma"] = ms
 
     # HBM stream copy: 1 GiB read + 1 GiB written
     nbytes = 1 << 30
@@ -73,6 +75,7 @@ def measure(dev="cuda:0", reps: int = 5) -> Dict[str, float]:
     ms = _time_ms(lambda s: lib.ceil_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nbytes,
                                           4 * n_cu * 8, s), reps)
     out["hbm_copy_tbps"] = 2 * nbytes / (ms * 1e-3) / 1e12
+    times["copy"] = ms
     del a, b
 
     # coherent cell-record gathers over the headline field's record grid (129^3 cells
@@ -86,6 +89,7 @@ def measure(dev="cuda:0", reps: int = 5) -> Dict[str, float]:
         ms = _time_ms(lambda s: lib.ceil_gather_coherent(C.c_void_p(recs.data_ptr()), rec_bytes, px, py, pz, w, h,
                                                          steps, C.c_void_p(o.data_ptr()), s), reps)
         out[key] = w * h * steps * 3 * rec_bytes / (ms * 1e-3) / 1e12
+        times["gather" if rec_bytes == 32 else "gather16"] = ms
         del recs, o
 
     # scattered 32-byte gathers within 2 MiB (L2-resident, a separate line per access)
@@ -97,6 +101,7 @@ def measure(dev="cuda:0", reps: int = 5) -> Dict[str, float]:
         ms = _time_ms(lambda s: lib.ceil_gather_scattered(C.c_void_p(recs.data_ptr()), 32, log2_n, blocks, iters,
                                                           C.c_void_p(o.data_ptr()), s), reps)
         out[key] = blocks * 256 * iters * 32 / (ms * 1e-3) / 1e12
+        times["l2gather" if log2_n == 16 else "hbmgather"] = ms
         del recs, o
 
     # FP64 atomic adds into a 128^3 gradient, 8 lanes per cell
@@ -104,6 +109,8 @@ def measure(dev="cuda:0", reps: int = 5) -> Dict[str, float]:
     blocks, iters = 16 * n_cu, 64
     ms = _time_ms(lambda s: lib.ceil_atomic_f64(C.c_void_p(g.data_ptr()), 128, 128, 128, blocks, iters, s), reps)
     out["atomic_f64_per_s"] = blocks * 256 * iters / (ms * 1e-3)
+    times["atomic"] = ms
     del g
     torch.cuda.synchronize()
+    out["ms"] = times
     return out

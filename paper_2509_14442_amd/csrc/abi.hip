@@ -276,6 +276,8 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
     d.c_p3[a] = (float)(h * h / 2.0 * km);
     d.c_x[a] = (float)(h * h / 6.0 * km);
     d.c_v[a] = (float)(h / 6.0 * km);
+    d.km_h[a] = (float)(h * km);
+    d.km_h6[a] = (float)(h / 6.0 * km);
   }
   d.max_steps = S->max_steps;
   d.ckpt_k = S->ckpt_stride > 0 ? S->ckpt_stride : 1;

@@ -46,7 +46,7 @@ __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, Sam
 
 // Reverse of K = force(P) for an adjoint v = dL/dK: returns p = dL/dP (grid units) and
 // the sample's contributions to dL/d(delta_c) for the 8 corners of its cell,
-//   w_a = v_a km_a,  sigma = sum_a w_a g_a,
+//   w_a = v_a km_a (km_a = dec / voxel_a^2),  sigma = sum_a w_a g_a,
 //   p_b = dec g_b sigma + eta sum_{a != b} w_a H_ab,
 //   dL/d delta_c = w_c sigma + sum_a W_a dw_c/du_a,  W_a = (eta / dec) w_a,
 // with w_c the trilinear weight of corner c. The contributions are multilinear in the
@@ -56,9 +56,11 @@ __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, Sam
 // values follow from the totals (corner_of_monomials). In apron cells the field is
 // constant along the clamped axis (g and H vanish there); the two corners that share one
 // edge voxel receive contributions that add up to the clamped-axis weights.
-__device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R, const float v[3], float p[3],
-                                          float M[8]) {
-  float w0 = v[0] * S.km[0], w1 = v[1] * S.km[1], w2 = v[2] * S.km[2];
+// The stage's adjoint arrives unscaled with its per-axis factor ks (h km, h km / 6, or km
+// when v already holds the h), so w = v ks.
+__device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R, const float v[3], const float ks[3],
+                                          float p[3], float M[8]) {
+  float w0 = v[0] * ks[0], w1 = v[1] * ks[1], w2 = v[2] * ks[2];
   float sigma = fmaf(w0, R.g[0], fmaf(w1, R.g[1], w2 * R.g[2]));
   float ds = S.dec * sigma;
   // H = (H_xy, H_xz, H_yz)
@@ -472,9 +474,9 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           for (int a = 0; a < 3; ++a) {
             ab[a] = fmaf(h_6, rb[a], tb[a] * (1.0f / 6.0f));
             bb[a] = fmaf(h * (1.0f / 3.0f), rb[a], tb[a] * (2.0f / 3.0f));
-            v[a] = h * (tb[a] * (1.0f / 6.0f));
+            v[a] = tb[a];  // h / 6 is in km_h6
           }
-          force_rev(S, R3, v, p, ct);
+          force_rev(S, R3, v, S.km_h6, p, ct);
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             bb[a] = fmaf(h_2, p[a], bb[a]);
@@ -485,10 +487,8 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
-          float v[3], p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) v[a] = h * bb[a];
-          force_rev(S, R2, v, p, ct);
+          float p[3];
+          force_rev(S, R2, bb, S.km_h, p, ct);  // v = h bb
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             ab[a] = fmaf(h * 0.125f, p[a], ab[a]);
@@ -499,10 +499,8 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
-          float v[3], p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) v[a] = h * ab[a];
-          force_rev(S, R1, v, p, ct);
+          float p[3];
+          force_rev(S, R1, ab, S.km_h, p, ct);  // v = h ab
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             rb[a] = rs[a] + p[a];
@@ -607,9 +605,9 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
           for (int a = 0; a < 3; ++a) {
             ab[a] = fmaf(h_6, rb[a], tb[a] * (1.0f / 6.0f));
             bb[a] = fmaf(h * (1.0f / 3.0f), rb[a], tb[a] * (2.0f / 3.0f));
-            v[a] = h * (tb[a] * (1.0f / 6.0f));
+            v[a] = tb[a];  // h / 6 is in km_h6
           }
-          force_rev(S, R3, v, p, ct);
+          force_rev(S, R3, v, S.km_h6, p, ct);
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             bb[a] = fmaf(h_2, p[a], bb[a]);
@@ -620,10 +618,8 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
-          float v[3], p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) v[a] = h * bb[a];
-          force_rev(S, R2, v, p, ct);
+          float p[3];
+          force_rev(S, R2, bb, S.km_h, p, ct);  // v = h bb
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             ab[a] = fmaf(h * 0.125f, p[a], ab[a]);
@@ -634,10 +630,8 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
         }
         accumulate(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
-          float v[3], p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) v[a] = h * ab[a];
-          force_rev(S, R1, v, p, ct);
+          float p[3];
+          force_rev(S, R1, ab, S.km_h, p, ct);  // v = h ab
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             rb[a] = rs[a] + p[a];
@@ -773,7 +767,7 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
       SampleRev Rs;
       sample_rev<DT>(S, C, Rs);
       float p[3];
-      force_rev(S, Rs, v, p, ct);
+      force_rev(S, Rs, v, S.km, p, ct);
       const float tj = jf * (0.5f * h);
 #pragma unroll
       for (int a = 0; a < 3; ++a) pv[a] = fmaf(tj, p[a], pv[a]);
