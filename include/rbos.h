@@ -210,9 +210,13 @@ const char* rbos_last_error(void);
 /* Bytes of the packed field for nx*ny*nz voxels and a storage format (0 if invalid).
    Cell records (RBOS_F32, RBOS_F16, RBOS_BF16): one record per interpolation cell
    (i, j, k), i in [-1, nx-1] etc., i.e. (nx+1)(ny+1)(nz+1) records in x-fastest order
-   starting at cell (-1, -1, -1); each holds the cell's 8 corner codes (32 B for FP32,
-   16 B for FP16/BF16), corner indices clamped to the grid (the apron cells repeat the
-   edge voxels). X-pairs (*_XPAIR): (nx+1)(ny+2)(nz+2) entries (i, j, k), i in [-1, nx-1],
+   starting at cell (-1, -1, -1), built from the cell's 8 corner codes q[a + 2b + 4c] at
+   voxels (clamp(i+a), clamp(j+b), clamp(k+c)) (the apron cells repeat the edge voxels).
+   FP16/BF16 records hold those 8 codes (16 B). FP32 records (32 B) hold the coefficients
+   of the cell's trilinear polynomial in its fractions, q0, q1 - q0, q2 - q0,
+   (q3 - q2) - (q1 - q0), q4 - q0, (q5 - q4) - (q1 - q0), (q6 - q4) - (q2 - q0),
+   ((q7 - q6) - (q5 - q4)) - ((q3 - q2) - (q1 - q0)), each difference rounded to binary32
+   in that order. X-pairs (*_XPAIR): (nx+1)(ny+2)(nz+2) entries (i, j, k), i in [-1, nx-1],
    j in [-1, ny], k in [-1, nz], x fastest, each holding the codes of voxels
    (clamp(i), clamp(j), clamp(k)) and (clamp(i+1), clamp(j), clamp(k)) (8 B FP32, 4 B
    for two 16-bit codes, low half first). */

@@ -1,6 +1,7 @@
 // field_pack.hip -- Sec. 2.A: eta - 1 from temperature and its storage codes, written
-// as cell records (the 8 corner codes of each interpolation cell, contiguous), plus two
-// small utility kernels (table upload through kernel arguments, counter fill).
+// as cell records (per interpolation cell, contiguous: the trilinear coefficients for FP32,
+// the 8 corner codes for 16-bit storage) or as x-pairs, plus two small utility kernels
+// (table upload through kernel arguments, counter fill).
 #include "rbos_device.hpp"
 #include "rbos_launch.hpp"
 
@@ -46,9 +47,12 @@ __global__ __launch_bounds__(256) void k_field_pack(int nx, int ny, int nz, cons
       q[c] = t * scale;
     }
     if (dtype == DT_F32) {
+      // FP32 records hold the cell's trilinear coefficients
+      float C[8];
+      corner_coefficients(q, C);
       float4* p = reinterpret_cast<float4*>(field) + 2 * (size_t)rec;
-      p[0] = make_float4(q[0], q[1], q[2], q[3]);
-      p[1] = make_float4(q[4], q[5], q[6], q[7]);
+      p[0] = make_float4(C[0], C[1], C[2], C[3]);
+      p[1] = make_float4(C[4], C[5], C[6], C[7]);
     } else {
       uint4 w;
       w.x = code16(q[0], dtype) | (code16(q[1], dtype) << 16);

@@ -406,10 +406,12 @@ __device__ __forceinline__ bool wall_hit_straight(const SceneDev& S, const df di
 // ------------------------------------------------------------------------------------
 // field: cell records or x-pairs, and the trilinear sampler
 // ------------------------------------------------------------------------------------
-// Cell records: the record of cell (i, j, k), i in [-1, n-1] per axis, holds the 8 corner
-// codes q[a + 2b + 4c] = code(clamp(i+a), clamp(j+b), clamp(k+c)), indices clamped to the
-// grid. FP32: 8 floats (32 B). FP16/BF16: 8 x 16-bit (16 B), two per 32-bit word. One
-// sample is one 32-byte (two 16-byte loads) or 16-byte load at the record index
+// Cell records: the record of cell (i, j, k), i in [-1, n-1] per axis, is built from the 8
+// corner codes q[a + 2b + 4c] = code(clamp(i+a), clamp(j+b), clamp(k+c)), indices clamped
+// to the grid. FP16/BF16: the 8 codes, 16 bits each (16 B), two per 32-bit word. FP32: the
+// 8 coefficients of the cell's trilinear polynomial in its fractions (u, v, w) (32 B, see
+// corner_coefficients), so that value and derivatives need no differences. One sample is
+// one 32-byte (two 16-byte loads) or 16-byte load at the record index
 // rec = p0 + P0 p1 + P01 p2 of the padded cell (p = i + 1).
 // X-pairs: entry (p0, r1, r2), p0 in [0, nx], r1 in [0, ny + 1], r2 in [0, nz + 1], holds
 // the codes of voxels (clamp(p0 - 1), y, z) and (clamp(p0), y, z) with y = clamp(r1 - 1),
@@ -417,8 +419,9 @@ __device__ __forceinline__ bool wall_hit_straight(const SceneDev& S, const df di
 // p = (p0, p1, p2) reads the four entries rec, rec + P0, rec + P01, rec + P0 + P01 with
 // rec = p0 + P0 p1 + P01 p2: four loads of 8 or 4 bytes instead of one record, over an
 // array 4 (16-bit) to 8 (FP32) times smaller than the cell records.
+// The 8 stored values of cell `rec`: the FP32 record's coefficients, else the corner codes.
 template <int DT>
-__device__ __forceinline__ void fetch_cell(const SceneDev& S, unsigned int rec, float c[8]) {
+__device__ __forceinline__ void fetch_corners(const SceneDev& S, unsigned int rec, float c[8]) {
   // 32-bit byte offsets from the array start (at most 449^3 records of 32 B < 4 GiB), so
   // the load takes the array base from SGPRs and the offset from one VGPR
   const unsigned char* base = static_cast<const unsigned char*>(S.field);
@@ -467,6 +470,37 @@ __device__ __forceinline__ void fetch_cell(const SceneDev& S, unsigned int rec, 
   }
 }
 
+// Coefficients of the trilinear polynomial of a cell from its corner values q (index
+// a + 2b + 4c): q(u, v, w) = sum_m C[m] u^(m & 1) v^(m >> 1 & 1) w^(m >> 2), i.e.
+//   C0 = q0, C1 = q1 - q0, C2 = q2 - q0, C4 = q4 - q0,
+//   C3 = (q3 - q2) - C1, C5 = (q5 - q4) - C1, C6 = (q6 - q4) - C2,
+//   C7 = ((q7 - q6) - (q5 - q4)) - C3.
+// The field encoder writes FP32 records this way (same operations, same order).
+__host__ __device__ __forceinline__ void corner_coefficients(const float q[8], float C[8]) {
+  const float d1 = q[1] - q[0], d3 = q[3] - q[2], d5 = q[5] - q[4], d7 = q[7] - q[6];
+  C[0] = q[0];
+  C[1] = d1;
+  C[2] = q[2] - q[0];
+  C[4] = q[4] - q[0];
+  C[3] = d3 - d1;
+  C[5] = d5 - d1;
+  C[6] = (q[6] - q[4]) - C[2];
+  C[7] = (d7 - d5) - C[3];
+}
+
+// The trilinear coefficients C[8] of cell `rec` (see corner_coefficients).
+template <int DT>
+__device__ __forceinline__ void fetch_cell(const SceneDev& S, unsigned int rec, float C[8]) {
+  float c[8];
+  fetch_corners<DT>(S, rec, c);
+  if constexpr (DT == DT_F32) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) C[k] = c[k];  // FP32 records hold the coefficients
+  } else {
+    corner_coefficients(c, C);
+  }
+}
+
 // Locate one axis: the point is u = bhi + small grid units (grid units count from one
 // cell below the first voxel centre: u = (x - lo) / voxel + 1/2), with bhi exact. The
 // padded cell index is p = floor(u) (cell i = p - 1 between centres i and i + 1) and
@@ -511,38 +545,37 @@ __device__ __forceinline__ void cell_of_record(const SceneDev& S, unsigned r, in
   p[2] = (int)z;
 }
 
-// Trilinear value q and its grid-unit gradient from the 8 corners.
-__device__ __forceinline__ void trilinear(const float c[8], const float f[3], float& q, float g[3]) {
-  float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
-  float a00 = fmaf(f[0], d00, c[0]), a10 = fmaf(f[0], d10, c[2]);
-  float a01 = fmaf(f[0], d01, c[4]), a11 = fmaf(f[0], d11, c[6]);
-  float e0 = a10 - a00, e1 = a11 - a01;
-  float b0 = fmaf(f[1], e0, a00), b1 = fmaf(f[1], e1, a01);
-  float gx0 = fmaf(f[1], d10 - d00, d00), gx1 = fmaf(f[1], d11 - d01, d01);
-  float dz = b1 - b0;
-  q = fmaf(f[2], dz, b0);
-  g[0] = fmaf(f[2], gx1 - gx0, gx0);
-  g[1] = fmaf(f[2], e1 - e0, e0);
-  g[2] = dz;
+// Trilinear value q and its grid-unit gradient from the cell's coefficients C (see
+// corner_coefficients) at the fractions f = (u, v, w): 11 fused multiply-adds.
+__device__ __forceinline__ void trilinear(const float C[8], const float f[3], float& q, float g[3]) {
+  const float u = f[0], v = f[1], w = f[2];
+  const float t1 = fmaf(w, C[7], C[3]);                  // C3 + w C7
+  const float gu = fmaf(w, C[5], fmaf(v, t1, C[1]));      // C1 + v C3 + w C5 + v w C7
+  const float t3 = fmaf(w, C[6], C[2]);                  // C2 + w C6
+  const float t5 = fmaf(v, C[7], C[5]);                  // C5 + v C7
+  const float t6 = fmaf(v, C[6], C[4]);                  // C4 + v C6
+  g[0] = gu;
+  g[1] = fmaf(u, t1, t3);
+  g[2] = fmaf(u, t5, t6);
+  q = fmaf(u, gu, fmaf(v, t3, fmaf(w, C[4], C[0])));
 }
 
-// Same, plus the mixed second derivatives H = (q_xy, q_xz, q_yz).
-__device__ __forceinline__ void trilinear_h(const float c[8], const float f[3], float& q, float g[3], float H[3]) {
-  float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
-  float a00 = fmaf(f[0], d00, c[0]), a10 = fmaf(f[0], d10, c[2]);
-  float a01 = fmaf(f[0], d01, c[4]), a11 = fmaf(f[0], d11, c[6]);
-  float e0 = a10 - a00, e1 = a11 - a01;
-  float b0 = fmaf(f[1], e0, a00), b1 = fmaf(f[1], e1, a01);
-  float x0 = d10 - d00, x1 = d11 - d01;
-  float gx0 = fmaf(f[1], x0, d00), gx1 = fmaf(f[1], x1, d01);
-  float dz = b1 - b0;
-  q = fmaf(f[2], dz, b0);
-  g[0] = fmaf(f[2], gx1 - gx0, gx0);
-  g[1] = fmaf(f[2], e1 - e0, e0);
-  g[2] = dz;
-  H[0] = fmaf(f[2], x1 - x0, x0);  // d2q / dx dy
-  H[1] = gx1 - gx0;                // d2q / dx dz
-  H[2] = e1 - e0;                  // d2q / dy dz
+// Same, plus the mixed second derivatives H = (q_uv, q_uw, q_vw); q and g are computed with
+// exactly the operations of trilinear.
+__device__ __forceinline__ void trilinear_h(const float C[8], const float f[3], float& q, float g[3], float H[3]) {
+  const float u = f[0], v = f[1], w = f[2];
+  const float t1 = fmaf(w, C[7], C[3]);
+  const float gu = fmaf(w, C[5], fmaf(v, t1, C[1]));
+  const float t3 = fmaf(w, C[6], C[2]);
+  const float t5 = fmaf(v, C[7], C[5]);
+  const float t6 = fmaf(v, C[6], C[4]);
+  g[0] = gu;
+  g[1] = fmaf(u, t1, t3);
+  g[2] = fmaf(u, t5, t6);
+  q = fmaf(u, gu, fmaf(v, t3, fmaf(w, C[4], C[0])));
+  H[0] = t1;                    // d2q / dx dy
+  H[1] = t5;                    // d2q / dx dz
+  H[2] = fmaf(u, C[7], C[6]);   // d2q / dy dz
 }
 
 // Force of Eq. (1) in code units from a cell's corner codes and the fractions:

@@ -68,8 +68,20 @@ def test_field_codes_bit_exact(dtype, offset):
     assert field.scale == scale
     d32 = oracle.delta_from_temperature_f32(w.T32, RHO0G, T0)
     ref = oracle.encode(d32, CODES[dtype], scale, offset)
-    ref = ref.view(np.uint32) if dtype == "f32" else ref
-    assert np.array_equal(got, _expected_records(ref))
+    if dtype == "f32":
+        # FP32 records hold the trilinear coefficients of each cell, differences of the
+        # corner codes rounded to binary32 in the documented order
+        q = _expected_records(ref).astype(np.float32)
+        d1, d3, d5, d7 = q[..., 1] - q[..., 0], q[..., 3] - q[..., 2], q[..., 5] - q[..., 4], q[..., 7] - q[..., 6]
+        C = np.empty_like(q)
+        C[..., 0], C[..., 1] = q[..., 0], d1
+        C[..., 2], C[..., 4] = q[..., 2] - q[..., 0], q[..., 4] - q[..., 0]
+        C[..., 3], C[..., 5] = d3 - d1, d5 - d1
+        C[..., 6] = (q[..., 6] - q[..., 4]) - C[..., 2]
+        C[..., 7] = (d7 - d5) - C[..., 3]
+        assert np.array_equal(got, C.view(np.uint32))
+    else:
+        assert np.array_equal(got, _expected_records(ref))
     if dtype != "f32":
         q = oracle.decode(ref, CODES[dtype], scale, 0.0) * scale
         assert np.abs(q).max() <= 2 ** 14  # scale keeps the codes in range
