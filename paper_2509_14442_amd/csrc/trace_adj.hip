@@ -96,13 +96,26 @@ __device__ __forceinline__ double corner_of_monomials(const float* vals, int c) 
   return g;
 }
 
-// Per-lane merge of the samples' monomial coefficients by cell, flushed across the wavefront.
+// Per-lane merge of the samples' monomial coefficients by cell. A lane that leaves a cell
+// parks its sums. With PARK (kernels with registers to spare), the parked sums of a cell
+// are reduced across the wavefront when one of its lanes leaves a second cell (its park
+// is needed again), together with those of every other lane parked in that cell: the
+// tile's rays leave a cell over a few samples, so one reduction then covers most of them.
+// Without, the lanes leaving cells at a sample are reduced at once.
 constexpr int CELL_NONE = INT_MIN;
 
 struct Accum {
   float acc[8];
-  int key;  // record index of the cell (< 2^27), CELL_NONE when empty
+  int key;        // record index of the cell (< 2^27), CELL_NONE when empty
+  float park[8];  // the sums of the last cell left
+  int pkey;       // its record index, CELL_NONE when the park is free
 };
+
+__device__ __forceinline__ void accum_init(Accum& A) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) A.acc[k] = A.park[k] = 0.0f;
+  A.key = A.pkey = CELL_NONE;
+}
 
 // Sum 8 per-lane values over the 64 lanes, all eight at once: each exchange step halves
 // the lanes per value and keeps the values apart (permlane32 / permlane16 swaps between
@@ -163,13 +176,44 @@ __device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, i
 // wavefront's LDS instructions in order; this keeps the compiler from moving them).
 __device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// Add the accumulators of lanes with `sel` to the cache: lanes that hold the same cell
-// are summed across the wavefront, then the 8 totals go into that cell's slot. Must run
-// with all 64 lanes active.
+// Corner of the total that lane group g = lane / 8 holds after wave_sum8.
+__device__ __forceinline__ int group_corner(int lane) {
+  const int g = lane >> 3;
+  return (g & 4) | ((g & 1) << 1) | ((g >> 1) & 1);
+}
+
+// Add the 8 wavefront totals of cell `key` (wave_sum8's layout) to its slot, taking a
+// free slot, or writing one out, when the cell has none.
+__device__ __forceinline__ void cache_add(const SceneDev& S, Pending& P, int key, float total, int lane) {
+  const int corner = group_corner(lane);
+  const unsigned long long hit = __ballot(P.key == key);
+  int slot;
+  if (hit) {
+    slot = __ffsll((long long)hit) - 1;
+    if ((lane & 7) == 0) atomicAdd(&P.vals[slot * 8 + corner], total);
+  } else {
+    const unsigned long long freem = ~P.occupied & ((1ull << PEND_SLOTS) - 1);
+    if (freem) {
+      slot = __ffsll((long long)freem) - 1;
+    } else {
+      slot = P.next;
+      P.next = (P.next + 1) & (PEND_SLOTS - 1);
+      const int old = __builtin_amdgcn_readlane(P.key, slot);
+      if (lane < 8) gatomic_add(voxel_of_corner(S, old, lane), corner_of_monomials(P.vals + slot * 8, lane));
+      wave_lds_order();
+    }
+    if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
+    if (lane == slot) P.key = key;
+    P.occupied |= 1ull << slot;
+  }
+  P.touched |= 1ull << slot;
+  wave_lds_order();
+}
+
+// Add the accumulators of lanes with `sel` to the cache (lanes that hold the same cell
+// summed across the wavefront) and restart them. Must run with all 64 lanes active.
 __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int lane, Pending& P) {
   unsigned long long pend = __ballot(sel);
-  const int g = lane >> 3;
-  const int corner = (g & 4) | ((g & 1) << 1) | ((g >> 1) & 1);  // corner of this group's total
   while (pend) {
     const int leader = __ffsll((long long)pend) - 1;
     const int key = __builtin_amdgcn_readlane(A.key, leader);
@@ -177,35 +221,30 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
     float v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = mine ? A.acc[k] : 0.0f;
-    const float total = wave_sum8(v);
-    const unsigned long long hit = __ballot(P.key == key);
-    int slot;
-    if (hit) {
-      slot = __ffsll((long long)hit) - 1;
-      if ((lane & 7) == 0) atomicAdd(&P.vals[slot * 8 + corner], total);
-    } else {
-      const unsigned long long freem = ~P.occupied & ((1ull << PEND_SLOTS) - 1);
-      if (freem) {
-        slot = __ffsll((long long)freem) - 1;
-      } else {
-        slot = P.next;
-        P.next = (P.next + 1) & (PEND_SLOTS - 1);
-        const int old = __builtin_amdgcn_readlane(P.key, slot);
-        if (lane < 8) gatomic_add(voxel_of_corner(S, old, lane), corner_of_monomials(P.vals + slot * 8, lane));
-        wave_lds_order();
-      }
-      if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
-      if (lane == slot) P.key = key;
-      P.occupied |= 1ull << slot;
-    }
-    P.touched |= 1ull << slot;
-    wave_lds_order();
+    cache_add(S, P, key, wave_sum8(v), lane);
     pend &= ~__ballot(mine);
   }
-  // the flushed lanes restart their sums (accumulate then only adds)
   if (sel) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
+  }
+}
+
+// For every cell parked by a lane with `trig`: the parks of all lanes holding that cell
+// go to the cache, summed across the wavefront, and are freed. Must run with all 64
+// lanes active.
+__device__ __forceinline__ void flush_parks(const SceneDev& S, Accum& A, bool trig, int lane, Pending& P) {
+  unsigned long long pend = __ballot(trig);
+  while (pend) {
+    const int leader = __ffsll((long long)pend) - 1;
+    const int key = __builtin_amdgcn_readlane(A.pkey, leader);
+    const bool mine = A.pkey == key;
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = mine ? A.park[k] : 0.0f;
+    cache_add(S, P, key, wave_sum8(v), lane);
+    pend &= ~__ballot(mine);
+    if (mine) A.pkey = CELL_NONE;
   }
 }
 
@@ -233,17 +272,40 @@ __device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lan
 }
 
 // Merge one sample's monomial coefficients (lanes with act) into the accumulators. A lane
-// that enters a new cell has had its sums flushed and zeroed (or never held any).
+// that enters a new cell parks the sums of the one it leaves (after its park has been
+// flushed, if taken) and starts from zero.
+template <bool PARK>
 __device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
                                            int lane, Pending& P) {
-  const bool change = act && key != A.key;
-  const bool out = change && A.key != CELL_NONE;
-  if (__ballot(out)) flush(S, A, out, lane, P);
+  const bool out = act && key != A.key && A.key != CELL_NONE;
+  if (__ballot(out)) {
+    if (PARK) {
+      const bool busy = out && A.pkey != CELL_NONE;
+      if (__ballot(busy)) flush_parks(S, A, busy, lane, P);
+      if (out) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          A.park[k] = A.acc[k];
+          A.acc[k] = 0.0f;
+        }
+        A.pkey = A.key;
+      }
+    } else {
+      flush(S, A, out, lane, P);
+    }
+  }
   if (act) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) A.acc[k] += ct[k];
     A.key = key;
   }
+}
+
+// Tile end: the parks, then the open accumulators, into the cache; every slot out.
+__device__ __forceinline__ void drain(const SceneDev& S, Accum& A, Pending& P, int lane) {
+  if (__ballot(A.pkey != CELL_NONE)) flush_parks(S, A, A.pkey != CELL_NONE, lane, P);
+  flush(S, A, A.key != CELL_NONE, lane, P);
+  if (P.occupied) write_out(S, P, P.occupied, lane);
 }
 
 __device__ __forceinline__ void load_ckpt(const SceneDev& S, int r, int slot, State& st) {
@@ -261,6 +323,16 @@ __device__ __forceinline__ void locate_state(const SceneDev& S, const RayBase& B
   for (int a = 0; a < 3; ++a) sm[a] = small_part(B, a, st.jf, st.d[a]);
   locate3(S, st.bh, sm, C);
 }
+
+// Occupancy: chunks of 8 steps take 13 KB of LDS per wavefront, so 3 wavefronts per SIMD;
+// chunks of 6 take 10 KB, and 4 fit when the registers are held to 128.
+template <int KS>
+constexpr int adj_waves_per_simd() { return KS == 6 ? 4 : 3; }
+
+// Recording form: chunks of 4 steps take 13 KB of LDS per wavefront (3 wavefronts per
+// SIMD), chunks of 3 take 10 KB (4 per SIMD with the registers held to 128).
+template <int KS>
+constexpr int rec_waves_per_simd() { return KS == 3 ? 4 : 3; }
 
 // LDS per wavefront: the replayed step-start states of one chunk, slot (i, component) of
 // lane l at replay[(i * 6 + c) * 64 + l] (conflict-free), then the cell-total cache.
@@ -329,6 +401,7 @@ __device__ __forceinline__ void adjoint_ray_setup(const SceneDev& S, int tile, i
 // Initial condition v0 = (1 + delta(x0)) dir: dL/d delta_c += w_c(x0) sum_a tb0_a dir_a /
 // voxel_a, with tb0 = dL/dv0 in grid units and V = v0 (m per unit t). Contributions of
 // lanes with `active`.
+template <bool PARK>
 __device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, const float V[3], bool active,
                                            const float tb0[3], Accum& A, Pending& P, int lane) {
   int key0 = 0;
@@ -352,11 +425,12 @@ __device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, 
     c0v[7] = c0v[3] * w;
     key0 = (int)cell_index(S, C0);
   }
-  accumulate(S, A, active, key0, c0v, lane, P);
+  accumulate<PARK>(S, A, active, key0, c0v, lane, P);
 }
 
 template <int DT, int KS, bool STORED>
 __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int lane, float* __restrict__ replay) {
+  constexpr bool PARK = adj_waves_per_simd<KS>() == 3;  // registers for the parks
   AdjRay R;
   adjoint_ray_setup(S, tile, lane, R);
   const int q = R.q, n = R.n;
@@ -374,9 +448,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   const int nseg = wave_max_nonneg(nseg_lane);
 
   Accum A;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
-  A.key = CELL_NONE;
+  accum_init(A);
   Pending P{replay + KS * 6 * 64, CELL_NONE, 0, 0ull, 0ull};
   const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6;
 
@@ -485,7 +557,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           key = R3.key;
         }
-        accumulate(S, A, act, key, ct, lane, P);
+        accumulate<PARK>(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
           float p[3];
           force_rev(S, R2, bb, S.km_h, p, ct);  // v = h bb
@@ -497,7 +569,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           key = R2.key;
         }
-        accumulate(S, A, act, key, ct, lane, P);
+        accumulate<PARK>(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
           float p[3];
           force_rev(S, R1, ab, S.km_h, p, ct);  // v = h ab
@@ -508,7 +580,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
           }
           key = R1.key;
         }
-        accumulate(S, A, act, key, ct, lane, P);
+        accumulate<PARK>(S, A, act, key, ct, lane, P);
       }
       chunk_end(S, P, lane);
     }
@@ -519,9 +591,8 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 #pragma unroll
     for (int a = 0; a < 3; ++a) V0[a] = gld(S.ckpt + (size_t)q + (size_t)(12 + a) * (size_t)S.ckpt_pad);
   }
-  entry_term(S, B, V0, active, tb, A, P, lane);
-  flush(S, A, A.key != CELL_NONE, lane, P);
-  if (P.occupied) write_out(S, P, P.occupied, lane);
+  entry_term<PARK>(S, B, V0, active, tb, A, P, lane);
+  drain(S, A, P, lane);
 }
 
 // Recording form (checkpoint strides that are multiples of KS = 3 or 4): the replay of a
@@ -536,6 +607,7 @@ constexpr int rec_floats_per_wave() { return KS * 3 * 64 * 4 + PEND_SLOTS * 8; }
 
 template <int DT, int KS>
 __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, int lane, float* __restrict__ lds) {
+  constexpr bool PARK = rec_waves_per_simd<KS>() == 3;  // registers for the parks
   AdjRay R;
   adjoint_ray_setup(S, tile, lane, R);
   const int q = R.q, n = R.n;
@@ -548,9 +620,7 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
   const int nseg = wave_max_nonneg(active ? (n + K - 1) / K : 0);
 
   Accum A;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
-  A.key = CELL_NONE;
+  accum_init(A);
   Pending P{lds + KS * 3 * 64 * 4, CELL_NONE, 0, 0ull, 0ull};
   f32x4* smp = reinterpret_cast<f32x4*>(lds);
   const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6;
@@ -616,7 +686,7 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
           }
           key = R3.key;
         }
-        accumulate(S, A, act, key, ct, lane, P);
+        accumulate<PARK>(S, A, act, key, ct, lane, P);
         if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
           float p[3];
           force_rev(S, R2, bb, S.km_h, p, ct);  // v = h bb
@@ -628,7 +698,7 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
           }
           key = R2.key;
         }
-        accumulate(S, A, act, key, ct, lane, P);
+        accumulate<PARK>(S, A, act, key, ct, lane, P);
         if (act) {  // stage A = h K1, P1 = x
           float p[3];
           force_rev(S, R1, ab, S.km_h, p, ct);  // v = h ab
@@ -639,7 +709,7 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
           }
           key = R1.key;
         }
-        accumulate(S, A, act, key, ct, lane, P);
+        accumulate<PARK>(S, A, act, key, ct, lane, P);
       }
       chunk_end(S, P, lane);
     }
@@ -649,13 +719,12 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
 #pragma unroll
     for (int a = 0; a < 3; ++a) V0[a] = gld(S.ckpt + (size_t)q + (size_t)(12 + a) * (size_t)S.ckpt_pad);
   }
-  entry_term(S, B, V0, active, tb, A, P, lane);
-  flush(S, A, A.key != CELL_NONE, lane, P);
-  if (P.occupied) write_out(S, P, P.occupied, lane);
+  entry_term<PARK>(S, B, V0, active, tb, A, P, lane);
+  drain(S, A, P, lane);
 }
 
 template <int DT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 3 ? 4 : 3))) void k_trace_adj_rec(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(rec_waves_per_simd<KS>()))) void k_trace_adj_rec(
     const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, int wpb, int nblocks) {
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
@@ -667,7 +736,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 3 ? 4
 }
 
 template <int DT, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS == 3 ? 4 : 3))) void k_trace_adj_rec_persistent(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(rec_waves_per_simd<KS>()))) void k_trace_adj_rec_persistent(
     const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, unsigned int* __restrict__ queues,
     const int* __restrict__ order) {
   const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
@@ -725,9 +794,7 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
   const int npts = wave_max_nonneg(active ? 2 * n + 1 : 0);
   const float h = S.hf, h_6 = S.h_6;
   Accum A;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) A.acc[k] = 0.0f;
-  A.key = CELL_NONE;
+  accum_init(A);
   Pending P{cache, CELL_NONE, 0, 0ull, 0ull};
   float pv[3] = {0.0f, 0.0f, 0.0f};  // dL/dv0 through the stage points (grid units)
 #pragma unroll 1
@@ -773,15 +840,14 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
       for (int a = 0; a < 3; ++a) pv[a] = fmaf(tj, p[a], pv[a]);
       key = Rs.key;
     }
-    accumulate(S, A, act, key, ct, lane, P);
+    accumulate<true>(S, A, act, key, ct, lane, P);
     if ((j & 15) == 15) chunk_end(S, P, lane);
   }
   float tb0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) tb0[a] = fmaf((float)n * h, R.rb[a], R.tb[a]) + pv[a];
-  entry_term(S, B, B.V, active, tb0, A, P, lane);
-  flush(S, A, A.key != CELL_NONE, lane, P);
-  if (P.occupied) write_out(S, P, P.occupied, lane);
+  entry_term<true>(S, B, B.V, active, tb0, A, P, lane);
+  drain(S, A, P, lane);
 }
 
 template <int DT>
@@ -835,11 +901,6 @@ static hipError_t launch_adj_ql(const LaunchPlan& P, hipStream_t stream) {
   }
   return hipGetLastError();
 }
-
-// Occupancy: chunks of 8 steps take 13 KB of LDS per wavefront, so 3 wavefronts per SIMD;
-// chunks of 6 take 10 KB, and 4 fit when the registers are held to 128.
-template <int KS>
-constexpr int adj_waves_per_simd() { return KS == 6 ? 4 : 3; }
 
 template <int DT, int KS, bool STORED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves_per_simd<KS>()))) void k_trace_adj(
