@@ -517,6 +517,16 @@ __device__ __forceinline__ void locate(float bhi, float small, float n_f, int& p
   p = (int)__builtin_amdgcn_fmed3f(fl + t, 0.0f, n_f);
 }
 
+// As locate, plus the unclamped floor pu of u (NaN when the position is not finite).
+__device__ __forceinline__ void locate_floor(float bhi, float small, float n_f, int& p, float& f, float& pu) {
+  const float fl = floorf(bhi);
+  const float ff = (bhi - fl) + small;
+  const float t = floorf(ff);
+  f = ff - t;
+  pu = fl + t;
+  p = (int)__builtin_amdgcn_fmed3f(pu, 0.0f, n_f);
+}
+
 struct Cell {
   int p[3];    // padded cell index i + 1 per axis, 0 .. n
   float f[3];  // fraction within the cell
@@ -671,6 +681,7 @@ struct State {
   float jf;     // 2n as a float
   float d[3];   // position deviation (grid units)
   float e[3];   // velocity deviation (grid units per unit t)
+  float pu[3];  // floor of u per axis at the position, unclamped, as sharma_step's last locate found it
 };
 
 __device__ __forceinline__ void state_at_step(const RayBase& B, int n, State& st) {
@@ -754,8 +765,9 @@ __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B,
     st.bh[a] = bh3[a];
   }
   st.jf += 2.0f;
-  for (int a = 0; a < 3; ++a) sm[a] = small_part(B, a, st.jf, st.d[a]);
-  locate3(S, st.bh, sm, C);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    locate_floor(st.bh[a], small_part(B, a, st.jf, st.d[a]), S.n_f[a], C.p[a], C.f[a], st.pu[a]);
 }
 
 // One quasi-linear step (Sec. 2.B): the forces are taken on the straight entry line, at
@@ -800,7 +812,20 @@ __device__ __forceinline__ bool outside_box(const SceneDev& S, const RayBase& B,
     float sm = small_part(B, a, st.jf, st.d[a]);
     float lo_gap = (st.bh[a] - 0.5f) + sm;            // u - 1/2, first term exact
     float hi_gap = (st.bh[a] - S.hi_bound[a]) + sm;   // u - (n + 1/2), first term exact
-    inside = inside && (lo_gap >= 0.0f) && (hi_gap <= 0.0f);
+    inside = inside & (lo_gap >= 0.0f) & (hi_gap <= 0.0f);
+  }
+  return !inside;
+}
+
+// The same test after a sharma_step, from its last locate (C, st.pu): u = pu + f lies in
+// [1/2, n + 1/2] iff -pu <= f - 1/2 <= n - pu, where both bounds are exact integers and
+// f - 1/2 has the sign of the exact difference; NaN (a non-finite position) is outside.
+__device__ __forceinline__ bool outside_located(const SceneDev& S, const State& st, const Cell& C) {
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float g = C.f[a] - 0.5f;
+    inside = inside & (g >= -st.pu[a]) & (g <= S.n_f[a] - st.pu[a]);
   }
   return !inside;
 }

@@ -45,14 +45,14 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int
     float* ck = S.ckpt ? S.ckpt + (size_t)RAY_HEADER * S.ckpt_pad + (size_t)q : nullptr;
     const size_t slot_stride = 6 * (size_t)S.ckpt_pad;
     bool exited = false;
-    // after each step: count it, stop on a non-finite state or outside the box
+    // after each step: count it, stop on a non-finite state or outside the box. After a
+    // Sharma step a non-finite position locates as NaN (outside), so only the velocity is
+    // tested every step and the whole state once the ray stops.
     auto stop = [&]() {
       ++n;
-      if (!state_finite(st)) {
-        status |= RAY_NONFINITE;
+      if (!isfinite((st.e[0] + st.e[1]) + st.e[2]) || outside_located(S, st, C)) {
         exited = true;
-      } else if (outside_box(S, B, st)) {
-        exited = true;
+        if (!state_finite(st)) status |= RAY_NONFINITE;
       }
       return exited;
     };
@@ -61,7 +61,14 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int
       force_at<DT>(S, C, Kc);
       while (n < S.max_steps) {
         ql_step<DT>(S, B, st, Kc);
-        if (stop()) break;
+        ++n;
+        if (!state_finite(st)) {
+          status |= RAY_NONFINITE;
+          exited = true;
+        } else if (outside_box(S, B, st)) {
+          exited = true;
+        }
+        if (exited) break;
       }
     } else if (!ck) {
       while (n < S.max_steps) {
