@@ -259,6 +259,7 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
   d.field = S->field;
   d.dec = (float)dec;
   d.inv_dec = (float)scale;
+  d.inv_dec_d = 1.0 / (double)d.dec;
   d.off = (float)S->enc_offset;
   d.one_plus_off = (float)(1.0 + (double)(float)S->enc_offset);
   const double h = S->step;
@@ -276,8 +277,8 @@ SceneDev make_dev(const rbos_scene* S, const Launch& L, int tile_begin, int rend
     d.c_p3[a] = (float)(h * h / 2.0 * km);
     d.c_x[a] = (float)(h * h / 6.0 * km);
     d.c_v[a] = (float)(h / 6.0 * km);
-    d.km_h[a] = (float)(h * km);
-    d.km_h6[a] = (float)(h / 6.0 * km);
+    d.c_x2[a] = 2.0f * d.c_x[a];
+    d.c_v4[a] = 4.0f * d.c_v[a];
   }
   d.max_steps = S->max_steps;
   d.ckpt_k = S->ckpt_stride > 0 ? S->ckpt_stride : 1;

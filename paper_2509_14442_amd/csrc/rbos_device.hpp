@@ -139,7 +139,8 @@ struct SceneDev {
   // stage coefficients of the force in code units (eta dq/du_a), per axis:
   // h^2/8 km_a (P2), h^2/2 km_a (P3), h^2/6 km_a (position), h/6 km_a (velocity)
   float c_p2[3], c_p3[3], c_x[3], c_v[3];
-  float km_h[3], km_h6[3];  // h km_a, h km_a / 6: the adjoint's stage factors
+  float c_x2[3], c_v4[3];  // 2 c_x, 4 c_v: the second stage's weights in the adjoint
+  double inv_dec_d;        // 1 / dec (binary64): scales the adjoint's monomial totals
   int max_steps, ckpt_k, ckpt_slots;
   int tracer;          // 0 nonlinear, 1 quasi-linear (forces on the entry line)
   long long ckpt_pad;  // entries per checkpoint component (a multiple of 64)

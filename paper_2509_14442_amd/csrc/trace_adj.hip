@@ -44,40 +44,39 @@ __device__ __forceinline__ void sample_rev(const SceneDev& S, const Cell& C, Sam
   sample_rev_at(S, c, rec, C.f, R);
 }
 
-// Reverse of K = force(P) for an adjoint v = dL/dK: returns p = dL/dP (grid units) and
-// the sample's contributions to dL/d(delta_c) for the 8 corners of its cell,
-//   w_a = v_a km_a (km_a = dec / voxel_a^2),  sigma = sum_a w_a g_a,
-//   p_b = dec g_b sigma + eta sum_{a != b} w_a H_ab,
-//   dL/d delta_c = w_c sigma + sum_a W_a dw_c/du_a,  W_a = (eta / dec) w_a,
+// Reverse of G = force_code(P) (code units, G_a = eta dq/du_a) for its adjoint
+// w = dL/dG: returns p = dL/dP (grid units) and adds the sample's contributions to
+// dL/d(delta_c) for the 8 corners of its cell, times dec, to acc:
+//   s = dec sum_a w_a g_a,  W_a = eta w_a,
+//   p_b = s g_b + sum_{a != b} W_a H_ab,
+//   dec dL/d delta_c = s w_c + sum_a W_a dw_c/du_a,
 // with w_c the trilinear weight of corner c. The contributions are multilinear in the
-// fractions (u, v, w) = f, so they are returned as the coefficients M[m] of the 8
-// monomials m = u^(m & 1) v^(m >> 1 & 1) w^(m >> 2): M[m] = sigma m + sum_a W_a dm/du_a.
-// Samples in one cell share the monomials' frame, so their coefficients add up; corner
-// values follow from the totals (corner_of_monomials). In apron cells the field is
+// fractions (u, v, w) = f, so they are kept as the coefficients of the 8 monomials
+// m = u^(m & 1) v^(m >> 1 & 1) w^(m >> 2): s m + sum_a W_a dm/du_a. Samples in one cell
+// share the monomials' frame, so their coefficients add up; corner values follow from
+// the totals (corner_of_monomials, scaled by 1 / dec). In apron cells the field is
 // constant along the clamped axis (g and H vanish there); the two corners that share one
 // edge voxel receive contributions that add up to the clamped-axis weights.
-// The stage's adjoint arrives unscaled with its per-axis factor ks (h km, h km / 6, or km
-// when v already holds the h), so w = v ks.
-__device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R, const float v[3], const float ks[3],
-                                          float p[3], float M[8]) {
-  float w0 = v[0] * ks[0], w1 = v[1] * ks[1], w2 = v[2] * ks[2];
-  float sigma = fmaf(w0, R.g[0], fmaf(w1, R.g[1], w2 * R.g[2]));
-  float ds = S.dec * sigma;
+__device__ __forceinline__ void force_rev(const SceneDev& S, const SampleRev& R, const float w[3], float p[3],
+                                          float acc[8]) {
+  const float s = S.dec * fmaf(w[0], R.g[0], fmaf(w[1], R.g[1], w[2] * R.g[2]));
+  const float Wx = R.eta * w[0], Wy = R.eta * w[1], Wz = R.eta * w[2];
   // H = (H_xy, H_xz, H_yz)
-  p[0] = fmaf(ds, R.g[0], R.eta * fmaf(w1, R.H[0], w2 * R.H[1]));
-  p[1] = fmaf(ds, R.g[1], R.eta * fmaf(w0, R.H[0], w2 * R.H[2]));
-  p[2] = fmaf(ds, R.g[2], R.eta * fmaf(w0, R.H[1], w1 * R.H[2]));
-  const float ed = R.eta * S.inv_dec;
-  const float Wx = w0 * ed, Wy = w1 * ed, Wz = w2 * ed;
-  const float u = R.f[0], vv = R.f[1], w = R.f[2];
-  M[0] = sigma;                                   // 1
-  M[1] = fmaf(sigma, u, Wx);                      // u
-  M[2] = fmaf(sigma, vv, Wy);                     // v
-  M[4] = fmaf(sigma, w, Wz);                      // w
-  M[3] = fmaf(vv, M[1], Wy * u);                  // uv:  sigma uv + Wx v + Wy u
-  M[5] = fmaf(w, M[1], Wz * u);                   // uw:  sigma uw + Wx w + Wz u
-  M[6] = fmaf(w, M[2], Wz * vv);                  // vw:  sigma vw + Wy w + Wz v
-  M[7] = fmaf(w, M[3], Wz * (u * vv));            // uvw: sigma uvw + Wx vw + Wy uw + Wz uv
+  p[0] = fmaf(s, R.g[0], fmaf(Wy, R.H[0], Wz * R.H[1]));
+  p[1] = fmaf(s, R.g[1], fmaf(Wx, R.H[0], Wz * R.H[2]));
+  p[2] = fmaf(s, R.g[2], fmaf(Wx, R.H[1], Wy * R.H[2]));
+  const float u = R.f[0], v = R.f[1], x = R.f[2];
+  const float m1 = fmaf(s, u, Wx);              // u:   s u + Wx
+  const float m2 = fmaf(s, v, Wy);              // v:   s v + Wy
+  const float m3 = fmaf(v, m1, Wy * u);         // uv:  s uv + Wx v + Wy u
+  acc[0] += s;                                  // 1
+  acc[1] += m1;
+  acc[2] += m2;
+  acc[3] += m3;
+  acc[4] += fmaf(s, x, Wz);                     // w:   s w + Wz
+  acc[5] = fmaf(x, m1, fmaf(Wz, u, acc[5]));    // uw:  s uw + Wx w + Wz u
+  acc[6] = fmaf(x, m2, fmaf(Wz, v, acc[6]));    // vw:  s vw + Wy w + Wz v
+  acc[7] = fmaf(x, m3, fmaf(Wz, u * v, acc[7]));  // uvw: s uvw + Wx vw + Wy uw + Wz uv
 }
 
 // Corner c of a cell from its 8 monomial totals: the trilinear weight of corner
@@ -199,7 +198,8 @@ __device__ __forceinline__ void cache_add(const SceneDev& S, Pending& P, int key
       slot = P.next;
       P.next = (P.next + 1) & (PEND_SLOTS - 1);
       const int old = __builtin_amdgcn_readlane(P.key, slot);
-      if (lane < 8) gatomic_add(voxel_of_corner(S, old, lane), corner_of_monomials(P.vals + slot * 8, lane));
+      if (lane < 8)
+        gatomic_add(voxel_of_corner(S, old, lane), corner_of_monomials(P.vals + slot * 8, lane) * S.inv_dec_d);
       wave_lds_order();
     }
     if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
@@ -257,7 +257,7 @@ __device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigne
     const int idx = q * 64 + lane, slot = idx >> 3;
     const int key = __shfl(P.key, slot);
     if ((which >> slot) & 1ull)
-      gatomic_add(voxel_of_corner(S, key, idx & 7), corner_of_monomials(P.vals + slot * 8, idx & 7));
+      gatomic_add(voxel_of_corner(S, key, idx & 7), corner_of_monomials(P.vals + slot * 8, idx & 7) * S.inv_dec_d);
   }
   wave_lds_order();
   if ((which >> lane) & 1ull) P.key = CELL_NONE;
@@ -271,12 +271,11 @@ __device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lan
   P.touched = 0;
 }
 
-// Merge one sample's monomial coefficients (lanes with act) into the accumulators. A lane
-// that enters a new cell parks the sums of the one it leaves (after its park has been
-// flushed, if taken) and starts from zero.
+// Lanes with act take a sample in cell `key`: a lane that enters a new cell parks the sums
+// of the one it leaves (after its park has been flushed, if taken), or flushes them
+// without PARK, and starts from zero. The caller then adds the sample to A.acc.
 template <bool PARK>
-__device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
-                                           int lane, Pending& P) {
+__device__ __forceinline__ void enter(const SceneDev& S, Accum& A, bool act, int key, int lane, Pending& P) {
   const bool out = act && key != A.key && A.key != CELL_NONE;
   if (__ballot(out)) {
     if (PARK) {
@@ -294,10 +293,17 @@ __device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act
       flush(S, A, out, lane, P);
     }
   }
+  if (act) A.key = key;
+}
+
+// Merge a sample's monomial coefficients ct (lanes with act) into the accumulators.
+template <bool PARK>
+__device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
+                                           int lane, Pending& P) {
+  enter<PARK>(S, A, act, key, lane, P);
   if (act) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) A.acc[k] += ct[k];
-    A.key = key;
   }
 }
 
@@ -413,6 +419,7 @@ __device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, 
     float kap = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) kap = fmaf(tb0[a], (V[a] / vn) * dd_to_f(S.inv_vox[a]), kap);
+    kap *= S.dec;  // the accumulators hold dec times the contributions
     // kap w_c(x0) as monomial coefficients: kap m(f)
     const float u = C0.f[0], v = C0.f[1], w = C0.f[2];
     c0v[0] = kap;
@@ -426,6 +433,66 @@ __device__ __forceinline__ void entry_term(const SceneDev& S, const RayBase& B, 
     key0 = (int)cell_index(S, C0);
   }
   accumulate<PARK>(S, A, active, key0, c0v, lane, P);
+}
+
+// Reverse of one Sharma step for the state adjoints rb = dL/dd, tb = dL/de after it.
+// The step (code-unit stage forces G_i at P_i, forward coefficients c_x, c_v, c_p2, c_p3)
+//   P2 = x + h/2 e + c_p2 G1,  P3 = x + h e + c_p3 G2,
+//   d' = x + h e + c_x (G1 + 2 G2),  e' = e + c_v (G1 + 4 G2 + G3)
+// gives the force adjoints wC = dL/dG3 = c_v tb, wB = dL/dG2 = 2 c_x rb + 4 c_v tb +
+// c_p3 p3, wA = dL/dG1 = c_x rb + c_v tb + c_p2 p2 (p_i = dL/dP_i from the stage's
+// force_rev), and before the step rb + p3 + p2 + p1 and tb + h (rb + p3) + h/2 p2.
+// stage_weights starts wA and wB from the step-end adjoints.
+__device__ __forceinline__ void stage_weights(const SceneDev& S, const float rb[3], const float tb[3], float wA[3],
+                                              float wB[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    wA[a] = fmaf(S.c_x[a], rb[a], S.c_v[a] * tb[a]);
+    wB[a] = fmaf(S.c_x2[a], rb[a], S.c_v4[a] * tb[a]);
+  }
+}
+
+// Stages C, B, A of the reverse (lanes with act), each sample's contributions into the
+// accumulators of its cell; rb, tb become the adjoints before the step.
+template <bool PARK>
+__device__ __forceinline__ void reverse_stages(const SceneDev& S, Accum& A, Pending& P, bool act,
+                                               const SampleRev& R1, const SampleRev& R2, const SampleRev& R3,
+                                               float wA[3], float wB[3], float rb[3], float tb[3], int lane) {
+  float rs[3], ts[3];
+  enter<PARK>(S, A, act, act ? R3.key : 0, lane, P);
+  if (act) {  // stage C
+    float w[3], p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] = S.c_v[a] * tb[a];
+    force_rev(S, R3, w, p, A.acc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rs[a] = rb[a] + p[a];
+      ts[a] = fmaf(S.hf, rs[a], tb[a]);
+      wB[a] = fmaf(S.c_p3[a], p[a], wB[a]);
+    }
+  }
+  enter<PARK>(S, A, act, act ? R2.key : 0, lane, P);
+  if (act) {  // stage B
+    float p[3];
+    force_rev(S, R2, wB, p, A.acc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rs[a] += p[a];
+      ts[a] = fmaf(S.h_2, p[a], ts[a]);
+      wA[a] = fmaf(S.c_p2[a], p[a], wA[a]);
+    }
+  }
+  enter<PARK>(S, A, act, act ? R1.key : 0, lane, P);
+  if (act) {  // stage A
+    float p[3];
+    force_rev(S, R1, wA, p, A.acc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rb[a] = rs[a] + p[a];
+      tb[a] = ts[a];
+    }
+  }
 }
 
 template <int DT, int KS, bool STORED>
@@ -450,7 +517,6 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   Accum A;
   accum_init(A);
   Pending P{replay + KS * 6 * 64, CELL_NONE, 0, 0ull, 0ull};
-  const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6;
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
     for (int ch = m_chunks - 1; ch >= 0; --ch) {
@@ -506,10 +572,9 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
         const bool act = lane_chunk && (c0 + i < n);
         // the samples of stages A and B: their forces K1, K2 locate P2 and P3 (the same
         // arithmetic as the forward's), their derivatives serve the reverse of the stage
-        SampleRev R1, R2;
+        SampleRev R1, R2, R3;
         Cell Q1;
-        float ab[3], bb[3], rs[3], ts[3], ct[8];
-        int key = 0;
+        float wA[3], wB[3];
         if (act) {
           // recompute the step's three sample points (same arithmetic as the forward)
           State s;
@@ -538,49 +603,10 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
             sm[a] = small_part(B, a, s.jf + 2.0f, stage3_dev(S, a, stage3_base(S, s, a), R2.eta * R2.g[a]));
           }
           locate3(S, bh, sm, Q3);
-          // stage C = h K3: adjoint v = h dL/dC
-          SampleRev R3;
           sample_rev<DT>(S, Q3, R3);
-          float v[3], p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            ab[a] = fmaf(h_6, rb[a], tb[a] * (1.0f / 6.0f));
-            bb[a] = fmaf(h * (1.0f / 3.0f), rb[a], tb[a] * (2.0f / 3.0f));
-            v[a] = tb[a];  // h / 6 is in km_h6
-          }
-          force_rev(S, R3, v, S.km_h6, p, ct);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            bb[a] = fmaf(h_2, p[a], bb[a]);
-            rs[a] = rb[a] + p[a];
-            ts[a] = fmaf(h, rb[a], tb[a]) + h * p[a];
-          }
-          key = R3.key;
+          stage_weights(S, rb, tb, wA, wB);
         }
-        accumulate<PARK>(S, A, act, key, ct, lane, P);
-        if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
-          float p[3];
-          force_rev(S, R2, bb, S.km_h, p, ct);  // v = h bb
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            ab[a] = fmaf(h * 0.125f, p[a], ab[a]);
-            rs[a] += p[a];
-            ts[a] = fmaf(h_2, p[a], ts[a]);
-          }
-          key = R2.key;
-        }
-        accumulate<PARK>(S, A, act, key, ct, lane, P);
-        if (act) {  // stage A = h K1, P1 = x
-          float p[3];
-          force_rev(S, R1, ab, S.km_h, p, ct);  // v = h ab
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            rb[a] = rs[a] + p[a];
-            tb[a] = ts[a];
-          }
-          key = R1.key;
-        }
-        accumulate<PARK>(S, A, act, key, ct, lane, P);
+        reverse_stages<PARK>(S, A, P, act, R1, R2, R3, wA, wB, rb, tb, lane);
       }
       chunk_end(S, P, lane);
     }
@@ -623,7 +649,6 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
   accum_init(A);
   Pending P{lds + KS * 3 * 64 * 4, CELL_NONE, 0, 0ull, 0ull};
   f32x4* smp = reinterpret_cast<f32x4*>(lds);
-  const float h = S.hf, h_2 = S.h_2, h_6 = S.h_6;
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
     for (int ch = m_chunks - 1; ch >= 0; --ch) {
@@ -655,8 +680,7 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
       for (int i = KS - 1; i >= 0; --i) {
         const bool act = lane_chunk && (c0 + i < n);
         SampleRev R1, R2, R3;
-        float ab[3], bb[3], rs[3], ts[3], ct[8];
-        int key = 0;
+        float wA[3], wB[3];
         if (act) {
           const f32x4* row = smp + i * 3 * 64 + lane;
           const f32x4 s1 = row[0], s2 = row[64], s3 = row[128];
@@ -669,47 +693,9 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
           sample_rev_at(S, c3, r3, f3, R3);
           sample_rev_at(S, c2, r2, f2, R2);
           sample_rev_at(S, c1, r1, f1, R1);
-          // stage C = h K3: adjoint v = h dL/dC
-          float v[3], p[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            ab[a] = fmaf(h_6, rb[a], tb[a] * (1.0f / 6.0f));
-            bb[a] = fmaf(h * (1.0f / 3.0f), rb[a], tb[a] * (2.0f / 3.0f));
-            v[a] = tb[a];  // h / 6 is in km_h6
-          }
-          force_rev(S, R3, v, S.km_h6, p, ct);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            bb[a] = fmaf(h_2, p[a], bb[a]);
-            rs[a] = rb[a] + p[a];
-            ts[a] = fmaf(h, rb[a], tb[a]) + h * p[a];
-          }
-          key = R3.key;
+          stage_weights(S, rb, tb, wA, wB);
         }
-        accumulate<PARK>(S, A, act, key, ct, lane, P);
-        if (act) {  // stage B = h K2, P2 = x + h/2 v + h/8 A
-          float p[3];
-          force_rev(S, R2, bb, S.km_h, p, ct);  // v = h bb
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            ab[a] = fmaf(h * 0.125f, p[a], ab[a]);
-            rs[a] += p[a];
-            ts[a] = fmaf(h_2, p[a], ts[a]);
-          }
-          key = R2.key;
-        }
-        accumulate<PARK>(S, A, act, key, ct, lane, P);
-        if (act) {  // stage A = h K1, P1 = x
-          float p[3];
-          force_rev(S, R1, ab, S.km_h, p, ct);  // v = h ab
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            rb[a] = rs[a] + p[a];
-            tb[a] = ts[a];
-          }
-          key = R1.key;
-        }
-        accumulate<PARK>(S, A, act, key, ct, lane, P);
+        reverse_stages<PARK>(S, A, P, act, R1, R2, R3, wA, wB, rb, tb, lane);
       }
       chunk_end(S, P, lane);
     }
@@ -800,8 +786,8 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
 #pragma unroll 1
   for (int j = 0; j < npts; ++j) {
     const bool act = active && j <= 2 * n;
-    int key = 0;
-    float ct[8];
+    SampleRev Rs;
+    float w[3];
     if (act) {
       float v[3];
       const int m = j >> 1;
@@ -831,16 +817,18 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
       }
       Cell C;
       locate3(S, bh, sm, C);
-      SampleRev Rs;
       sample_rev<DT>(S, C, Rs);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) w[a] = v[a] * S.km[a];  // dL/dK -> dL/dG
+    }
+    enter<true>(S, A, act, act ? Rs.key : 0, lane, P);
+    if (act) {
       float p[3];
-      force_rev(S, Rs, v, S.km, p, ct);
-      const float tj = jf * (0.5f * h);
+      force_rev(S, Rs, w, p, A.acc);
+      const float tj = (float)j * (0.5f * h);
 #pragma unroll
       for (int a = 0; a < 3; ++a) pv[a] = fmaf(tj, p[a], pv[a]);
-      key = Rs.key;
     }
-    accumulate<true>(S, A, act, key, ct, lane, P);
     if ((j & 15) == 15) chunk_end(S, P, lane);
   }
   float tb0[3];
