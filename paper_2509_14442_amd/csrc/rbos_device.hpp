@@ -715,8 +715,10 @@ __device__ __forceinline__ float stage3_dev(const SceneDev& S, int a, float base
 //   K3 = D(P3), P3 = x + h v + h^2/2 K2
 //   x <- x + h v + h^2/6 (K1 + 2 K2),  v <- v + h/6 (K1 + 4 K2 + K3)
 // The base absorbs the h V part of every position. On return st holds the new state
-// and `C` the located cell of the new position (the next step's first sample).
-template <int DT, class Record = NoRecord, class Issue = NoIssue>
+// and `C` the located cell of the new position (the next step's first sample). With
+// FULL false the step ends once its third sample is located and recorded (no force
+// there, no new state): the last step of a replayed chunk needs only its samples.
+template <int DT, class Record = NoRecord, class Issue = NoIssue, bool FULL = true>
 __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B, State& st, Cell& C,
                                             const Record& record = Record(), const Issue& issue = Issue()) {
   float G1[3], G2[3], G3[3], bh2[3], bh3[3], sm[3], base3[3];
@@ -752,6 +754,7 @@ __device__ __forceinline__ void sharma_step(const SceneDev& S, const RayBase& B,
   locate3(S, bh3, sm, C);
   rec = cell_index(S, C);
   record(2, rec, C);
+  if constexpr (!FULL) return;
   {
     float c[8];
     fetch_cell<DT>(S, rec, c);

@@ -556,13 +556,15 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
         locate_state(S, B, st, C);
 #pragma unroll 1
         for (int i = 0; i < ch * KS; ++i) sharma_step<DT>(S, B, st, C);  // to the chunk start
+        const int cnt = min(KS, n - c0);  // steps of the chunk (the state after the last is not needed)
 #pragma unroll 1
-        for (int i = 0; i < KS && c0 + i < n; ++i) {
+        for (int i = 0;; ++i) {
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             replay[(i * 6 + a) * 64 + lane] = st.d[a];
             replay[(i * 6 + 3 + a) * 64 + lane] = st.e[a];
           }
+          if (i + 1 == cnt) break;
           sharma_step<DT>(S, B, st, C);
         }
       }
@@ -631,6 +633,14 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 template <int KS>
 constexpr int rec_floats_per_wave() { return KS * 3 * 64 * 4 + PEND_SLOTS * 8; }
 
+// Recorder of the replay: sample s of the step at row[s * 64].
+struct SampleRow {
+  f32x4* row;
+  __device__ __forceinline__ void operator()(int stage, unsigned rec, const Cell& Cs) const {
+    row[stage * 64] = f32x4{__uint_as_float(rec), Cs.f[0], Cs.f[1], Cs.f[2]};
+  }
+};
+
 template <int DT, int KS>
 __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, int lane, float* __restrict__ lds) {
   constexpr bool PARK = rec_waves_per_simd<KS>() == 3;  // registers for the parks
@@ -667,13 +677,11 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
         locate_state(S, B, st, C);
 #pragma unroll 1
         for (int i = 0; i < ch * KS; ++i) sharma_step<DT>(S, B, st, C);  // to the chunk start
+        // the chunk's steps, the last one only up to its third sample
+        const int cnt = min(KS, n - c0);
 #pragma unroll 1
-        for (int i = 0; i < KS && c0 + i < n; ++i) {
-          f32x4* row = smp + i * 3 * 64 + lane;
-          sharma_step<DT>(S, B, st, C, [row](int stage, unsigned rec, const Cell& Cs) {
-            row[stage * 64] = f32x4{__uint_as_float(rec), Cs.f[0], Cs.f[1], Cs.f[2]};
-          });
-        }
+        for (int i = 0; i < cnt - 1; ++i) sharma_step<DT>(S, B, st, C, SampleRow{smp + i * 3 * 64 + lane});
+        sharma_step<DT, SampleRow, NoIssue, false>(S, B, st, C, SampleRow{smp + (cnt - 1) * 3 * 64 + lane});
       }
       // reverse the chunk's steps, one stage at a time (C, B, A)
 #pragma unroll 1
