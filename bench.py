@@ -90,8 +90,8 @@ def parse(argv=None):
     p.add_argument("--adj-blocks-per-cu", type=int, default=0)
     p.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
     p.add_argument("--tune", type=int, default=1,
-                   help="autotune launch shapes, checkpoint stride and field layout before timing (0: use the "
-                        "command-line values)")
+                   help="launch shapes, checkpoint stride and field layout from the autotuner: 1 its cache, "
+                        "else the shipped table, else tune now; 2 tune now; 0 the command-line values")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--counters", default=COUNTERS_FILE, help="summary of the counter runs of the tracer kernels")
@@ -365,7 +365,8 @@ class Workload:
         scene; returns the forward and adjoint launches."""
         from paper_2509_14442_amd import autotune
 
-        entry = autotune.tune(sub, "fwd+adj", targets, reps=1 if apply_to is not None else 2)
+        entry = autotune.tune(sub, "fwd+adj", targets, reps=1 if apply_to is not None else 2,
+                              force=self.args.tune == 2)
         for i, s in enumerate(apply_to if apply_to is not None else sub):
             s.struct.ckpt_stride = entry["ckpt_stride"]
             if entry["layout"] != s.field.layout:

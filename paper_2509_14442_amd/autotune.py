@@ -3,8 +3,11 @@
 It times the forward (and, for mode "fwd+adj", render and adjoint) of the given scenes
 with HIP events on the current stream for a list of candidates, and caches the winner
 as JSON keyed by (gfx arch, storage dtype, tracer, samples per pixel, step-cap bucket,
-grid-size bucket, ray-count bucket, scene count, mode). On return (cached or new) the
-scenes carry the chosen checkpoint stride.
+grid-size bucket, ray-count bucket, scene count, mode). A key missing from the user's
+cache is looked up in the table shipped with the package (autotune_table.json, winners
+this same tuner measured on an MI355X), and only then tuned. On return the scenes carry
+the chosen checkpoint stride; the entry's "source" says where it came from ("cache",
+"table" or "measured").
 Run it before capturing a graph: tuning launches kernels and allocates buffers.
 """
 
@@ -21,6 +24,7 @@ from . import api
 
 DEFAULT_CACHE = os.environ.get("RBOS_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "rbos", "autotune.json"))
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table.json")
 
 # (tile, waves per block, persistent, blocks per CU; 0 = each kernel's occupancy limit)
 LAUNCHES: List[Tuple[Tuple[int, int], int, bool, int]] = [
@@ -89,7 +93,7 @@ def _entry_of(launch_t) -> Dict:
 def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[torch.Tensor]] = None,
          strides: Sequence[int] = STRIDES, launches=LAUNCHES, layouts: Sequence[str] = LAYOUTS,
          hbm_budget: Optional[int] = None, reps: int = 2, cache: Optional[str] = DEFAULT_CACHE,
-         force: bool = False) -> Dict:
+         force: bool = False, table: Optional[str] = TABLE) -> Dict:
     """Pick launch shapes, the checkpoint stride and the field layout for these scenes;
     returns the cached or new entry {"fwd": launch, "adj": launch, "ckpt_stride", "layout",
     "ms"} (a launch is {"tile", "waves_per_block", "persistent", "blocks_per_cu"}; "adj" is
@@ -100,17 +104,22 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
     for every launch shape, stage 2 the adjoint alone for every shape after one forward
     with the best forward shape, stage 3 the whole forward + render + adjoint for every
     stride whose checkpoints fit `hbm_budget` (default: half the free device memory), stage 4
-    the best of those with the scenes' fields re-encoded in each other layout."""
+    the best of those with the scenes' fields re-encoded in each other layout. With force
+    the cache and the table are not consulted."""
     key = cache_key(scenes, mode)
     db = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
             db = json.load(f)
-        if key in db and not force:
-            entry = db[key]
+    if not force:
+        entry, source = db.get(key), "cache"
+        if entry is None and table and os.path.exists(table):
+            with open(table) as f:
+                entry, source = json.load(f).get(key), "table"
+        if entry is not None:
             for s in scenes:
                 s.struct.ckpt_stride = entry["ckpt_stride"]
-            return entry
+            return dict(entry, source=source)
     if hbm_budget is None:
         free, _ = torch.cuda.mem_get_info()
         hbm_budget = int(free * 0.5)
@@ -181,11 +190,11 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
     for s in scenes:
         s.struct.ckpt_stride = entry["ckpt_stride"]
     if cache:
-        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         db[key] = entry
         with open(cache, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)
-    return entry
+    return dict(entry, source="measured")
 
 
 def launch_of(entry: Dict, which: str = "fwd"):
