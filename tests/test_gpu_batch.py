@@ -104,11 +104,13 @@ def test_graph_replay_matches_eager():
 def test_autotune_picks_valid_config(tmp_path):
     b = _batch(2)
     scenes = [s for s, _ in b]
-    entry = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"), reps=1,
+    entry = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"), reps=1, table=None,
                           launches=autotune.LAUNCHES[:2] + autotune.LAUNCHES[3:4], strides=(1, 8, 16))
-    assert entry["ckpt_stride"] in (1, 8, 16) and entry["ms"] > 0
+    assert entry["ckpt_stride"] in (1, 8, 16) and entry["ms"] > 0 and entry["source"] == "measured"
     assert {"fwd", "adj"} <= set(entry)
     again = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"))
+    assert again.pop("source") == "cache"
+    entry.pop("source")
     assert again == entry  # served from the cache
     tr = api.Tracer(scenes, autotune.launch_of(entry), adjoint_launch=autotune.launch_of(entry, "adj"))
     tr.forward()
@@ -122,6 +124,29 @@ def test_autotune_picks_valid_config(tmp_path):
     for i in range(len(scenes)):
         assert torch.equal(tr.uv[i], ref.uv[i])
         assert torch.linalg.norm(g[i] - g_ref[i]) <= 1e-5 * torch.linalg.norm(g_ref[i])
+
+
+def test_shipped_table_covers_the_benchmark_room():
+    """The 1024 x 1024-ray room at FP32 (the benchmark's default workload) finds its
+    configuration in the table shipped with the package: no tuning run, the stride and
+    launches applied, and the result equal to an untuned trace of the same scene."""
+    import bos_inputs as bi
+
+    sc = bi.scene_room_1m()
+    T = bi.temperature_grid(bi.plumes_room(3, sc.box_lo, sc.box_hi), sc.box_lo, sc.box_hi, sc.dims)
+    pat = torch.from_numpy(bi.blurred_noise(12, (1024, 1024)).astype(np.float32)).to(DEV)
+    f = api.Field.from_temperature(torch.from_numpy(T.astype(np.float32)).to(DEV), "f32")
+    scenes = [api.Scene(sc, f, pat)]
+    entry = autotune.tune(scenes, "fwd+adj", cache=None)
+    assert entry["source"] == "table"
+    assert scenes[0].struct.ckpt_stride == entry["ckpt_stride"]
+    assert entry["layout"] in autotune.LAYOUTS and entry["ckpt_stride"] in autotune.STRIDES
+    tr = api.Tracer(scenes, autotune.launch_of(entry), adjoint_launch=autotune.launch_of(entry, "adj"))
+    tr.forward()
+    ref = api.Tracer(scenes, checkpoints=False)
+    ref.forward()
+    torch.cuda.synchronize()
+    assert torch.equal(tr.uv[0], ref.uv[0])
 
 
 def test_batch_mixing_samples_weights_and_pixel_lists():
