@@ -3,8 +3,10 @@
 
 Default workload (room1m): the 4 x 4 x 3 m room with a 128^3 voxel field (seeded hot plumes
 plus 0.5 K/m stratification), a 1024 x 1024 pinhole camera (1,048,576 rays), Sharma RK4
-with h = 0.5 voxel and at most 512 steps, checkpoints every 16 steps, projector pattern
-1024 x 1024 (blurred uniform noise). Inputs are synthetic and seeded.
+with h = 0.5 voxel and at most 512 steps, projector pattern 1024 x 1024 (blurred uniform
+noise). Inputs are synthetic and seeded. Launch shapes, checkpoint stride and field layout
+come from the autotuner (its cache, else the table shipped with the package, else a tuning
+run; --tune 2 forces one, --tune 0 takes the command line).
 
 One timed step = the whole hot path on resident inputs, replayed as one captured HIP
 graph: encode the field(s) from temperature, trace every ray with checkpoints, render +
@@ -12,9 +14,9 @@ L_BOS + dL/d(u, v), zero the FP64 gradient(s), adjoint. value = ray-steps / step
 (ray-steps = sum of per-ray Sharma steps inside the box, read back from the kernels).
 
 Other workloads (--workload): batch64 = 64 scenes of uneven grids (48-192 per axis) and
-cameras (128-1024 per side) in one persistent launch with autotuned launch shape and
-checkpoint stride; room256 = 256 x 256 x 192 field, 2048 x 1536 rays, <= 1024 steps, with
-16-bit storage (--dtype f16/bf16) and errors on a 4096-ray subsample.
+cameras (128-1024 per side) in one persistent launch; room256 = 256 x 256 x 192 field,
+2048 x 1536 rays, <= 1024 steps, with 16-bit storage (--dtype f16/bf16) and errors on a
+4096-ray subsample.
 
 Prints one JSON line.
 """

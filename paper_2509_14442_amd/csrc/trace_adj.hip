@@ -4,12 +4,14 @@
 // Per wavefront (64 rays of one tile), segments between checkpoints are processed from
 // the last to the first, aligned on the step index so that the tile's rays move through
 // the same cells together. A segment is replayed forward from its checkpoint in chunks
-// of KS steps whose step-start states are kept in LDS, then reversed step by step. Each
-// sample's eight corner contributions are merged per lane while the ray stays in one
-// cell; on a cell change the lanes leaving the same cell are summed across the
-// wavefront and one FP64 atomic per corner goes to the gradient. Loops stay rolled so
-// the kernel fits the instruction cache; the per-ray geometry comes from the header the
-// forward pass stored with the checkpoints.
+// of KS steps, keeping in LDS either each step's start state (then the reverse relocates
+// the step's samples) or, for strides 3 and 4, the cells and fractions of its three
+// samples; the chunk is then reversed step by step. Each sample's contributions are
+// merged per lane, as monomial coefficients, while the ray stays in one cell; lanes that
+// left the same cell are summed across the wavefront into a per-wavefront LDS cache of
+// cell totals, which goes to the gradient with one FP64 atomic per corner. Loops stay
+// rolled so the kernel fits the instruction cache; the per-ray geometry comes from the
+// header the forward pass stored with the checkpoints.
 #include <climits>
 
 #include "rbos_device.hpp"
