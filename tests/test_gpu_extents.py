@@ -44,3 +44,17 @@ def test_longest_axis_forward_and_adjoint(axis):
     # the far end of the long axis receives gradient
     far = np.take(np.abs(g_ref), range(MAX_DIM - 16, MAX_DIM), axis=2 - axis)
     assert far.max() > 0
+    # the recording adjoint (strides 4 and 3: cell keys of the samples kept from the
+    # replay), the second with the field stored as x-pairs
+    pat = torch.from_numpy(w.pattern32).to(DEV)
+    for k, layout in ((4, "cell"), (3, "xpair")):
+        field = api.Field.from_temperature(torch.from_numpy(w.T32).to(DEV), "f32")
+        if layout != "cell":
+            field = field.relayout(layout)
+        trk = api.Tracer([api.Scene(w.scene.replace(ckpt_stride=k), field, pat)], checkpoints=True)
+        trk.forward()
+        assert torch.equal(trk.uv[0], tr.uv[0])
+        gk = _np(trk.adjoint(dL_duv=[torch.from_numpy(lam).to(DEV)])[0])
+        l2, frac = grad_errors(gk, g_ref)
+        print(f"dims {tuple(dims)}, stride {k}, {layout}: gradient rel-L2 {l2:.2e}, voxels off {frac:.1e}")
+        assert l2 < 1e-3 and frac < 5e-3, (k, layout, l2, frac)
