@@ -86,6 +86,32 @@ def test_adjoint_room_subset_matches_oracle():
     assert frac < 5e-3, (l2, frac)
 
 
+_SPARSE = {}
+
+
+def _sparse_reference():
+    """A 24 x 24 camera on a 240 x 240 x 180 room and one dL/d(u, v); the oracle's gradient."""
+    if not _SPARSE:
+        w = room_workload((240, 240, 180), 24, 24, seed=7, max_steps=800, pat=256)
+        lam = np.random.default_rng(8).standard_normal((24 * 24, 2)).astype(np.float32)
+        _, _, g_ref, _ = _oracle_loss_and_grad(w, np.zeros(24 * 24, np.float32), dL_duv=lam)
+        _SPARSE.update(w=w, lam=lam, g_ref=g_ref)
+    return _SPARSE["w"], _SPARSE["lam"], _SPARSE["g_ref"]
+
+
+@pytest.mark.parametrize("ckpt", [1, 3, 4, 6, 8])
+def test_adjoint_sparse_rays_every_lane_in_its_own_cell(ckpt):
+    """Rays 3-10 cells apart: the 64 rays of a tile sit in different cells, so one
+    wavefront reduction follows another for dozens of cells at a time, and the
+    wavefront's 32-slot cache of cell totals fills and writes slots out within a chunk.
+    Every adjoint form (stored, recording, replay; with and without parked sums) against
+    the oracle."""
+    w, lam, g_ref = _sparse_reference()
+    _, g = _gpu_loss_and_grad(w, np.zeros(24 * 24, np.float32), ckpt=ckpt, dL_duv=lam)
+    l2, frac = grad_errors(g, g_ref)
+    assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
+
+
 @pytest.mark.parametrize("ckpt", [16, 3, 4])
 def test_adjoint_persistent_and_tiles_agree(ckpt):
     w = room_workload((48, 40, 32), 96, 80, seed=4)
