@@ -89,6 +89,20 @@ def test_ql_adjoint_matches_oracle(room):
     assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
 
 
+def test_ql_adjoint_sparse_rays_every_lane_in_its_own_cell():
+    """Rays 3-10 cells apart (24 x 24 camera, 240 x 240 x 180 room): the quasi-linear
+    adjoint's parked sums and 32-slot cell cache under dozens of cells per reduction."""
+    w = _ql(room_workload((240, 240, 180), 24, 24, seed=7, max_steps=800, pat=256))
+    lam = np.random.default_rng(9).standard_normal((24 * 24, 2)).astype(np.float32)
+    tr = _tracer(w)
+    tr.forward()
+    g = _np(tr.adjoint(dL_duv=[torch.from_numpy(lam).to(DEV)])[0])
+    F = oracle.grid_field(stored_delta(w.T32), w.scene.box_lo, w.scene.box_hi)
+    g_ref = oracle.adjoint(F, w.scene, lam.astype(np.float64))
+    l2, frac = grad_errors(g, g_ref)
+    assert l2 < 1e-3 and frac < 5e-3, (l2, frac)
+
+
 def test_ql_adjoint_locked_differences_including_entry_layer():
     w = _ql(unit_box_workload(40, 40))
     T2 = bi.temperature_grid(bi.plume_unit_box(2), w.scene.box_lo, w.scene.box_hi, w.scene.dims)
