@@ -92,3 +92,16 @@ def grad_errors(g: np.ndarray, ref: np.ndarray):
     bound = 1e-3 * np.maximum(np.abs(ref), 1e-2 * np.abs(ref).max())
     frac = float(np.mean(np.abs(g - ref) > bound))
     return l2, frac
+
+
+def bench_tuned(scenes):
+    """The launch shapes and checkpoint stride bench.py times for these scenes (api.Scene
+    objects, built as bench.py builds them): the autotuner's entry in the table shipped
+    with the package, never a tuning run here. The scenes come back with its stride."""
+    from paper_2509_14442_amd import autotune
+
+    e = autotune.tune(scenes, "fwd+adj", cache=None)
+    assert e["source"] == "table", e
+    assert e["layout"] == "cell", e
+    return autotune.launch_of(e), autotune.launch_of(e, "adj"), e["ckpt_stride"]
+

@@ -8,7 +8,7 @@ import torch
 
 import bos_inputs as bi
 import oracle
-from _common import exit_error, stored_delta
+from _common import bench_tuned, exit_error, stored_delta
 from paper_2509_14442_amd import api, autotune
 from test_gpu_forward import DEV, _np
 
@@ -191,25 +191,23 @@ def test_batch_mixing_samples_weights_and_pixel_lists():
 
 def test_batch64_bench_workload_on_sampled_rays():
     """The 64-scene workload of the benchmark (grids 48-192 per axis, cameras 128-1024 per
-    side, 20.6M rays, checkpoint stride 6) in one persistent forward and one persistent
-    adjoint launch. Per scene, 24 sampled rays: their wall exits against the oracle, and
-    the gradient of seeds that are non-zero only on them against the oracle's adjoint of
-    those rays."""
-    import bench
-
-    args = bench.parse([])
+    side, 20.6M rays) in one persistent forward and one persistent adjoint launch, with the
+    launch shapes and stride bench.py times. Per scene, 24 sampled rays: their wall exits
+    against the oracle, and the gradient of seeds that are non-zero only on them against
+    the oracle's adjoint of those rays."""
     pat_np = bi.blurred_noise(12, (1024, 1024)).astype(np.float32)
     pat = torch.from_numpy(pat_np).to(DEV)
-    launch = api.make_launch((8, 8), 4, persistent=True)
-    adj_launch = api.make_launch((8, 8), 2, persistent=True)
     scenes, temps = [], []
     for sc, spec in bi.scenes_batch(64):
-        sc = sc.replace(ckpt_stride=args.ckpt)
         T = bi.temperature_grid(spec, sc.box_lo, sc.box_hi, sc.dims).astype(np.float32)
         f = api.Field.from_temperature(torch.from_numpy(T).to(DEV), "f32")
         scenes.append(api.Scene(sc, f, pat))
         temps.append(T)
     assert sum(s.n_rays for s in scenes) > 20_000_000
+    # bench.py tunes on every 8th scene and applies the entry to all of them
+    launch, adj_launch, k = bench_tuned(scenes[::8])
+    for s in scenes:
+        s.struct.ckpt_stride = k
     tr = api.Tracer(scenes, launch, adjoint_launch=adj_launch)
     tr.forward()
     rng = np.random.default_rng(64)

@@ -19,7 +19,7 @@ import torch
 import bench
 import bos_inputs as bi
 import oracle
-from _common import exit_error, grad_errors, room_workload, stored_delta, unit_box_workload
+from _common import bench_tuned, exit_error, grad_errors, room_workload, stored_delta, unit_box_workload
 from paper_2509_14442_amd import api
 from test_gpu_forward import DEV, NOT_OFF, _np
 
@@ -99,7 +99,7 @@ def _target(w, seed):
     return _oracle(w2)[1]["image"]
 
 
-@pytest.mark.parametrize("tracer,ckpt", [(0, 16), (0, 1), (QL, 16)])
+@pytest.mark.parametrize("tracer,ckpt", [(0, 16), (0, 1), (0, 4), (QL, 16)])
 def test_sampled_radiometric_gradient_matches_oracle(tracer, ckpt):
     w = _with(unit_box_workload(40, 40), spp=4, seed=21, radiometry=1, tracer=tracer, ckpt_stride=ckpt)
     target = _target(w, 2)
@@ -170,9 +170,10 @@ def test_launch_shapes_agree_with_samples():
 
 
 def test_room_1m_pixels_4_samples_in_bench_configuration():
-    args = bench.parse([])
-    fwd, adj = bench.launches(args)
-    w = _with(room_workload((128, 128, 128), 1024, 1024, seed=3, ckpt=args.ckpt), spp=4, seed=11, radiometry=1)
+    w = _with(room_workload((128, 128, 128), 1024, 1024, seed=3), spp=4, seed=11, radiometry=1)
+    field = api.Field.from_temperature(torch.from_numpy(w.T32).to(DEV), "f32")
+    fwd, adj, k = bench_tuned([api.Scene(w.scene, field, torch.from_numpy(w.pattern32).to(DEV))])
+    w.scene = w.scene.replace(ckpt_stride=k)
     tr = _tracer(w, launch=fwd, adj_launch=adj)
     tr.forward().render()
     torch.cuda.synchronize()

@@ -84,9 +84,10 @@ def test_16bit_without_offset_misses_bound(dtype):
     assert EXIT_BOUND < e <= ceiling, (e, factor)
 
 
+@pytest.mark.parametrize("ckpt", [16, 4])
 @pytest.mark.parametrize("dtype,offset", CASES)
-def test_16bit_adjoint_against_dequantised(dtype, offset):
-    w = room_workload((64, 64, 48), 256, 256, seed=3)
+def test_16bit_adjoint_against_dequantised(dtype, offset, ckpt):
+    w = room_workload((64, 64, 48), 256, 256, seed=3, ckpt=ckpt)
     rng = np.random.default_rng(15)
     ids = np.sort(rng.choice(256 * 256, 4096, replace=False)).astype(np.int32)
     lam = rng.standard_normal((4096, 2)).astype(np.float32)

@@ -9,10 +9,9 @@ import numpy as np
 import pytest
 import torch
 
-import bench
 import bos_inputs as bi
 import oracle
-from _common import exit_error, grad_errors, oracle_forward, room_workload, stored_delta, unit_box_workload
+from _common import bench_tuned, exit_error, grad_errors, oracle_forward, room_workload, stored_delta, unit_box_workload
 from paper_2509_14442_amd import api
 from test_gpu_forward import DEV, NOT_OFF, _np
 
@@ -142,9 +141,10 @@ def test_ql_launch_shapes_agree():
 
 
 def test_ql_room_1m_in_bench_configuration():
-    args = bench.parse([])
-    fwd, adj = bench.launches(args)
-    w = _ql(room_workload((128, 128, 128), 1024, 1024, seed=3, ckpt=args.ckpt))
+    w = _ql(room_workload((128, 128, 128), 1024, 1024, seed=3))
+    field = api.Field.from_temperature(torch.from_numpy(w.T32).to(DEV), "f32")
+    fwd, adj, k = bench_tuned([api.Scene(w.scene, field, torch.from_numpy(w.pattern32).to(DEV))])
+    w.scene = w.scene.replace(ckpt_stride=k)
     tr = _tracer(w, fwd, adj)
     tr.forward()
     uv = _np(tr.uv[0])

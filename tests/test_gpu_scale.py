@@ -18,21 +18,21 @@ import numpy as np
 import pytest
 import torch
 
-import bench
 import bos_inputs as bi
 import oracle
-from _common import (RHO0G, Workload, exit_error, expected_scale, grad_errors, oracle_forward, room_workload,
-                     stored_delta)
+from _common import (RHO0G, Workload, bench_tuned, exit_error, expected_scale, grad_errors, oracle_forward,
+                     room_workload, stored_delta)
 from paper_2509_14442_amd import api
 from test_gpu_forward import DEV, _np
 
 pytestmark = pytest.mark.gpu
 
 
-def _bench_launches():
-    args = bench.parse([])
-    fwd, adj = bench.launches(args)
-    return fwd, adj, args.ckpt
+def _bench_config(w, dtype="f32", offset=0.0):
+    """bench.py's tuned launches and stride for workload w stored as dtype."""
+    field = api.Field.from_temperature(torch.from_numpy(w.T32).to(DEV), dtype, None if dtype != "f32" else 1.0,
+                                       offset)
+    return bench_tuned([api.Scene(w.scene, field, torch.from_numpy(w.pattern32).to(DEV))])
 
 
 def _tracer(w, launch=None, adj_launch=None, dtype="f32", offset=0.0, ids=None, ckpt=True):
@@ -44,8 +44,9 @@ def _tracer(w, launch=None, adj_launch=None, dtype="f32", offset=0.0, ids=None, 
 
 
 def test_room_1m_in_bench_configuration():
-    fwd, adj, k = _bench_launches()
-    w = room_workload((128, 128, 128), 1024, 1024, seed=3, ckpt=k)
+    w = room_workload((128, 128, 128), 1024, 1024, seed=3)
+    fwd, adj, k = _bench_config(w)
+    w.scene = w.scene.replace(ckpt_stride=k)
     tr, field = _tracer(w, fwd, adj)
     tr.forward()
     uv, ns = _np(tr.uv[0]), _np(tr.n_steps[0])
@@ -135,11 +136,12 @@ def test_room256_16bit_ambient_subsample(dtype):
     """The 256 x 256 x 192 room, 2048 x 1536 rays, <= 1024 steps, with the default 16-bit
     storage (ambient offset): exits within 1e-6 m of the oracle on the dequantised field and
     within 1e-5 m on the exact field, gradient within 1e-3, on a seeded 4096-ray subsample."""
-    fwd, adj, _ = _bench_launches()
     desc = bi.scene_room_256_3m()
     lo, hi = desc.box_lo, desc.box_hi
     T = bi.temperature_grid(bi.plumes_room(5, lo, hi), lo, hi, desc.dims).astype(np.float32)
     w = Workload(desc, T, bi.blurred_noise(12, (desc.pat_h, desc.pat_w)))
+    fwd, adj, k = _bench_config(w, dtype, RHO0G)
+    w.scene = w.scene.replace(ckpt_stride=k)
     print(f"room256 {dtype} ambient subsample", flush=True)
     tr, field = _tracer(w, fwd, adj, dtype, RHO0G, ckpt=False)
     tr.forward()
