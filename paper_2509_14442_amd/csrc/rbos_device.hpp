@@ -36,6 +36,12 @@ template <class T>
 __device__ __forceinline__ void gst(T* p, T v) {
   *(RBOS_GLOBAL T*)p = v;
 }
+// Streaming store (non-temporal hint): data written once and read back much later, such
+// as the checkpoints, then does not displace the field records from the caches.
+template <class T>
+__device__ __forceinline__ void gst_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, (RBOS_GLOBAL T*)p);
+}
 __device__ __forceinline__ void gatomic_add(double* p, double v) {
   __builtin_amdgcn_global_atomic_fadd_f64((RBOS_GLOBAL double*)p, v);
 }
@@ -925,14 +931,14 @@ __device__ __forceinline__ void store_ray_header(const SceneDev& S, int r, const
   const size_t P = (size_t)S.ckpt_pad;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    gst(p + (0 + a) * P, B.U0hi[a]);
-    gst(p + (3 + a) * P, B.U0lo[a]);
-    gst(p + (6 + a) * P, B.g2hi[a]);
-    gst(p + (9 + a) * P, B.g2lo[a]);
-    gst(p + (12 + a) * P, B.V[a]);
-    gst(p + (15 + a) * P, st.e[a]);
+    gst_stream(p + (0 + a) * P, B.U0hi[a]);
+    gst_stream(p + (3 + a) * P, B.U0lo[a]);
+    gst_stream(p + (6 + a) * P, B.g2hi[a]);
+    gst_stream(p + (9 + a) * P, B.g2lo[a]);
+    gst_stream(p + (12 + a) * P, B.V[a]);
+    gst_stream(p + (15 + a) * P, st.e[a]);
   }
-  gst(p + 18 * P, s);
+  gst_stream(p + 18 * P, s);
 }
 
 __device__ __forceinline__ void load_ray_header(const SceneDev& S, int r, RayBase& B, float e_end[3], float& s) {

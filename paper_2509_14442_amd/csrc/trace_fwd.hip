@@ -91,8 +91,8 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int
         sharma_step<DT>(S, B, st, C, NoRecord(), [&]() {
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            gst(ck + (size_t)a * S.ckpt_pad, st.d[a]);
-            gst(ck + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
+            gst_stream(ck + (size_t)a * S.ckpt_pad, st.d[a]);
+            gst_stream(ck + (size_t)(3 + a) * S.ckpt_pad, st.e[a]);
           }
         });
         ck += slot_stride;
