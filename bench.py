@@ -392,7 +392,7 @@ class Workload:
         scene; returns the forward and adjoint launches."""
         from paper_2509_14442_amd import autotune
 
-        entry = autotune.tune(sub, "fwd+adj", targets, reps=1 if apply_to is not None else 2,
+        entry = autotune.tune(sub, "fwd+adj", targets, reps=2 if apply_to is not None else 3,
                               force=self.args.tune == 2)
         for i, s in enumerate(apply_to if apply_to is not None else sub):
             s.struct.ckpt_stride = entry["ckpt_stride"]

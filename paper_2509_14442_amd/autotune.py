@@ -16,6 +16,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
@@ -30,14 +31,18 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_table
 LAUNCHES: List[Tuple[Tuple[int, int], int, bool, int]] = [
     ((8, 8), 4, False, 0),
     ((8, 8), 2, False, 0),
+    ((8, 8), 1, False, 0),
     ((16, 4), 4, False, 0),
+    ((32, 2), 4, False, 0),
+    ((64, 1), 4, False, 0),
     ((8, 8), 4, True, 0),
     ((8, 8), 2, True, 0),
     ((8, 8), 4, True, 2),
 ]
 # 1: every step stored (24 B per ray-step), no replay; 3, 4: chunks that record their
-# samples for the reverse; 6: chunks of 6 at 4 wavefronts per SIMD; 8, 16, 32: chunks of 8
-STRIDES = (1, 3, 4, 6, 8, 16, 32)
+# samples for the reverse; 6: chunks of 6 at 4 wavefronts per SIMD; 8, 16, 32, 64: chunks
+# of 8
+STRIDES = (1, 3, 4, 6, 8, 16, 32, 64)
 LAYOUTS = ("cell", "xpair")
 
 
@@ -85,6 +90,15 @@ def _time(fn, reps: int) -> float:
     return best
 
 
+def _warm(fn, seconds: float) -> None:
+    """Run fn back to back for about `seconds`, so that the first candidates are not timed
+    while the device clocks are still rising."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        fn()
+        torch.cuda.synchronize()
+
+
 def _entry_of(launch_t) -> Dict:
     (tw, th), wpb, pers, bpc = launch_t
     return {"tile": [tw, th], "waves_per_block": wpb, "persistent": bool(pers), "blocks_per_cu": bpc}
@@ -92,7 +106,7 @@ def _entry_of(launch_t) -> Dict:
 
 def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[torch.Tensor]] = None,
          strides: Sequence[int] = STRIDES, launches=LAUNCHES, layouts: Sequence[str] = LAYOUTS,
-         hbm_budget: Optional[int] = None, reps: int = 2, cache: Optional[str] = DEFAULT_CACHE,
+         hbm_budget: Optional[int] = None, reps: int = 3, cache: Optional[str] = DEFAULT_CACHE,
          force: bool = False, table: Optional[str] = TABLE) -> Dict:
     """Pick launch shapes, the checkpoint stride and the field layout for these scenes;
     returns the cached or new entry {"fwd": launch, "adj": launch, "ckpt_stride", "layout",
@@ -100,7 +114,7 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
     absent for mode "fwd"). The scenes come back with the chosen stride; the layout is the
     caller's to apply (Field.relayout).
 
-    Stage 1 times the forward trace (with checkpoints at stride 16 unless mode is "fwd")
+    After a short warm-up, stage 1 times the forward trace (with checkpoints at stride 16 unless mode is "fwd")
     for every launch shape, stage 2 the adjoint alone for every shape after one forward
     with the best forward shape, stage 3 the whole forward + render + adjoint for every
     stride whose checkpoints fit `hbm_budget` (default: half the free device memory), stage 4
@@ -135,6 +149,7 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
                           adjoint_launch=api.make_launch(*adj_t) if adj_t is not None else None)
 
     default_stride = 16 if adj else 0
+    _warm(tracer(launches[0], None, default_stride).forward, 0.3)
     fwd_ms = [(_time(tracer(lt, None, default_stride).forward, reps), lt) for lt in launches]
     fwd_ms.sort(key=lambda x: x[0])
     best_fwd = fwd_ms[0][1]

@@ -105,7 +105,8 @@ def test_autotune_picks_valid_config(tmp_path):
     b = _batch(2)
     scenes = [s for s, _ in b]
     entry = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"), reps=1, table=None,
-                          launches=autotune.LAUNCHES[:2] + autotune.LAUNCHES[3:4], strides=(1, 8, 16))
+                          launches=autotune.LAUNCHES[:2] + [l for l in autotune.LAUNCHES if l[2]][:1],
+                          strides=(1, 8, 16))
     assert entry["ckpt_stride"] in (1, 8, 16) and entry["ms"] > 0 and entry["source"] == "measured"
     assert {"fwd", "adj"} <= set(entry)
     again = autotune.tune(scenes, "fwd+adj", cache=str(tmp_path / "tune.json"))
