@@ -153,14 +153,17 @@ __device__ __forceinline__ float wave_sum8(const float v[8]) {
 // chunk) and at the end of the tile, so the atomics' latency is exposed once per chunk
 // rather than once per cell (a non-returning atomic still counts in vmcnt, which the
 // next load waits on). A miss with every slot taken writes one slot out at once.
+// The slot masks are 32-bit (one scalar register each): the kernels run at the scalar
+// register limit, and every register freed spares a reload of a scene constant.
 constexpr int PEND_SLOTS = 32;
+static_assert(PEND_SLOTS == 32, "slot masks are one 32-bit word, all of whose bits are slots");
 
 struct Pending {
-  float* vals;                  // LDS, PEND_SLOTS * 8 floats, wave-private
-  int key;                      // lane p < PEND_SLOTS: key of slot p; CELL_NONE when free (always for p >= PEND_SLOTS)
-  int next;                     // wave-uniform: slot replaced when all are taken
-  unsigned long long occupied;  // wave-uniform slot masks
-  unsigned long long touched;   // slots hit or filled since the last chunk end
+  float* vals;        // LDS, PEND_SLOTS * 8 floats, wave-private
+  int key;            // lane p < PEND_SLOTS: key of slot p; CELL_NONE when free (always for p >= PEND_SLOTS)
+  int next;           // wave-uniform: slot replaced when all are taken
+  unsigned occupied;  // wave-uniform slot masks
+  unsigned touched;   // slots hit or filled since the last chunk end
 };
 
 __device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, int c) {
@@ -187,15 +190,15 @@ __device__ __forceinline__ int group_corner(int lane) {
 // free slot, or writing one out, when the cell has none.
 __device__ __forceinline__ void cache_add(const SceneDev& S, Pending& P, int key, float total, int lane) {
   const int corner = group_corner(lane);
-  const unsigned long long hit = __ballot(P.key == key);
+  const unsigned hit = (unsigned)__ballot(P.key == key);  // only lanes < PEND_SLOTS hold keys
   int slot;
   if (hit) {
-    slot = __ffsll((long long)hit) - 1;
+    slot = __ffs((int)hit) - 1;
     if ((lane & 7) == 0) atomicAdd(&P.vals[slot * 8 + corner], total);
   } else {
-    const unsigned long long freem = ~P.occupied & ((1ull << PEND_SLOTS) - 1);
+    const unsigned freem = ~P.occupied;
     if (freem) {
-      slot = __ffsll((long long)freem) - 1;
+      slot = __ffs((int)freem) - 1;
     } else {
       slot = P.next;
       P.next = (P.next + 1) & (PEND_SLOTS - 1);
@@ -206,9 +209,9 @@ __device__ __forceinline__ void cache_add(const SceneDev& S, Pending& P, int key
     }
     if ((lane & 7) == 0) P.vals[slot * 8 + corner] = total;
     if (lane == slot) P.key = key;
-    P.occupied |= 1ull << slot;
+    P.occupied |= 1u << slot;
   }
-  P.touched |= 1ull << slot;
+  P.touched |= 1u << slot;
   wave_lds_order();
 }
 
@@ -220,11 +223,12 @@ __device__ __forceinline__ void flush(const SceneDev& S, Accum& A, bool sel, int
     const int leader = __ffsll((long long)pend) - 1;
     const int key = __builtin_amdgcn_readlane(A.key, leader);
     const bool mine = sel && A.key == key;
+    const unsigned long long mine_m = __ballot(A.key == key);  // a single comparison: no VALU round trip
     float v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = mine ? A.acc[k] : 0.0f;
     cache_add(S, P, key, wave_sum8(v), lane);
-    pend &= ~__ballot(mine);
+    pend &= ~mine_m;
   }
   if (sel) {
 #pragma unroll
@@ -241,48 +245,56 @@ __device__ __forceinline__ void flush_parks(const SceneDev& S, Accum& A, bool tr
     const int leader = __ffsll((long long)pend) - 1;
     const int key = __builtin_amdgcn_readlane(A.pkey, leader);
     const bool mine = A.pkey == key;
+    const unsigned long long mine_m = __ballot(A.pkey == key);  // taken before the pkey reset below
     float v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = mine ? A.park[k] : 0.0f;
     cache_add(S, P, key, wave_sum8(v), lane);
-    pend &= ~__ballot(mine);
+    pend &= ~mine_m;
     if (mine) A.pkey = CELL_NONE;
   }
 }
 
 // Write the slots in `which` out to the gradient and free them.
-__device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigned long long which, int lane) {
+__device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigned which, int lane) {
   wave_lds_order();
 #pragma unroll 1
   for (int q = 0; q < PEND_SLOTS * 8 / 64; ++q) {
-    if (((which >> (8 * q)) & 0xffull) == 0) continue;
+    if (((which >> (8 * q)) & 0xffu) == 0) continue;
     const int idx = q * 64 + lane, slot = idx >> 3;
     const int key = __shfl(P.key, slot);
-    if ((which >> slot) & 1ull)
+    if ((which >> slot) & 1u)
       gatomic_add(voxel_of_corner(S, key, idx & 7), corner_of_monomials(P.vals + slot * 8, idx & 7) * S.inv_dec_d);
   }
   wave_lds_order();
-  if ((which >> lane) & 1ull) P.key = CELL_NONE;
+  if (lane < PEND_SLOTS && ((which >> lane) & 1u)) P.key = CELL_NONE;
   P.occupied &= ~which;
 }
 
 // Chunk end: write out the slots the chunk did not touch (cells the rays have left).
 __device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lane) {
-  const unsigned long long stale = P.occupied & ~P.touched;
+  const unsigned stale = P.occupied & ~P.touched;
   if (stale) write_out(S, P, stale, lane);
   P.touched = 0;
 }
 
 // Lanes with act take a sample in cell `key`: a lane that enters a new cell parks the sums
 // of the one it leaves (after its park has been flushed, if taken), or flushes them
-// without PARK, and starts from zero. The caller then adds the sample to A.acc.
+// without PARK, and starts from zero. The caller then adds the sample to A.acc. act_m is
+// the ballot of act, which the caller takes once for all stages of a step. The wave-uniform
+// tests combine ballots of single comparisons in scalar registers: a ballot of a compound
+// lane predicate is lowered through a VALU select and compare, on the latency path of
+// every sample.
 template <bool PARK>
-__device__ __forceinline__ void enter(const SceneDev& S, Accum& A, bool act, int key, int lane, Pending& P) {
+__device__ __forceinline__ void enter(const SceneDev& S, Accum& A, bool act, unsigned long long act_m, int key,
+                                      int lane, Pending& P) {
   const bool out = act && key != A.key && A.key != CELL_NONE;
-  if (__ballot(out)) {
+  const unsigned long long out_m = act_m & __ballot(key != A.key) & __ballot(A.key != CELL_NONE);
+  if (out_m) {
     if (PARK) {
       const bool busy = out && A.pkey != CELL_NONE;
-      if (__ballot(busy)) flush_parks(S, A, busy, lane, P);
+      const unsigned long long busy_m = out_m & __ballot(A.pkey != CELL_NONE);
+      if (busy_m) flush_parks(S, A, busy, lane, P);
       if (out) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -302,7 +314,7 @@ __device__ __forceinline__ void enter(const SceneDev& S, Accum& A, bool act, int
 template <bool PARK>
 __device__ __forceinline__ void accumulate(const SceneDev& S, Accum& A, bool act, int key, const float ct[8],
                                            int lane, Pending& P) {
-  enter<PARK>(S, A, act, key, lane, P);
+  enter<PARK>(S, A, act, __ballot(act), key, lane, P);
   if (act) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) A.acc[k] += ct[k];
@@ -461,7 +473,8 @@ __device__ __forceinline__ void reverse_stages(const SceneDev& S, Accum& A, Pend
                                                const SampleRev& R1, const SampleRev& R2, const SampleRev& R3,
                                                float wA[3], float wB[3], float rb[3], float tb[3], int lane) {
   float rs[3], ts[3];
-  enter<PARK>(S, A, act, act ? R3.key : 0, lane, P);
+  const unsigned long long act_m = __ballot(act);
+  enter<PARK>(S, A, act, act_m, act ? R3.key : 0, lane, P);
   if (act) {  // stage C
     float w[3], p[3];
 #pragma unroll
@@ -474,7 +487,7 @@ __device__ __forceinline__ void reverse_stages(const SceneDev& S, Accum& A, Pend
       wB[a] = fmaf(S.c_p3[a], p[a], wB[a]);
     }
   }
-  enter<PARK>(S, A, act, act ? R2.key : 0, lane, P);
+  enter<PARK>(S, A, act, act_m, act ? R2.key : 0, lane, P);
   if (act) {  // stage B
     float p[3];
     force_rev(S, R2, wB, p, A.acc);
@@ -485,7 +498,7 @@ __device__ __forceinline__ void reverse_stages(const SceneDev& S, Accum& A, Pend
       wA[a] = fmaf(S.c_p2[a], p[a], wA[a]);
     }
   }
-  enter<PARK>(S, A, act, act ? R1.key : 0, lane, P);
+  enter<PARK>(S, A, act, act_m, act ? R1.key : 0, lane, P);
   if (act) {  // stage A
     float p[3];
     force_rev(S, R1, wA, p, A.acc);
@@ -518,7 +531,7 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 
   Accum A;
   accum_init(A);
-  Pending P{replay + KS * 6 * 64, CELL_NONE, 0, 0ull, 0ull};
+  Pending P{replay + KS * 6 * 64, CELL_NONE, 0, 0u, 0u};
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
     for (int ch = m_chunks - 1; ch >= 0; --ch) {
@@ -625,8 +638,8 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
   drain(S, A, P, lane);
 }
 
-// Recording form (checkpoint strides that are multiples of KS = 3 or 4): the replay of a
-// chunk keeps, for each of its steps, the record index and fractions of the step's three
+// Recording form (checkpoint strides KS = 3 and 4, one chunk per checkpoint segment): the
+// replay of a chunk keeps, for each of its steps, the record index and fractions of the step's three
 // samples as the forward located them (16 bytes per sample and lane in LDS, sample s of
 // step i of lane l at [(i * 3 + s) * 64 + l]). The reverse of a step then reads them back,
 // issues its three cell gathers together and evaluates value, gradient and mixed second
@@ -653,62 +666,57 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
   const RayBase& B = R.B;
   float* rb = R.rb;
   float* tb = R.tb;
-  const int K = S.ckpt_k;  // a multiple of KS
-  const int m_chunks = K / KS;
-  const int nseg = wave_max_nonneg(active ? (n + K - 1) / K : 0);
+  // the launcher takes this form only for a checkpoint stride of KS: a segment is one chunk
+  const int nseg = wave_max_nonneg(active ? (n + KS - 1) / KS : 0);
 
   Accum A;
   accum_init(A);
-  Pending P{lds + KS * 3 * 64 * 4, CELL_NONE, 0, 0ull, 0ull};
+  Pending P{lds + KS * 3 * 64 * 4, CELL_NONE, 0, 0u, 0u};
   f32x4* smp = reinterpret_cast<f32x4*>(lds);
 
   for (int seg = nseg - 1; seg >= 0; --seg) {
-    for (int ch = m_chunks - 1; ch >= 0; --ch) {
-      const int c0 = seg * K + ch * KS;  // first step of the chunk
-      const bool lane_chunk = active && c0 < n;
-      if (lane_chunk) {
-        State st;
-        Cell C;
-        state_at_step(B, seg * K, st);
-        if (seg == 0) {
+    const int c0 = seg * KS;  // first step of the chunk
+    const bool lane_chunk = active && c0 < n;
+    if (lane_chunk) {
+      State st;
+      Cell C;
+      state_at_step(B, c0, st);
+      if (seg == 0) {
 #pragma unroll
-          for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
-        } else {
-          load_ckpt(S, q, seg - 1, st);
-        }
-        locate_state(S, B, st, C);
-#pragma unroll 1
-        for (int i = 0; i < ch * KS; ++i) sharma_step<DT>(S, B, st, C);  // to the chunk start
-        // the chunk's steps, the last one only up to its third sample
-        const int cnt = min(KS, n - c0);
-#pragma unroll 1
-        for (int i = 0; i < cnt - 1; ++i) sharma_step<DT>(S, B, st, C, SampleRow{smp + i * 3 * 64 + lane});
-        sharma_step<DT, SampleRow, NoIssue, false>(S, B, st, C, SampleRow{smp + (cnt - 1) * 3 * 64 + lane});
+        for (int a = 0; a < 3; ++a) { st.d[a] = 0.0f; st.e[a] = 0.0f; }
+      } else {
+        load_ckpt(S, q, seg - 1, st);
       }
-      // reverse the chunk's steps, one stage at a time (C, B, A)
+      locate_state(S, B, st, C);
+      // the chunk's steps, the last one only up to its third sample
+      const int cnt = min(KS, n - c0);
 #pragma unroll 1
-      for (int i = KS - 1; i >= 0; --i) {
-        const bool act = lane_chunk && (c0 + i < n);
-        SampleRev R1, R2, R3;
-        float wA[3], wB[3];
-        if (act) {
-          const f32x4* row = smp + i * 3 * 64 + lane;
-          const f32x4 s1 = row[0], s2 = row[64], s3 = row[128];
-          const unsigned r1 = __float_as_uint(s1.x), r2 = __float_as_uint(s2.x), r3 = __float_as_uint(s3.x);
-          float c1[8], c2[8], c3[8];
-          fetch_cell<DT>(S, r3, c3);
-          fetch_cell<DT>(S, r2, c2);
-          fetch_cell<DT>(S, r1, c1);
-          const float f3[3] = {s3.y, s3.z, s3.w}, f2[3] = {s2.y, s2.z, s2.w}, f1[3] = {s1.y, s1.z, s1.w};
-          sample_rev_at(S, c3, r3, f3, R3);
-          sample_rev_at(S, c2, r2, f2, R2);
-          sample_rev_at(S, c1, r1, f1, R1);
-          stage_weights(S, rb, tb, wA, wB);
-        }
-        reverse_stages<PARK>(S, A, P, act, R1, R2, R3, wA, wB, rb, tb, lane);
-      }
-      chunk_end(S, P, lane);
+      for (int i = 0; i < cnt - 1; ++i) sharma_step<DT>(S, B, st, C, SampleRow{smp + i * 3 * 64 + lane});
+      sharma_step<DT, SampleRow, NoIssue, false>(S, B, st, C, SampleRow{smp + (cnt - 1) * 3 * 64 + lane});
     }
+    // reverse the chunk's steps, one stage at a time (C, B, A)
+#pragma unroll 1
+    for (int i = KS - 1; i >= 0; --i) {
+      const bool act = lane_chunk && (c0 + i < n);
+      SampleRev R1, R2, R3;
+      float wA[3], wB[3];
+      if (act) {
+        const f32x4* row = smp + i * 3 * 64 + lane;
+        const f32x4 s1 = row[0], s2 = row[64], s3 = row[128];
+        const unsigned r1 = __float_as_uint(s1.x), r2 = __float_as_uint(s2.x), r3 = __float_as_uint(s3.x);
+        float c1[8], c2[8], c3[8];
+        fetch_cell<DT>(S, r3, c3);
+        fetch_cell<DT>(S, r2, c2);
+        fetch_cell<DT>(S, r1, c1);
+        const float f3[3] = {s3.y, s3.z, s3.w}, f2[3] = {s2.y, s2.z, s2.w}, f1[3] = {s1.y, s1.z, s1.w};
+        sample_rev_at(S, c3, r3, f3, R3);
+        sample_rev_at(S, c2, r2, f2, R2);
+        sample_rev_at(S, c1, r1, f1, R1);
+        stage_weights(S, rb, tb, wA, wB);
+      }
+      reverse_stages<PARK>(S, A, P, act, R1, R2, R3, wA, wB, rb, tb, lane);
+    }
+    chunk_end(S, P, lane);
   }
   float V0[3] = {0.0f, 0.0f, 0.0f};
   if (active) {
@@ -758,6 +766,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(rec_waves_p
 
 template <int DT, int KS>
 static hipError_t launch_adj_rec(const LaunchPlan& P, hipStream_t stream) {
+  if (P.ckpt_k != KS) return hipErrorInvalidValue;  // one chunk per checkpoint segment
   const size_t lds = sizeof(float) * rec_floats_per_wave<KS>() * (size_t)P.wpb;
   if (P.persistent) {
     const int grid = persistent_grid(k_trace_adj_rec_persistent<DT, KS>, P, lds);
@@ -791,7 +800,7 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
   const float h = S.hf, h_6 = S.h_6;
   Accum A;
   accum_init(A);
-  Pending P{cache, CELL_NONE, 0, 0ull, 0ull};
+  Pending P{cache, CELL_NONE, 0, 0u, 0u};
   float pv[3] = {0.0f, 0.0f, 0.0f};  // dL/dv0 through the stage points (grid units)
 #pragma unroll 1
   for (int j = 0; j < npts; ++j) {
@@ -831,7 +840,7 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
 #pragma unroll
       for (int a = 0; a < 3; ++a) w[a] = v[a] * S.km[a];  // dL/dK -> dL/dG
     }
-    enter<true>(S, A, act, act ? Rs.key : 0, lane, P);
+    enter<true>(S, A, act, __ballot(act), act ? Rs.key : 0, lane, P);
     if (act) {
       float p[3];
       force_rev(S, Rs, w, p, A.acc);
