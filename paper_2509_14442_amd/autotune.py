@@ -114,11 +114,13 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
     absent for mode "fwd"). The scenes come back with the chosen stride; the layout is the
     caller's to apply (Field.relayout).
 
-    After a short warm-up, stage 1 times the forward trace (with checkpoints at stride 16 unless mode is "fwd")
-    for every launch shape, stage 2 the adjoint alone for every shape after one forward
-    with the best forward shape, stage 3 the whole forward + render + adjoint for every
-    stride whose checkpoints fit `hbm_budget` (default: half the free device memory), stage 4
-    the best of those with the scenes' fields re-encoded in each other layout. With force
+    After a short warm-up, stage 1 times the forward trace (with checkpoints at stride 16
+    unless mode is "fwd") for every launch shape, stage 2 the adjoint alone for every shape
+    after one forward with the best forward shape, stage 3 the whole forward + render + adjoint for every
+    stride whose checkpoints fit `hbm_budget` (default: half the free device memory), then the
+    adjoint alone again for every shape at the chosen stride (the adjoint's form depends on
+    the stride), stage 4 the best of those with the scenes' fields re-encoded in each other
+    layout. With force
     the cache and the table are not consulted."""
     key = cache_key(scenes, mode)
     db = {}
@@ -183,6 +185,23 @@ def tune(scenes: List[api.Scene], mode: str = "fwd+adj", targets: Optional[List[
             ms = whole(st)
             if ms < best[0]:
                 best = (ms, st)
+        if best[1] != default_stride:
+            # the adjoint's form follows the stride, and so does its best launch
+            first_adj, adj_ms = best_adj, []
+            for lt in launches:
+                tr = tracer(best_fwd, lt, best[1])
+                tr.forward()
+                tr.render(tg)
+                adj_ms.append((_time(lambda: tr.adjoint(grads, zero=False), reps), lt))
+                del tr
+            adj_ms.sort(key=lambda x: x[0])
+            if adj_ms[0][1] != first_adj:
+                best_adj = adj_ms[0][1]
+                ms = whole(best[1])
+                if ms < best[0]:
+                    best = (ms, best[1])
+                else:
+                    best_adj = first_adj
         entry.update({"adj": _entry_of(best_adj), "ckpt_stride": best[1], "ms": best[0]})
     own = scenes[0].field.layout if scenes else "cell"
     entry["layout"] = own

@@ -5,8 +5,8 @@
 // the last to the first, aligned on the step index so that the tile's rays move through
 // the same cells together. A segment is replayed forward from its checkpoint in chunks
 // of KS steps, keeping in LDS either each step's start state (then the reverse relocates
-// the step's samples) or, for strides 3 and 4, the cells and fractions of its three
-// samples; the chunk is then reversed step by step. Each sample's contributions are
+// the step's samples) or, for strides 3 and 4 (a segment is then one chunk), the cells
+// and fractions of its three samples; the chunk is then reversed step by step. Each sample's contributions are
 // merged per lane, as monomial coefficients, while the ray stays in one cell; lanes that
 // left the same cell are summed across the wavefront into a per-wavefront LDS cache of
 // cell totals, which goes to the gradient with one FP64 atomic per corner. Loops stay
