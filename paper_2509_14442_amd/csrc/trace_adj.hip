@@ -857,9 +857,11 @@ __device__ __forceinline__ void adjoint_tile_ql(const SceneDev& S, int tile, int
   drain(S, A, P, lane);
 }
 
+// Held to 80 registers for 6 wavefronts per SIMD: this latency-bound grid form runs 4 %
+// faster that way, its small spill included (the persistent form gains nothing from it).
 template <int DT>
-__global__ __launch_bounds__(256) void k_trace_adj_ql(const SceneDev* __restrict__ scenes, int n_scenes,
-                                                      int total_tiles, int wpb, int nblocks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_trace_adj_ql(
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, int wpb, int nblocks) {
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
   if (gtile >= total_tiles) return;  // whole wavefront

@@ -168,9 +168,11 @@ __device__ __forceinline__ void trace_one(const SceneDev& S, int r, int pix, int
   }
 }
 
+// Held to 64 registers for 8 wavefronts per SIMD (68 would allow 7): the trace without
+// checkpoints runs 3 % faster; with checkpoints it is unchanged.
 template <int DT, bool QL>
-__global__ __launch_bounds__(256) void k_trace_fwd(const SceneDev* __restrict__ scenes, int n_scenes,
-                                                   int total_tiles, int wpb, int nblocks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_trace_fwd(
+    const SceneDev* __restrict__ scenes, int n_scenes, int total_tiles, int wpb, int nblocks) {
   const int wave = wave_uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int gtile = xcd_remap(blockIdx.x, nblocks) * wpb + wave;
   if (gtile >= total_tiles) return;
