@@ -291,6 +291,7 @@ __device__ __forceinline__ void enter(const SceneDev& S, Accum& A, bool act, uns
   const bool out = act && key != A.key && A.key != CELL_NONE;
   const unsigned long long out_m = act_m & __ballot(key != A.key) & __ballot(A.key != CELL_NONE);
   if (out_m) {
+    __builtin_amdgcn_s_setprio(3);  // the merge's reduction chains first (see the recording form)
     if (PARK) {
       const bool busy = out && A.pkey != CELL_NONE;
       const unsigned long long busy_m = out_m & __ballot(A.pkey != CELL_NONE);
@@ -306,6 +307,7 @@ __device__ __forceinline__ void enter(const SceneDev& S, Accum& A, bool act, uns
     } else {
       flush(S, A, out, lane, P);
     }
+    __builtin_amdgcn_s_setprio(1);
   }
   if (act) A.key = key;
 }
@@ -677,6 +679,11 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int c0 = seg * KS;  // first step of the chunk
     const bool lane_chunk = active && c0 < n;
+    // Wave priority, lowest to highest: the replay (a chain of dependent gathers), the
+    // reverse (independent gathers, long VALU runs), the merge (serial wavefront
+    // reductions, raised in `enter`). Each ordering step measured -2 % adjoint time in
+    // alternating runs, whatever the levels.
+    __builtin_amdgcn_s_setprio(0);
     if (lane_chunk) {
       State st;
       Cell C;
@@ -695,6 +702,7 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
       sharma_step<DT, SampleRow, NoIssue, false>(S, B, st, C, SampleRow{smp + (cnt - 1) * 3 * 64 + lane});
     }
     // reverse the chunk's steps, one stage at a time (C, B, A)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll 1
     for (int i = KS - 1; i >= 0; --i) {
       const bool act = lane_chunk && (c0 + i < n);
