@@ -131,10 +131,12 @@ typedef struct rbos_scene {
   double proj_fov_x_deg;
   /* integrator: Sharma RK4 step h in the ray parameter t (at most 4 voxels), step cap
      (1 .. 65536), checkpoint stride k (0 = no checkpoints; 1 = every step's state is
-     stored and the adjoint reads it instead of replaying: 24 B per ray-step; 6: replayed
-     in chunks of 6, whose smaller on-chip buffer lets more wavefronts share a compute
-     unit; else a multiple of 8 up to 256, replayed in chunks of 8; rbos_trace_adjoint
-     needs k > 0).
+     stored and the adjoint reads it instead of replaying: 24 B per ray-step; 3 or 4: each
+     segment is replayed once and the cell and fractions of its samples are kept on chip
+     for the reverse, the fastest adjoint (3 is the autotuned choice on MI355X); 6:
+     replayed in chunks of 6, whose smaller on-chip buffer lets more wavefronts share a
+     compute unit; else a multiple of 8 up to 256, replayed in chunks of 8; any other
+     value is rejected with RBOS_E_UNSUPPORTED; rbos_trace_adjoint needs k > 0).
      With the quasi-linear tracer the adjoint needs no states: any k > 0 stores only the
      per-ray header. */
   double step;
