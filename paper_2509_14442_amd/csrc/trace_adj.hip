@@ -149,9 +149,9 @@ __device__ __forceinline__ float wave_sum8(const float v[8]) {
 // atomics: a cell is left by the tile's rays over several steps (the bundle crosses a
 // face obliquely), so its partial totals are merged here and reach the gradient once.
 // Slot p holds 8 corner totals in LDS (corner a + 2b + 4c) and its key in lane p of one
-// register. Slots are written out in batches at chunk ends (those not touched during the
-// chunk) and at the end of the tile, so the atomics' latency is exposed once per chunk
-// rather than once per cell (a non-returning atomic still counts in vmcnt, which the
+// register. Slots are written out in batches every few chunks (those not touched since
+// the last batch) and at the end of the tile, so the atomics' latency is exposed once per
+// batch rather than once per cell (a non-returning atomic still counts in vmcnt, which the
 // next load waits on). A miss with every slot taken writes one slot out at once.
 // The slot masks are 32-bit (one scalar register each): the kernels run at the scalar
 // register limit, and every register freed spares a reload of a scene constant.
@@ -271,7 +271,7 @@ __device__ __forceinline__ void write_out(const SceneDev& S, Pending& P, unsigne
   P.occupied &= ~which;
 }
 
-// Chunk end: write out the slots the chunk did not touch (cells the rays have left).
+// Batch write-out: the slots not touched since the last one (cells the rays have left).
 __device__ __forceinline__ void chunk_end(const SceneDev& S, Pending& P, int lane) {
   const unsigned stale = P.occupied & ~P.touched;
   if (stale) write_out(S, P, stale, lane);
@@ -650,6 +650,10 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 template <int KS>
 constexpr int rec_floats_per_wave() { return KS * 3 * 64 * 4 + PEND_SLOTS * 8; }
 
+// Chunks between two write-outs of the cache's stale slots.
+template <int KS>
+constexpr int rec_writeout_chunks() { return KS == 3 ? 3 : 2; }
+
 // Recorder of the replay: sample s of the step at row[s * 64].
 struct SampleRow {
   f32x4* row;
@@ -724,7 +728,10 @@ __device__ __forceinline__ void adjoint_tile_rec(const SceneDev& S, int tile, in
       }
       reverse_stages<PARK>(S, A, P, act, R1, R2, R3, wA, wB, rb, tb, lane);
     }
-    chunk_end(S, P, lane);
+    // stale slots go out every ~8 steps: each write-out exposes its atomics' latency once,
+    // and at every chunk of 3 steps that cost showed (-2 % adjoint time at 9 steps; at 12 or
+    // more the cache fills and misses write slots out one at a time)
+    if (seg % rec_writeout_chunks<KS>() == 0) chunk_end(S, P, lane);
   }
   float V0[3] = {0.0f, 0.0f, 0.0f};
   if (active) {
