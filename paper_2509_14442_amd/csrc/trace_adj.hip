@@ -6,12 +6,13 @@
 // the same cells together. A segment is replayed forward from its checkpoint in chunks
 // of KS steps, keeping in LDS either each step's start state (then the reverse relocates
 // the step's samples) or, for strides 3 and 4 (a segment is then one chunk), the cells
-// and fractions of its three samples; the chunk is then reversed step by step. Each sample's contributions are
-// merged per lane, as monomial coefficients, while the ray stays in one cell; lanes that
-// left the same cell are summed across the wavefront into a per-wavefront LDS cache of
-// cell totals, which goes to the gradient with one FP64 atomic per corner. Loops stay
-// rolled so the kernel fits the instruction cache; the per-ray geometry comes from the
-// header the forward pass stored with the checkpoints.
+// and fractions of its three samples; the chunk is then reversed step by step. Each
+// sample's contributions are merged per lane, as monomial coefficients, while the ray
+// stays in one cell; lanes that left the same cell are summed across the wavefront into a
+// per-wavefront LDS cache of cell totals, which goes to the gradient with one FP64 atomic
+// per corner. A wavefront lowers its issue priority while replaying and raises it while
+// merging. Most loops stay rolled so the kernel fits the instruction cache; the per-ray
+// geometry comes from the header the forward pass stored with the checkpoints.
 #include <climits>
 
 #include "rbos_device.hpp"
@@ -163,7 +164,7 @@ struct Pending {
   int key;            // lane p < PEND_SLOTS: key of slot p; CELL_NONE when free (always for p >= PEND_SLOTS)
   int next;           // wave-uniform: slot replaced when all are taken
   unsigned occupied;  // wave-uniform slot masks
-  unsigned touched;   // slots hit or filled since the last chunk end
+  unsigned touched;   // slots hit or filled since the last batch write-out
 };
 
 __device__ __forceinline__ double* voxel_of_corner(const SceneDev& S, int key, int c) {
@@ -641,8 +642,8 @@ __device__ __forceinline__ void adjoint_tile(const SceneDev& S, int tile, int la
 }
 
 // Recording form (checkpoint strides KS = 3 and 4, one chunk per checkpoint segment): the
-// replay of a chunk keeps, for each of its steps, the record index and fractions of the step's three
-// samples as the forward located them (16 bytes per sample and lane in LDS, sample s of
+// replay of a chunk keeps, for each of its steps, the record index and fractions of the
+// step's three samples as the forward located them (16 bytes per sample and lane in LDS, sample s of
 // step i of lane l at [(i * 3 + s) * 64 + l]). The reverse of a step then reads them back,
 // issues its three cell gathers together and evaluates value, gradient and mixed second
 // derivatives at exactly the forward's cells and fractions, without relocating the
