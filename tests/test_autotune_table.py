@@ -41,7 +41,7 @@ def test_table_covers_the_benchmark_workloads():
     keys = list(_entries())
     wanted = [("f32", "t0", "spp1", "g21", "r20", "n1"), ("f16", "t0", "spp1", "g21", "r20", "n1"),
               ("bf16", "t0", "spp1", "g21", "r20", "n1"), ("f32", "t1", "spp1", "g21", "r20", "n1"),
-              ("f32", "t0", "spp4", "g21", "r22", "n1"), ("f32", "t0", "spp1", "g21", "r21", "n8"),
+              ("f32", "t0", "spp4", "g21", "r22", "n1"), ("f32", "t0", "spp1", "g21", "r24", "n64"),
               ("f32", "t0", "spp1", "g24", "r22", "n1")]
     for w in wanted:
         assert any(all(part in k.split("|") for part in w) for k in keys), w

@@ -205,8 +205,8 @@ def test_batch64_bench_workload_on_sampled_rays():
         scenes.append(api.Scene(sc, f, pat))
         temps.append(T)
     assert sum(s.n_rays for s in scenes) > 20_000_000
-    # bench.py tunes on every 8th scene and applies the entry to all of them
-    launch, adj_launch, k = bench_tuned(scenes[::8])
+    # the launches and stride bench.py tunes for this batch
+    launch, adj_launch, k = bench_tuned(scenes)
     for s in scenes:
         s.struct.ckpt_stride = k
     tr = api.Tracer(scenes, launch, adjoint_launch=adj_launch)
